@@ -1,0 +1,203 @@
+"""FP64 CPU oracle of the BGK discrete-velocity step (test infrastructure).
+
+This package is the independent reference the HIP library is checked
+against.  Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import it.  It shares no code with the
+library under ``paper_0903_4044_amd/``; both read problem statements from
+``paper_0903_4044_amd.inputs`` (parameters and seeded draws only).
+
+The arithmetic lives in ``bgk_oracle.c`` (plain C, FP64, OpenMP over spatial
+cells), compiled with gcc by :func:`build`.  ``twin.py`` is a second, NumPy
+implementation written separately, used only to cross-check the C code on
+tiny inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "bgk_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("nv", ctypes.c_int * 3),
+        ("vlo", ctypes.c_double * 3), ("vhi", ctypes.c_double * 3),
+        ("kn", ctypes.c_double), ("omega", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
+        ("mach", ctypes.c_double), ("lid_mach", ctypes.c_double),
+        ("t_wall", ctypes.c_double),
+        ("strang", ctypes.c_int), ("minmod", ctypes.c_int),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+                               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=False)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER(Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_dt.argtypes = [P]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_velocity_nodes.argtypes = [P, dp, dp, dp]
+        L.orc_maxwellian.argtypes = [P, ctypes.c_double, dp, ctypes.c_double, dp]
+        L.orc_moments.argtypes = [P, dp, dp]
+        L.orc_collision_frequency.argtypes = [P, ctypes.c_double, ctypes.c_double]
+        L.orc_collision_frequency.restype = ctypes.c_double
+        L.orc_relax.argtypes = [P, dp, dp, ctypes.c_double]
+        L.orc_rankine_hugoniot.argtypes = [ctypes.c_double, dp, dp]
+        L.orc_wall_density.argtypes = [P, dp, dp]
+        L.orc_stream.argtypes = [P, dp, dp, ctypes.c_double]
+        L.orc_step.argtypes = [P, dp, dp]
+        L.orc_run.argtypes = [P, dp, ctypes.c_int]
+        L.orc_initial_state.argtypes = [P, dp]
+        L.orc_totals.argtypes = [P, dp, dp]
+        L.orc_lid_shear.argtypes = [P, dp]
+        L.orc_lid_shear.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_problem(cfg: dict) -> Problem:
+    p = Problem()
+    p.kind = KINDS[cfg["kind"]]
+    p.nx = int(cfg["nx"])
+    p.ny = int(cfg.get("ny", 1))
+    p.x0, p.x1 = float(cfg["x0"]), float(cfg["x1"])
+    p.y0, p.y1 = float(cfg.get("y0", 0.0)), float(cfg.get("y1", 1.0))
+    for a in range(3):
+        p.nv[a] = int(cfg["nv"][a])
+        p.vlo[a] = float(cfg["vlo"][a])
+        p.vhi[a] = float(cfg["vhi"][a])
+    p.kn, p.omega = float(cfg["kn"]), float(cfg["omega"])
+    p.cfl, p.dt = float(cfg.get("cfl", 0.5)), float(cfg.get("dt", 0.0))
+    p.mach = float(cfg.get("mach", 0.0))
+    p.lid_mach = float(cfg.get("lid_mach", 0.0))
+    p.t_wall = float(cfg.get("t_wall", 1.0))
+    p.strang = 1 if cfg.get("splitting", "strang") == "strang" else 0
+    p.minmod = 1 if cfg.get("limiter", "minmod") == "minmod" else 0
+    return p
+
+
+class Oracle:
+    """FP64 reference stepper for one problem (a dict of ``inputs``)."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = dict(cfg)
+        self.p = make_problem(cfg)
+        self.L = lib()
+        self.two_d = cfg["kind"] in ("cavity", "periodic2d")
+        self.nx = self.p.nx
+        self.ny = self.p.ny if self.two_d else 1
+        self.ncell = self.nx * self.ny
+        self.nv = tuple(int(v) for v in cfg["nv"])
+        self.nvel = self.nv[0] * self.nv[1] * self.nv[2]
+        self.shape = (self.ncell, self.nvel)
+
+    @property
+    def dt(self) -> float:
+        return self.L.orc_dt(ctypes.byref(self.p))
+
+    def velocity_nodes(self):
+        vx, vy, vz = (np.empty(self.nvel) for _ in range(3))
+        self.L.orc_velocity_nodes(ctypes.byref(self.p), _ptr(vx), _ptr(vy), _ptr(vz))
+        return vx, vy, vz
+
+    def _f(self, f) -> np.ndarray:
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.shape)
+        return f
+
+    def initial_state(self) -> np.ndarray:
+        f = np.empty(self.shape)
+        self.L.orc_initial_state(ctypes.byref(self.p), _ptr(f))
+        return f
+
+    def maxwellian(self, n, V, T) -> np.ndarray:
+        out = np.empty(self.nvel)
+        Va = np.ascontiguousarray(V, dtype=np.float64)
+        self.L.orc_maxwellian(ctypes.byref(self.p), float(n), _ptr(Va), float(T), _ptr(out))
+        return out
+
+    def moments(self, f) -> np.ndarray:
+        f = self._f(f)
+        m = np.empty((self.ncell, 5))
+        self.L.orc_moments(ctypes.byref(self.p), _ptr(f), _ptr(m))
+        return m
+
+    def collision_frequency(self, n, T) -> float:
+        return self.L.orc_collision_frequency(ctypes.byref(self.p), float(n), float(T))
+
+    def relax(self, f, tau) -> np.ndarray:
+        f = self._f(f)
+        out = np.empty(self.shape)
+        self.L.orc_relax(ctypes.byref(self.p), _ptr(f), _ptr(out), float(tau))
+        return out
+
+    def stream(self, g, dt=None) -> np.ndarray:
+        g = self._f(g)
+        out = np.empty(self.shape)
+        self.L.orc_stream(ctypes.byref(self.p), _ptr(g), _ptr(out), float(self.dt if dt is None else dt))
+        return out
+
+    def step(self, f, n: int = 1) -> np.ndarray:
+        f = self._f(f).copy()
+        if n == 1:
+            out = np.empty(self.shape)
+            self.L.orc_step(ctypes.byref(self.p), _ptr(f), _ptr(out))
+            return out
+        self.L.orc_run(ctypes.byref(self.p), _ptr(f), int(n))
+        return f
+
+    def wall_density(self, g) -> np.ndarray:
+        g = self._f(g)
+        L = max(self.nx, self.ny)
+        out = np.zeros((4, L))
+        self.L.orc_wall_density(ctypes.byref(self.p), _ptr(g), _ptr(out))
+        return out
+
+    def totals(self, f) -> np.ndarray:
+        f = self._f(f)
+        out = np.empty(6)
+        self.L.orc_totals(ctypes.byref(self.p), _ptr(f), _ptr(out))
+        return out
+
+    def lid_shear(self, f) -> float:
+        f = self._f(f)
+        return self.L.orc_lid_shear(ctypes.byref(self.p), _ptr(f))
+
+    @staticmethod
+    def rankine_hugoniot(mach):
+        up, dn = np.empty(3), np.empty(3)
+        lib().orc_rankine_hugoniot(float(mach), _ptr(up), _ptr(dn))
+        return up, dn

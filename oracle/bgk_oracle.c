@@ -1,0 +1,529 @@
+/*
+ * bgk_oracle.c -- plain FP64 CPU reference of the BGK discrete-velocity step.
+ *
+ * TEST INFRASTRUCTURE.  This is the oracle the HIP library is checked
+ * against.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  The library never links, imports or calls it and
+ * the two share no code: no header, helper, table or constant generator.
+ *
+ * What it computes follows Frezzotti, Ghiroldi and Gibelli, "Solving Kinetic
+ * Equations on GPUs I: Model Kinetic Equations" (arXiv:0903.4044):
+ *   BGKW equation, local Maxwellian ............ Sec. 2, Eqs. (BGKW), (Maxw)
+ *   macroscopic moments ........................ Sec. 2, Eq. (macroscopic)
+ *   collision frequency ........................ Sec. 2, Eq. (frequency), Sec. 4.1
+ *   phase-space grid of point values ........... Sec. 2.1
+ *   splitting, exact homogeneous relaxation .... Sec. 2.1, Eq. (relaxation)
+ *   upwind free streaming (first-order base) ... Sec. 2.1, Eq. (upwind)
+ *   shock far-field states ..................... Sec. 4.1, Eqs. (bc_shock), (RH)
+ *   diffuse (fully accommodating) walls ........ Sec. 5.1, Eq. (bc_cavity)
+ *
+ * Units are the normalised ones of Sec. 4.1: velocity in sqrt(2 R T_r), so
+ * that 2RT becomes T and the Maxwellian reads
+ *     Phi_j = n (pi T)^(-3/2) exp(-|v_j - V|^2 / T),
+ * the temperature moment reads T = (2 / 3n) sum_j |v_j - V|^2 f_j dV, and the
+ * collision frequency (Eq. frequency with mu ~ T^omega) is nu = n T^(1-omega)/Kn.
+ *
+ * Readings of points the paper leaves open (all restated where used):
+ *   - streaming is the one-step minmod-limited upwind scheme in flux form;
+ *     with the limiter off it is Eq. (upwind) exactly;
+ *   - a time step is R_{dt/2} S_dt R_{dt/2} (Strang) or R_dt S_dt (Lie,
+ *     the paper's order), every R using the moments of its own input;
+ *   - two ghost layers per side: the far-field Maxwellians for the shock,
+ *     the diffuse-wall rule of Eq. (bc_cavity) for the cavity;
+ *   - dt = CFL / max_j sum_d |v_d(j)| / dx_d over velocity cell centres.
+ *
+ * Storage: f[cell][jz][jy][jx] (velocity fastest), cell = iy * nx + ix.
+ * Everything is double precision.  Loops are plain; OpenMP only splits the
+ * loop over spatial cells.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SHOCK 0
+#define ORC_CAVITY 1
+#define ORC_PERIODIC1 2
+#define ORC_PERIODIC2 3
+
+typedef struct {
+    int kind;
+    int nx, ny;
+    double x0, x1, y0, y1;
+    int nv[3];
+    double vlo[3], vhi[3];
+    double kn, omega;
+    double cfl, dt;
+    double mach;
+    double lid_mach;
+    double t_wall;
+    int strang; /* 1: R_{dt/2} S R_{dt/2}; 0: R_dt S (Lie) */
+    int minmod; /* 1: minmod slopes; 0: first-order upwind */
+} orc_problem;
+
+static const double GAMMA = 5.0 / 3.0;
+
+/* ------------------------------------------------------------------ grid */
+
+static int is2d(const orc_problem *p) { return p->kind == ORC_CAVITY || p->kind == ORC_PERIODIC2; }
+static long ncell(const orc_problem *p) { return (long)p->nx * (is2d(p) ? p->ny : 1); }
+static long nvel(const orc_problem *p) { return (long)p->nv[0] * p->nv[1] * p->nv[2]; }
+static double dvel(const orc_problem *p, int a) { return (p->vhi[a] - p->vlo[a]) / p->nv[a]; }
+static double dvol(const orc_problem *p) { return dvel(p, 0) * dvel(p, 1) * dvel(p, 2); }
+static double dxs(const orc_problem *p) { return (p->x1 - p->x0) / p->nx; }
+static double dys(const orc_problem *p) { return (p->y1 - p->y0) / p->ny; }
+
+/* Velocity of every node, Sec. 2.1: cell centres of a box cut into equal
+ * cells, v_a(k) = lo_a + (k + 1/2) dv_a.  Returned as three arrays of Nv. */
+typedef struct { double *vx, *vy, *vz; long nv; } velgrid;
+
+static velgrid make_velgrid(const orc_problem *p)
+{
+    velgrid g;
+    g.nv = nvel(p);
+    g.vx = malloc(sizeof(double) * g.nv);
+    g.vy = malloc(sizeof(double) * g.nv);
+    g.vz = malloc(sizeof(double) * g.nv);
+    for (int jz = 0; jz < p->nv[2]; ++jz)
+        for (int jy = 0; jy < p->nv[1]; ++jy)
+            for (int jx = 0; jx < p->nv[0]; ++jx) {
+                long j = ((long)jz * p->nv[1] + jy) * p->nv[0] + jx;
+                g.vx[j] = p->vlo[0] + (jx + 0.5) * dvel(p, 0);
+                g.vy[j] = p->vlo[1] + (jy + 0.5) * dvel(p, 1);
+                g.vz[j] = p->vlo[2] + (jz + 0.5) * dvel(p, 2);
+            }
+    return g;
+}
+
+static void free_velgrid(velgrid *g) { free(g->vx); free(g->vy); free(g->vz); }
+
+void orc_velocity_nodes(const orc_problem *p, double *vx, double *vy, double *vz)
+{
+    velgrid g = make_velgrid(p);
+    memcpy(vx, g.vx, sizeof(double) * g.nv);
+    memcpy(vy, g.vy, sizeof(double) * g.nv);
+    memcpy(vz, g.vz, sizeof(double) * g.nv);
+    free_velgrid(&g);
+}
+
+/* Time step.  The paper fixes dt as a fraction of the collision time and
+ * handles Courant numbers above one by shifting (Sec. 2.1); the workloads
+ * here fix a Courant number instead: dt = CFL / max_j sum_d |v_d(j)|/dx_d. */
+double orc_dt(const orc_problem *p)
+{
+    if (p->dt > 0.0) return p->dt;
+    double m = 0.0;
+    for (int jx = 0; jx < p->nv[0]; ++jx) {
+        double ax = fabs(p->vlo[0] + (jx + 0.5) * dvel(p, 0)) / dxs(p);
+        if (!is2d(p)) { if (ax > m) m = ax; continue; }
+        for (int jy = 0; jy < p->nv[1]; ++jy) {
+            double ay = fabs(p->vlo[1] + (jy + 0.5) * dvel(p, 1)) / dys(p);
+            if (ax + ay > m) m = ax + ay;
+        }
+    }
+    return p->cfl / m;
+}
+
+/* ------------------------------------------------------------- physics */
+
+/* Local Maxwellian, Eq. (Maxw), in normalised units. */
+void orc_maxwellian(const orc_problem *p, double n, const double V[3], double T, double *phi)
+{
+    velgrid g = make_velgrid(p);
+    double pre = n * pow(M_PI * T, -1.5);
+    for (long j = 0; j < g.nv; ++j) {
+        double cx = g.vx[j] - V[0], cy = g.vy[j] - V[1], cz = g.vz[j] - V[2];
+        phi[j] = pre * exp(-(cx * cx + cy * cy + cz * cz) / T);
+    }
+    free_velgrid(&g);
+}
+
+static void maxwellian_on(const velgrid *g, double n, const double V[3], double T, double *phi)
+{
+    double pre = n * pow(M_PI * T, -1.5);
+    for (long j = 0; j < g->nv; ++j) {
+        double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1], cz = g->vz[j] - V[2];
+        phi[j] = pre * exp(-(cx * cx + cy * cy + cz * cz) / T);
+    }
+}
+
+/* Macroscopic moments of one cell, Eq. (macroscopic), as velocity sums over
+ * the piecewise-constant f of Sec. 2.1:  n = sum f dV,  V = sum v f dV / n,
+ * T = (2/3) sum |v - V|^2 f dV / n  (second pass about the mean). */
+static void cell_moments(const velgrid *g, double dV, const double *f, double *n, double V[3], double *T)
+{
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (long j = 0; j < g->nv; ++j) {
+        s0 += f[j];
+        sx += g->vx[j] * f[j];
+        sy += g->vy[j] * f[j];
+        sz += g->vz[j] * f[j];
+    }
+    *n = s0 * dV;
+    V[0] = sx * dV / *n;
+    V[1] = sy * dV / *n;
+    V[2] = sz * dV / *n;
+    double s2 = 0.0;
+    for (long j = 0; j < g->nv; ++j) {
+        double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1], cz = g->vz[j] - V[2];
+        s2 += (cx * cx + cy * cy + cz * cz) * f[j];
+    }
+    *T = 2.0 / 3.0 * s2 * dV / *n;
+}
+
+/* mom[cell][5] = (n, Vx, Vy, Vz, T). */
+void orc_moments(const orc_problem *p, const double *f, double *mom)
+{
+    velgrid g = make_velgrid(p);
+    const long nc = ncell(p), nv = nvel(p);
+    const double dV = dvol(p);
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nc; ++c)
+        cell_moments(&g, dV, f + c * nv, &mom[5 * c], &mom[5 * c + 1], &mom[5 * c + 4]);
+    free_velgrid(&g);
+}
+
+/* Collision frequency, Eq. (frequency) with a power-law viscosity
+ * (Eq. viscosity, exponent omega), normalised as in Sec. 4.1. */
+double orc_collision_frequency(const orc_problem *p, double n, double T)
+{
+    return n * pow(T, 1.0 - p->omega) / p->kn;
+}
+
+/* Homogeneous relaxation over a time tau, solved exactly (Eq. relaxation):
+ * out = Phi + (f - Phi) exp(-nu tau), Phi and nu from the moments of f. */
+void orc_relax(const orc_problem *p, const double *f, double *out, double tau)
+{
+    velgrid g = make_velgrid(p);
+    const long nc = ncell(p), nv = nvel(p);
+    const double dV = dvol(p);
+#pragma omp parallel
+    {
+        double *phi = malloc(sizeof(double) * nv);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            const double *fc = f + c * nv;
+            double n, V[3], T;
+            cell_moments(&g, dV, fc, &n, V, &T);
+            maxwellian_on(&g, n, V, T, phi);
+            double decay = exp(-orc_collision_frequency(p, n, T) * tau);
+            for (long j = 0; j < nv; ++j)
+                out[c * nv + j] = phi[j] + (fc[j] - phi[j]) * decay;
+        }
+        free(phi);
+    }
+    free_velgrid(&g);
+}
+
+/* -------------------------------------------------------- boundary states */
+
+/* Rankine-Hugoniot states, Eq. (RH), with upstream n = T = 1 and the Mach
+ * number defined below Eq. (RH); V^- = M sqrt(gamma/2) in sqrt(2RT^-) units. */
+void orc_rankine_hugoniot(double mach, double up[3], double down[3])
+{
+    double m2 = mach * mach;
+    double r = 4.0 * m2 / (m2 + 3.0);
+    up[0] = 1.0;
+    up[1] = mach * sqrt(GAMMA / 2.0);
+    up[2] = 1.0;
+    down[0] = up[0] * r;
+    down[1] = up[1] / r;
+    down[2] = up[2] * (5.0 * m2 - 1.0) * (m2 + 3.0) / (16.0 * m2);
+}
+
+/* Lid speed: the lid Mach number taken at the reference temperature T_r,
+ * U_W = Ma sqrt(gamma R T_r) = Ma sqrt(gamma / 2) in sqrt(2RT_r) units.  It
+ * does not change with the wall temperature. */
+static double lid_speed(const orc_problem *p)
+{
+    return p->lid_mach * sqrt(GAMMA / 2.0);
+}
+
+/* Unit-density wall Maxwellian (pi T_w)^(-3/2) exp(-|v - V_W|^2 / T_w). */
+static void wall_maxwellian(const orc_problem *p, const velgrid *g, double uw, double *phi)
+{
+    double V[3] = {uw, 0.0, 0.0};
+    maxwellian_on(g, 1.0, V, p->t_wall, phi);
+}
+
+/* Walls are numbered 0 left (x = x0, inward normal +x), 1 right (-x),
+ * 2 bottom (y = y0, +y), 3 top / lid (-y, moving with speed U_W along x). */
+static void wall_normal(int w, int *axis, double *sign)
+{
+    *axis = (w < 2) ? 0 : 1;
+    *sign = (w == 0 || w == 2) ? 1.0 : -1.0;
+}
+
+/* Wall density of Eq. (bc_cavity): the emitted Maxwellian carries the mass
+ * flux that the gas brings to the wall, so the net flux through the wall is
+ * zero.  Both fluxes are the discrete sums over the velocity grid:
+ *   n_W = sum_{v.n<0} |v.n| g0 / sum_{v.n>0} (v.n) Phi_W,
+ * g0 being the wall-adjacent cell. */
+static double wall_density(const velgrid *g, int axis, double sign, const double *g0, const double *phiw)
+{
+    const double *va = axis == 0 ? g->vx : g->vy;
+    double num = 0.0, den = 0.0;
+    for (long j = 0; j < g->nv; ++j) {
+        double vn = sign * va[j];
+        if (vn < 0.0) num += -vn * g0[j];
+        else if (vn > 0.0) den += vn * phiw[j];
+    }
+    return num / den;
+}
+
+/* n_W for every wall face of a cavity state g: nw[w * L + k] with
+ * L = max(nx, ny), k the cell index along the wall. */
+void orc_wall_density(const orc_problem *p, const double *gs, double *nw)
+{
+    velgrid g = make_velgrid(p);
+    const int nx = p->nx, ny = p->ny;
+    const long nv = nvel(p);
+    const int L = nx > ny ? nx : ny;
+    double *rest = malloc(sizeof(double) * nv), *lid = malloc(sizeof(double) * nv);
+    wall_maxwellian(p, &g, 0.0, rest);
+    wall_maxwellian(p, &g, lid_speed(p), lid);
+    for (int w = 0; w < 4; ++w) {
+        int axis; double sign;
+        wall_normal(w, &axis, &sign);
+        int len = axis == 0 ? ny : nx;
+        for (int k = 0; k < len; ++k) {
+            long c;
+            if (w == 0) c = (long)k * nx;
+            else if (w == 1) c = (long)k * nx + nx - 1;
+            else if (w == 2) c = k;
+            else c = (long)(ny - 1) * nx + k;
+            nw[w * L + k] = wall_density(&g, axis, sign, gs + c * nv, w == 3 ? lid : rest);
+        }
+    }
+    free(rest); free(lid);
+    free_velgrid(&g);
+}
+
+/* --------------------------------------------------------------- streaming */
+
+static double minmod(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+/* Upwind value at the face between u0 and u1 for Courant number C, given the
+ * four values (um1, u0, u1, u2) along the direction.  For C > 0 the face takes
+ * u0 plus half its limited slope scaled by (1 - C); for C < 0 it mirrors onto
+ * u1.  Without the limiter this is the donor cell value of Eq. (upwind). */
+static double face_value(double um1, double u0, double u1, double u2, double C, int limit)
+{
+    if (C > 0.0) return u0 + (limit ? 0.5 * (1.0 - C) * minmod(u1 - u0, u0 - um1) : 0.0);
+    if (C < 0.0) return u1 - (limit ? 0.5 * (1.0 + C) * minmod(u2 - u1, u1 - u0) : 0.0);
+    return 0.0;
+}
+
+/* Free streaming over dt, Eq. (freestreaming), in flux form:
+ *   out_i = g_i - sum_d C_d (face_{i+1/2} - face_{i-1/2}),  C_d = v_d dt / dx_d,
+ * every face built from the same input g.  g is first copied into an array
+ * with two ghost layers on each side of each streaming direction. */
+void orc_stream(const orc_problem *p, const double *gs, double *out, double dt)
+{
+    velgrid g = make_velgrid(p);
+    const int two = is2d(p);
+    const int nx = p->nx, ny = two ? p->ny : 1;
+    const long nv = nvel(p);
+    const int px = nx + 4, py = two ? ny + 4 : 1, oy = two ? 2 : 0;
+    double *G = malloc(sizeof(double) * (long)px * py * nv);
+#define PAD(ix, iy) (G + ((long)((iy) + oy) * px + (ix) + 2) * nv)
+#define SRC(ix, iy) (gs + ((long)(iy) * nx + (ix)) * nv)
+
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix)
+            memcpy(PAD(ix, iy), SRC(ix, iy), sizeof(double) * nv);
+
+    if (p->kind == ORC_SHOCK) {
+        /* Far-field states of Eq. (bc_shock) fill both ghost layers. */
+        double up[3], dn[3];
+        orc_rankine_hugoniot(p->mach, up, dn);
+        double Vu[3] = {up[1], 0, 0}, Vd[3] = {dn[1], 0, 0};
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(-2, 0));
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(-1, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx + 1, 0));
+    } else if (p->kind == ORC_PERIODIC1 || p->kind == ORC_PERIODIC2) {
+        for (int iy = 0; iy < ny; ++iy) {
+            memcpy(PAD(-2, iy), SRC(nx - 2, iy), sizeof(double) * nv);
+            memcpy(PAD(-1, iy), SRC(nx - 1, iy), sizeof(double) * nv);
+            memcpy(PAD(nx, iy), SRC(0, iy), sizeof(double) * nv);
+            memcpy(PAD(nx + 1, iy), SRC(1, iy), sizeof(double) * nv);
+        }
+        if (two)
+            for (int ix = 0; ix < nx; ++ix) {
+                memcpy(PAD(ix, -2), SRC(ix, ny - 2), sizeof(double) * nv);
+                memcpy(PAD(ix, -1), SRC(ix, ny - 1), sizeof(double) * nv);
+                memcpy(PAD(ix, ny), SRC(ix, 0), sizeof(double) * nv);
+                memcpy(PAD(ix, ny + 1), SRC(ix, 1), sizeof(double) * nv);
+            }
+    } else {
+        /* Diffuse walls, Eq. (bc_cavity).  For velocities leaving the wall
+         * (v.n > 0) both ghosts hold n_W Phi_W; for velocities arriving at it
+         * both ghosts repeat the wall-adjacent cell, so the wall face takes
+         * that cell's value and the net mass flux through it is exactly zero. */
+        double *rest = malloc(sizeof(double) * nv), *lid = malloc(sizeof(double) * nv);
+        wall_maxwellian(p, &g, 0.0, rest);
+        wall_maxwellian(p, &g, lid_speed(p), lid);
+        for (int w = 0; w < 4; ++w) {
+            int axis; double sign;
+            wall_normal(w, &axis, &sign);
+            const double *va = axis == 0 ? g.vx : g.vy;
+            const double *phiw = w == 3 ? lid : rest;
+            int len = axis == 0 ? ny : nx;
+            for (int k = 0; k < len; ++k) {
+                int ax, ay, gx1, gy1, gx2, gy2;
+                if (w == 0) { ax = 0; ay = k; gx1 = -1; gx2 = -2; gy1 = gy2 = k; }
+                else if (w == 1) { ax = nx - 1; ay = k; gx1 = nx; gx2 = nx + 1; gy1 = gy2 = k; }
+                else if (w == 2) { ax = k; ay = 0; gy1 = -1; gy2 = -2; gx1 = gx2 = k; }
+                else { ax = k; ay = ny - 1; gy1 = ny; gy2 = ny + 1; gx1 = gx2 = k; }
+                const double *g0 = SRC(ax, ay);
+                double nW = wall_density(&g, axis, sign, g0, phiw);
+                double *d1 = PAD(gx1, gy1), *d2 = PAD(gx2, gy2);
+                for (long j = 0; j < nv; ++j) {
+                    double v = sign * va[j] > 0.0 ? nW * phiw[j] : g0[j];
+                    d1[j] = v;
+                    d2[j] = v;
+                }
+            }
+        }
+        free(rest); free(lid);
+    }
+
+    const double dx = dxs(p), dy = two ? dys(p) : 1.0;
+    const int limit = p->minmod;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) {
+            const double *xm2 = PAD(ix - 2, iy), *xm1 = PAD(ix - 1, iy), *c0 = PAD(ix, iy),
+                         *xp1 = PAD(ix + 1, iy), *xp2 = PAD(ix + 2, iy);
+            const double *ym2 = two ? PAD(ix, iy - 2) : 0, *ym1 = two ? PAD(ix, iy - 1) : 0,
+                         *yp1 = two ? PAD(ix, iy + 1) : 0, *yp2 = two ? PAD(ix, iy + 2) : 0;
+            double *o = out + ((long)iy * nx + ix) * nv;
+            for (long j = 0; j < nv; ++j) {
+                double Cx = g.vx[j] * dt / dx;
+                double r = c0[j] - Cx * (face_value(xm1[j], c0[j], xp1[j], xp2[j], Cx, limit) -
+                                         face_value(xm2[j], xm1[j], c0[j], xp1[j], Cx, limit));
+                if (two) {
+                    double Cy = g.vy[j] * dt / dy;
+                    r -= Cy * (face_value(ym1[j], c0[j], yp1[j], yp2[j], Cy, limit) -
+                               face_value(ym2[j], ym1[j], c0[j], yp1[j], Cy, limit));
+                }
+                o[j] = r;
+            }
+        }
+#undef PAD
+#undef SRC
+    free(G);
+    free_velgrid(&g);
+}
+
+/* ------------------------------------------------------------ time step */
+
+/* One time step (Sec. 2.1).  Strang: out = R_{dt/2}(S_dt(R_{dt/2}(f))).
+ * Lie (the paper's order): out = R_dt(S_dt(f)). */
+void orc_step(const orc_problem *p, const double *f, double *out)
+{
+    const double dt = orc_dt(p);
+    const long n = ncell(p) * nvel(p);
+    double *a = malloc(sizeof(double) * n);
+    if (p->strang) {
+        double *b = malloc(sizeof(double) * n);
+        orc_relax(p, f, a, 0.5 * dt);
+        orc_stream(p, a, b, dt);
+        orc_relax(p, b, out, 0.5 * dt);
+        free(b);
+    } else {
+        orc_stream(p, f, a, dt);
+        orc_relax(p, a, out, dt);
+    }
+    free(a);
+}
+
+/* nsteps steps in place on f. */
+void orc_run(const orc_problem *p, double *f, int nsteps)
+{
+    const long n = ncell(p) * nvel(p);
+    double *t = malloc(sizeof(double) * n);
+    for (int s = 0; s < nsteps; ++s) {
+        orc_step(p, f, t);
+        memcpy(f, t, sizeof(double) * n);
+    }
+    free(t);
+}
+
+/* Initial states: the Rankine-Hugoniot step of Sec. 4.1 (upstream state for
+ * x < 0, downstream for x >= 0); the gas at rest, n = T = 1, otherwise. */
+void orc_initial_state(const orc_problem *p, double *f)
+{
+    velgrid g = make_velgrid(p);
+    const long nc = ncell(p), nv = nvel(p);
+    if (p->kind == ORC_SHOCK) {
+        double up[3], dn[3];
+        orc_rankine_hugoniot(p->mach, up, dn);
+        double Vu[3] = {up[1], 0, 0}, Vd[3] = {dn[1], 0, 0};
+        for (long c = 0; c < nc; ++c) {
+            double x = p->x0 + (c + 0.5) * dxs(p);
+            if (x < 0.0) maxwellian_on(&g, up[0], Vu, up[2], f + c * nv);
+            else maxwellian_on(&g, dn[0], Vd, dn[2], f + c * nv);
+        }
+    } else {
+        double V[3] = {0, 0, 0};
+        for (long c = 0; c < nc; ++c) maxwellian_on(&g, 1.0, V, 1.0, f + c * nv);
+    }
+    free_velgrid(&g);
+}
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Domain totals of mass, momentum (3) and energy sum |v|^2 f, and the
+ * entropy functional sum f ln f, all times dV and the cell size. */
+void orc_totals(const orc_problem *p, const double *f, double *tot /* [6] */)
+{
+    velgrid g = make_velgrid(p);
+    const long nc = ncell(p), nv = nvel(p);
+    const double w = dvol(p) * dxs(p) * (is2d(p) ? dys(p) : 1.0);
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (long c = 0; c < nc; ++c)
+        for (long j = 0; j < nv; ++j) {
+            double v = f[c * nv + j];
+            s[0] += v;
+            s[1] += g.vx[j] * v;
+            s[2] += g.vy[j] * v;
+            s[3] += g.vz[j] * v;
+            s[4] += (g.vx[j] * g.vx[j] + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j]) * v;
+            if (v > 0.0) s[5] += v * log(v);
+        }
+    for (int k = 0; k < 6; ++k) tot[k] = s[k] * w;
+    free_velgrid(&g);
+}
+
+/* Lid shear: the flux of x-momentum through the lid face, built with the
+ * same ghost rule as the streaming step (gas leaving the top row for
+ * v_y > 0, wall Maxwellian n_W Phi_W entering for v_y < 0), summed along
+ * the lid: L = sum_i dx [sum_{vy>0} vx vy f dV + n_W,i sum_{vy<0} vx vy Phi_W dV]. */
+double orc_lid_shear(const orc_problem *p, const double *f)
+{
+    velgrid g = make_velgrid(p);
+    const int nx = p->nx, ny = p->ny;
+    const long nv = nvel(p);
+    const double dV = dvol(p), dx = dxs(p);
+    double *lid = malloc(sizeof(double) * nv);
+    wall_maxwellian(p, &g, lid_speed(p), lid);
+    double L = 0.0;
+    for (int ix = 0; ix < nx; ++ix) {
+        const double *ft = f + ((long)(ny - 1) * nx + ix) * nv;
+        double nW = wall_density(&g, 1, -1.0, ft, lid);
+        double s_in = 0.0, s_out = 0.0;
+        for (long j = 0; j < nv; ++j) {
+            if (g.vy[j] > 0.0) s_in += g.vx[j] * g.vy[j] * ft[j];
+            else if (g.vy[j] < 0.0) s_out += g.vx[j] * g.vy[j] * lid[j];
+        }
+        L += dx * (s_in + nW * s_out) * dV;
+    }
+    free(lid);
+    free_velgrid(&g);
+    return L;
+}

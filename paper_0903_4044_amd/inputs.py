@@ -1,0 +1,123 @@
+"""Problem statements and seeded synthetic inputs.
+
+This module holds parameter sets and random draws only: it contains none of
+the solver's arithmetic (no Maxwellian, no moment, no streaming formula), so
+that the HIP library and the FP64 oracle can both be driven from it without
+sharing any code of the method.
+
+A problem is a plain ``dict`` with the keys below (units are the normalised
+ones of Sec. 4.1 of the paper: velocity in sqrt(2 R T_r), temperature in T_r,
+density in n_r, length in the domain unit, time in length / sqrt(2 R T_r)):
+
+    kind       'shock' (1D, far-field Maxwellian ghosts, Sec. 4.1),
+               'cavity' (2D, diffuse walls, Sec. 5.1),
+               'periodic1d' / 'periodic2d' (test problems)
+    nx, ny     spatial cells (ny = 1 for 1D kinds)
+    x0, x1, y0, y1   spatial box
+    nv         (Nvx, Nvy, Nvz) velocity cells (Sec. 2.1)
+    vlo, vhi   velocity box per component
+    kn, omega  collision frequency nu = n T^(1-omega) / Kn
+    cfl, dt    dt > 0 fixes the time step, else dt comes from cfl
+    mach       shock: upstream Mach number (Eq. RH)
+    lid_mach   cavity: lid speed as a Mach number at the wall temperature
+    t_wall     cavity: wall temperature
+    splitting  'strang' (R_{dt/2} S_dt R_{dt/2}) or 'lie' (R_dt S_dt, Sec. 2.1)
+    limiter    'minmod' (second order) or 'none' (first-order upwind, Eq. upwind)
+    steps      number of time steps of the workload
+    precision  'fp64' or 'fp32' (storage/streaming precision of f)
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+BATCH_SEED = 9034044
+NOISE_SEED = 9034045
+
+
+def _base(**kw):
+    d = dict(kind="shock", nx=1, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+             nv=(8, 8, 8), vlo=(-4.0, -4.0, -4.0), vhi=(4.0, 4.0, 4.0),
+             kn=1.0, omega=0.5, cfl=0.5, dt=0.0, mach=0.0, lid_mach=0.0,
+             t_wall=1.0, splitting="strang", limiter="minmod", steps=1,
+             precision="fp64")
+    d.update(kw)
+    return d
+
+
+# The five workloads.  Sizes follow the paper's two problems (Sec. 4.1 and
+# Sec. 5.1) at the resolutions this library is measured on.
+CONFIGS = {
+    # 1D normal shock, Mach 1.5, FP64 throughout, 200 Strang steps.
+    "shock_m1.5_fp64": _base(kind="shock", nx=256, x0=-20.0, x1=20.0,
+                             nv=(32, 32, 32), vlo=(-6.0,) * 3, vhi=(6.0,) * 3,
+                             kn=1.0, mach=1.5, steps=200, precision="fp64"),
+    # 1D normal shock, Mach 3, FP32 f with FP64 moments, 2000 steps.
+    "shock_m3_fp32": _base(kind="shock", nx=1024, x0=-20.0, x1=20.0,
+                           nv=(48, 48, 48), vlo=(-8.0,) * 3, vhi=(8.0,) * 3,
+                           kn=1.0, mach=3.0, steps=2000, precision="fp32"),
+    # 2D lid-driven cavity 128^2, lid Mach 0.1, Kn 0.1, 5000 steps.
+    "cavity_128_fp32": _base(kind="cavity", nx=128, ny=128, nv=(24, 24, 24),
+                             vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
+                             lid_mach=0.1, t_wall=1.0, steps=5000,
+                             precision="fp32"),
+    # Adjoint workload: 64^2 cavity, 200 steps.
+    "cavity_64_adjoint": _base(kind="cavity", nx=64, ny=64, nv=(24, 24, 24),
+                               vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
+                               lid_mach=0.1, t_wall=1.0, steps=200,
+                               precision="fp32"),
+}
+
+SIDES = (32, 48, 64, 96, 128)
+
+
+def config(name: str, **override) -> dict:
+    """A deep copy of a named workload, with keyword overrides."""
+    d = copy.deepcopy(CONFIGS[name])
+    d.update(override)
+    return d
+
+
+def batch_cavities(n: int = 64, seed: int = BATCH_SEED, steps: int = 1000,
+                   precision: str = "fp32") -> list[dict]:
+    """Seeded draw of ``n`` independent lid-driven cavities.
+
+    Per instance, in order: side from {32, 48, 64, 96, 128} (uniform),
+    Kn = 10**U(-2, 0) (log-uniform on [0.01, 1]), lid Mach U(0.05, 0.3).
+    All share a 24^3 velocity grid on [-5, 5]^3 and T_wall = 1.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        side = int(rng.choice(SIDES))
+        kn = float(10.0 ** rng.uniform(-2.0, 0.0))
+        ma = float(rng.uniform(0.05, 0.3))
+        out.append(_base(kind="cavity", nx=side, ny=side, nv=(24, 24, 24),
+                         vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=kn,
+                         lid_mach=ma, t_wall=1.0, steps=steps,
+                         precision=precision))
+    return out
+
+
+def noise(shape, seed: int = NOISE_SEED) -> np.ndarray:
+    """Standard normal draws (FP64, C order) for the seeded perturbation."""
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def uniform(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """Uniform draws (FP64, C order) for test inputs."""
+    return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+def ncells(p: dict) -> int:
+    return int(p["nx"]) * (int(p["ny"]) if p["kind"] in ("cavity", "periodic2d") else 1)
+
+
+def nvel(p: dict) -> int:
+    a, b, c = p["nv"]
+    return int(a) * int(b) * int(c)
+
+
+def is_2d(p: dict) -> bool:
+    return p["kind"] in ("cavity", "periodic2d")

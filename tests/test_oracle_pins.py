@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against facts fixed by the paper or by mathematics.
+
+None of these re-types the oracle's own formulas: each checks a closed form,
+an invariant, a textbook special case or an independent implementation, chosen
+so that a plausible slip in the oracle (a dropped factor in the Maxwellian or
+in T, a wrong sign or index in the streaming, the wrong wall in n_W, a
+transposed axis) makes at least one of them fail.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_0903_4044_amd import inputs
+
+GAMMA = 5.0 / 3.0
+
+
+def prob(**kw):
+    d = dict(kind="periodic1d", nx=4, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+             nv=(32, 32, 32), vlo=(-8.0,) * 3, vhi=(8.0,) * 3, kn=1.0, omega=0.5,
+             cfl=0.5, dt=0.0, mach=0.0, lid_mach=0.0, t_wall=1.0,
+             splitting="strang", limiter="minmod")
+    d.update(kw)
+    return d
+
+
+def gauss(O, n, V, T):
+    """Maxwellian point values written from the Gaussian integral, as the test's
+    own closed form: n * prod_a exp(-(v_a - V_a)^2 / T) / sqrt(pi T)."""
+    vx, vy, vz = O.velocity_nodes()
+    out = np.full(vx.shape, float(n))
+    for v, c in zip((vx, vy, vz), V):
+        out *= np.exp(-((v - c) ** 2) / T) / math.sqrt(math.pi * T)
+    return out
+
+
+# --------------------------------------------------------------- Maxwellian
+
+
+def test_maxwellian_discrete_moments(oracle_mod):
+    """Sec. 2, Eqs. (Maxw) and (macroscopic): on a resolving grid the moments of
+    the sampled Maxwellian are its parameters (midpoint rule on a Gaussian is
+    spectrally accurate).  Pins the (pi T)^(-3/2) prefactor, the exponent and
+    the 2/(3n) temperature factor."""
+    O = oracle_mod.Oracle(prob(nv=(40, 40, 40), vlo=(-9,) * 3, vhi=(9,) * 3))
+    for (n, V, T) in [(1.0, (0, 0, 0), 1.0), (2.5, (0.7, -0.3, 0.2), 1.7), (0.4, (1.2, 0.1, -0.5), 0.6)]:
+        phi = O.maxwellian(n, np.array(V, float), T)
+        np.testing.assert_allclose(phi, gauss(O, n, V, T), rtol=1e-13, atol=0)
+        m = O.moments(np.tile(phi, (O.ncell, 1)))
+        np.testing.assert_allclose(m[0], [n, *V, T], rtol=1e-11, atol=1e-12)
+
+
+def test_rankine_hugoniot_fluxes(oracle_mod):
+    """Sec. 4.1, Eq. (RH): the two far-field states carry equal fluxes of mass
+    nV, momentum nV^2 + nT/2 and energy nV(V^2 + 5T/2) (moments of a drifting
+    Maxwellian in sqrt(2RT) units), and the upstream Mach number is M."""
+    for M in (1.5, 3.0):
+        up, dn = oracle_mod.Oracle.rankine_hugoniot(M)
+        assert up[1] / math.sqrt(GAMMA * up[2] / 2) == pytest.approx(M, rel=1e-15)
+
+        def fl(s):
+            n, V, T = s
+            return np.array([n * V, n * V * V + n * T / 2, n * V * (V * V + 2.5 * T)])
+        np.testing.assert_allclose(fl(dn), fl(up), rtol=1e-14)
+    up, dn = oracle_mod.Oracle.rankine_hugoniot(1.5)
+    # M = 1.5: n+ = 9/5.25 = 12/7, V+ = V-/n+, T+ = 10.25 * 5.25 / 36
+    np.testing.assert_allclose(dn, [12 / 7, 1.5 * math.sqrt(5 / 6) * 7 / 12, 10.25 * 5.25 / 36], rtol=1e-14)
+
+
+def test_discrete_shock_fluxes_match_closed_form(oracle_mod):
+    """The velocity-grid flux sums of a far-field Maxwellian reproduce the
+    closed-form fluxes above (pins the grid nodes and dV)."""
+    O = oracle_mod.Oracle(prob(nv=(64, 64, 64), vlo=(-12,) * 3, vhi=(12,) * 3))
+    vx, vy, vz = O.velocity_nodes()
+    dV = (24 / 64) ** 3
+    up, dn = oracle_mod.Oracle.rankine_hugoniot(3.0)
+    for n, V, T in (up, dn):
+        phi = O.maxwellian(n, np.array([V, 0, 0]), T)
+        got = [np.sum(vx * phi) * dV, np.sum(vx * vx * phi) * dV,
+               np.sum(vx * (vx * vx + vy * vy + vz * vz) * phi) * dV]
+        want = [n * V, n * V * V + n * T / 2, n * V * (V * V + 2.5 * T)]
+        np.testing.assert_allclose(got, want, rtol=1e-11)
+
+
+# --------------------------------------------------------------- relaxation
+
+
+def test_relaxation_fixed_point(oracle_mod):
+    """Uniform Maxwellian is a fixed point of the relaxation (Sec. 2.1): it
+    changes only by the discrete moment defect, far below 1e-12 here."""
+    O = oracle_mod.Oracle(prob(nv=(40, 40, 40), vlo=(-9,) * 3, vhi=(9,) * 3))
+    phi = O.maxwellian(1.3, np.array([0.4, -0.2, 0.1]), 1.4)
+    f = np.tile(phi, (O.ncell, 1))
+    out = O.relax(f, 0.37)
+    assert np.max(np.abs(out - f)) <= 1e-12 * np.max(f)
+
+
+def test_homogeneous_relaxation_closed_form(oracle_mod):
+    """Sec. 2.1, Eq. (relaxation): with f uniform in space, streaming is the
+    identity and f(t) = Phi_inf + (f0 - Phi_inf) exp(-nu t), Phi_inf carrying
+    the (conserved) moments of f0.  f0 is two Maxwellians of density 1/2,
+    velocities +-u e_x, temperature T0, whose mixture has n = 1, V = 0 and
+    T = T0 + (2/3) u^2 in closed form; nu = n T^(1-omega) / Kn."""
+    u, T0, kn, omega = 0.5, 0.8, 0.7, 0.74  # omega of Eq. (viscosity)
+    for splitting in ("strang", "lie"):
+        cfg = prob(nv=(40, 40, 40), kn=kn, omega=omega, splitting=splitting, dt=0.01)
+        O = oracle_mod.Oracle(cfg)
+        f0 = 0.5 * gauss(O, 1.0, (u, 0, 0), T0) + 0.5 * gauss(O, 1.0, (-u, 0, 0), T0)
+        Tinf = T0 + 2.0 / 3.0 * u * u
+        nu = 1.0 * Tinf ** (1 - omega) / kn
+        nsteps = 25
+        f = O.step(np.tile(f0, (O.ncell, 1)), nsteps)
+        t = nsteps * 0.01
+        Pinf = gauss(O, 1.0, (0, 0, 0), Tinf)
+        want = Pinf + (f0 - Pinf) * math.exp(-nu * t)
+        assert np.max(np.abs(f - want)) <= 1e-12 * np.max(f0)
+
+
+def test_collisions_conserve(oracle_mod):
+    """Relaxation conserves mass, momentum and energy (Sec. 2) up to the
+    discrete Maxwellian's moment defect, which is below 1e-13 on this grid."""
+    O = oracle_mod.Oracle(prob(nx=3, nv=(36, 36, 36), vlo=(-9,) * 3, vhi=(9,) * 3))
+    base = gauss(O, 1.0, (0.3, -0.1, 0.2), 1.2)
+    xi = inputs.uniform((O.ncell, O.nvel), seed=11, lo=0.5, hi=1.5)
+    f = base[None, :] * xi
+    before = O.totals(f)
+    after = O.totals(O.relax(f, 0.9))
+    np.testing.assert_allclose(after[:5], before[:5], rtol=1e-13, atol=1e-14)
+
+
+def test_entropy_decreases_under_relaxation(oracle_mod):
+    """H = sum f ln f is non-increasing under relaxation (convexity)."""
+    O = oracle_mod.Oracle(prob(nx=2, nv=(24, 24, 24)))
+    base = gauss(O, 1.0, (0.0, 0.0, 0.0), 1.5)
+    f = base[None, :] * inputs.uniform((O.ncell, O.nvel), seed=3, lo=0.2, hi=1.8)
+    h0 = O.totals(f)[5]
+    g = O.relax(f, 0.1)
+    h1 = O.totals(g)[5]
+    h2 = O.totals(O.relax(g, 0.5))[5]
+    assert h1 < h0 and h2 < h1
+
+
+# --------------------------------------------------------------- streaming
+
+
+def test_first_order_upwind_is_eq_upwind(oracle_mod):
+    """Limiter off: streaming is the donor-cell formula of Sec. 2.1, Eq. (upwind):
+    f_i <- (1 - C) f_i + C f_{i-1} for C > 0, (1 + C) f_i - C f_{i+1} for C < 0."""
+    cfg = prob(kind="periodic1d", nx=9, nv=(6, 2, 2), vlo=(-3,) * 3, vhi=(3,) * 3, limiter="none")
+    O = oracle_mod.Oracle(cfg)
+    g = inputs.uniform(O.shape, seed=5, lo=0.1, hi=1.0)
+    dt = O.dt
+    out = O.stream(g, dt)
+    vx, _, _ = O.velocity_nodes()
+    C = vx * dt / (1.0 / 9)
+    left, right = np.roll(g, 1, axis=0), np.roll(g, -1, axis=0)
+    want = np.where(C > 0, (1 - C) * g + C * left, (1 + C) * g - C * right)
+    np.testing.assert_allclose(out, want, rtol=1e-14, atol=1e-16)
+
+
+def test_unit_courant_number_is_exact_shift(oracle_mod):
+    """Sec. 2.1, Eq. (exact): at |C| = 1 the scheme moves f by one cell,
+    whatever the limiter does (the slope term carries a factor 1 - |C|)."""
+    cfg = prob(kind="periodic1d", nx=10, nv=(2, 2, 2), vlo=(-1,) * 3, vhi=(1,) * 3, dt=0.2)
+    O = oracle_mod.Oracle(cfg)  # v_x = +-0.5, dx = 0.1 -> C = +-1
+    g = inputs.uniform(O.shape, seed=7, lo=0.0, hi=1.0)
+    out = O.stream(g, 0.2)
+    vx, _, _ = O.velocity_nodes()
+    want = np.where(vx > 0, np.roll(g, 1, axis=0), np.roll(g, -1, axis=0))
+    np.testing.assert_allclose(out, want, rtol=0, atol=1e-15)
+
+
+def test_linear_profile_translates_exactly(oracle_mod):
+    """Second-order reading: minmod keeps the exact slope of linear data, so a
+    linear profile moves by v dt exactly in cells whose stencil is interior."""
+    cfg = prob(kind="shock", nx=16, x0=-1.0, x1=1.0, nv=(4, 2, 2), vlo=(-2,) * 3, vhi=(2,) * 3,
+               mach=1.2, cfl=0.45)
+    O = oracle_mod.Oracle(cfg)
+    x = -1.0 + (np.arange(16) + 0.5) * (2.0 / 16)
+    vx, _, _ = O.velocity_nodes()
+    a, b = 0.3 + np.arange(O.nvel) * 0.01, 0.2 + np.arange(O.nvel) * 0.005
+    g = a[None, :] + b[None, :] * x[:, None]
+    dt = O.dt
+    out = O.stream(g, dt)
+    want = a[None, :] + b[None, :] * (x[:, None] - vx[None, :] * dt)
+    np.testing.assert_allclose(out[3:-3], want[3:-3], rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["periodic1d", "periodic2d", "cavity"])
+def test_streaming_conserves_mass(oracle_mod, kind):
+    """Flux form telescopes; periodic ghosts wrap and the wall density makes the
+    net wall mass flux zero (Sec. 5.1), so sum f is kept to rounding."""
+    cfg = prob(kind=kind, nx=7, ny=5, nv=(8, 8, 4), vlo=(-4,) * 3, vhi=(4,) * 3, lid_mach=0.3, t_wall=1.3)
+    O = oracle_mod.Oracle(cfg)
+    base = gauss(O, 1.0, (0.1, 0.0, 0.0), 1.0)
+    g = base[None, :] * inputs.uniform(O.shape, seed=13, lo=0.3, hi=1.7)
+    out = O.stream(g)
+    assert abs(out.sum() - g.sum()) <= 1e-14 * g.sum()
+    if kind.startswith("periodic"):  # per velocity as well
+        np.testing.assert_allclose(out.sum(axis=0), g.sum(axis=0), rtol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["periodic2d", "cavity"])
+def test_streaming_positivity(oracle_mod, kind):
+    """Courant sum 2/3 keeps every value non-negative (each update is a convex
+    combination of neighbours under minmod), also for rough data."""
+    cfg = prob(kind=kind, nx=6, ny=6, nv=(6, 6, 2), vlo=(-3,) * 3, vhi=(3,) * 3, cfl=2.0 / 3.0,
+               lid_mach=0.3)
+    O = oracle_mod.Oracle(cfg)
+    g = inputs.uniform(O.shape, seed=17, lo=0.0, hi=1.0) ** 4
+    assert O.stream(g).min() >= 0.0
+
+
+# ------------------------------------------------------------------ walls
+
+
+def test_wall_density_balances_equal_temperature(oracle_mod):
+    """Sec. 5.1: gas at rest at the wall temperature is re-emitted unchanged,
+    n_W = n, on every wall (the discrete half-range sums mirror each other)."""
+    cfg = prob(kind="cavity", nx=3, ny=2, nv=(12, 12, 6), vlo=(-5,) * 3, vhi=(5,) * 3, t_wall=1.7)
+    O = oracle_mod.Oracle(cfg)
+    f = np.tile(gauss(O, 1.3, (0, 0, 0), 1.7), (O.ncell, 1))
+    nw = O.wall_density(f)
+    np.testing.assert_allclose(nw[:2, :2], 1.3, rtol=1e-14)
+    np.testing.assert_allclose(nw[2:, :3], 1.3, rtol=1e-14)
+
+
+def test_wall_density_closed_form_limit(oracle_mod):
+    """Sec. 5.1: for gas at rest (n, T) next to a wall at T_w the flux balance
+    gives n_W = n sqrt(T / T_w) (half-range Gaussian fluxes (1/2) n sqrt(T/pi)
+    and (1/2) n_W sqrt(T_w/pi)).  The discrete half-range sums carry the
+    midpoint rule's O(dv^2) error at the kink v.n = 0, so the check is the
+    limit: the error is small and falls fourfold when dv halves."""
+    n, T, Tw = 1.3, 0.9, 1.7
+    errs = []
+    for nvx in (200, 400):
+        cfg = prob(kind="cavity", nx=1, ny=1, nv=(nvx, 30, 30), vlo=(-9,) * 3, vhi=(9,) * 3, t_wall=Tw)
+        O = oracle_mod.Oracle(cfg)
+        f = np.tile(gauss(O, n, (0, 0, 0), T), (O.ncell, 1))
+        errs.append(O.wall_density(f)[0, 0] / (n * math.sqrt(T / Tw)) - 1.0)
+    assert abs(errs[0]) < 1e-3
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
+
+
+def test_rest_cavity_is_stationary_under_streaming(oracle_mod):
+    """With U_W = 0 and T_w = T, the rest Maxwellian is reproduced by the
+    walls (n_W = n by the grid's symmetry), so streaming leaves it alone."""
+    cfg = prob(kind="cavity", nx=5, ny=4, nv=(8, 8, 4), vlo=(-4,) * 3, vhi=(4,) * 3, t_wall=1.0)
+    O = oracle_mod.Oracle(cfg)
+    f = O.initial_state()
+    out = O.stream(f)
+    assert np.max(np.abs(out - f)) <= 1e-14 * np.max(f)
+
+
+def test_cavity_mirror_symmetry(oracle_mod):
+    """x -> 1 - x, v_x -> -v_x, U_W -> -U_W maps solutions to solutions (P7)."""
+    nx, ny, nv = 6, 5, (6, 4, 2)
+    base = prob(kind="cavity", nx=nx, ny=ny, nv=nv, vlo=(-3,) * 3, vhi=(3,) * 3, kn=0.3, lid_mach=0.4)
+    O1 = oracle_mod.Oracle(base)
+    O2 = oracle_mod.Oracle(dict(base, lid_mach=-0.4))
+    f = O1.initial_state() * (1 + 0.2 * inputs.uniform(O1.shape, seed=21, lo=-1, hi=1))
+
+    def mirror(a):
+        a5 = a.reshape(ny, nx, nv[2], nv[1], nv[0])
+        return a5[:, ::-1, :, :, ::-1].reshape(a.shape)
+    out1 = O1.step(f, 3)
+    out2 = O2.step(mirror(f), 3)
+    np.testing.assert_allclose(mirror(out1), out2, rtol=1e-13, atol=1e-15)
+
+
+def test_cavity_transpose_symmetry_without_lid(oracle_mod):
+    """With a resting lid all four walls are alike: swapping x <-> y together
+    with v_x <-> v_y maps solutions to solutions (pins 2D indexing)."""
+    n, nv = 5, (4, 4, 2)
+    cfg = prob(kind="cavity", nx=n, ny=n, nv=nv, vlo=(-3,) * 3, vhi=(3,) * 3, kn=0.3, t_wall=1.4)
+    O = oracle_mod.Oracle(cfg)
+    f = O.initial_state() * (1 + 0.2 * inputs.uniform(O.shape, seed=23, lo=-1, hi=1))
+
+    def tr(a):
+        a5 = a.reshape(n, n, nv[2], nv[1], nv[0])
+        return np.ascontiguousarray(a5.transpose(1, 0, 2, 4, 3)).reshape(a.shape)
+    np.testing.assert_allclose(tr(O.step(f, 2)), O.step(tr(f), 2), rtol=1e-13, atol=1e-15)
+
+
+def test_cavity_mass_conserved_over_steps(oracle_mod):
+    """Walls pass no net mass (Sec. 5.1) and collisions conserve it up to the
+    moment defect, so total mass is constant over many steps."""
+    cfg = inputs.config("cavity_128_fp32", nx=6, ny=6)
+    O = oracle_mod.Oracle(cfg)
+    f = O.initial_state()
+    m0 = O.totals(f)[0]
+    f = O.step(f, 40)
+    assert abs(O.totals(f)[0] - m0) <= 1e-11 * m0
+
+
+def test_lid_shear_no_slip_and_limit(oracle_mod):
+    """Lid shear (x-momentum flux through the lid face, Sec. 5.2's D before
+    normalisation).  Gas drifting with the lid at the wall temperature carries
+    no shear; otherwise the flux tends to (1/2) n sqrt(T/pi) (U - U_W) per unit
+    lid length (half-range Gaussian flux times the slip), with the midpoint
+    rule's O(dv^2) error at v_y = 0."""
+    Tw, ma = 1.2, 0.3
+    uw = ma * math.sqrt(GAMMA / 2)
+    cfg = prob(kind="cavity", nx=4, ny=3, nv=(16, 16, 6), vlo=(-6,) * 3, vhi=(6,) * 3, t_wall=Tw, lid_mach=ma)
+    O = oracle_mod.Oracle(cfg)
+    f = np.tile(gauss(O, 1.1, (uw, 0, 0), Tw), (O.ncell, 1))
+    assert abs(O.lid_shear(f)) < 1e-15
+    n, U = 1.1, 0.05
+    errs = []
+    for nvy in (200, 400):
+        cfg = prob(kind="cavity", nx=1, ny=1, nv=(40, nvy, 30), vlo=(-9,) * 3, vhi=(9,) * 3, t_wall=Tw,
+                   lid_mach=ma)
+        O = oracle_mod.Oracle(cfg)
+        f = np.tile(gauss(O, n, (U, 0, 0), Tw), (O.ncell, 1))
+        want = 0.5 * n * math.sqrt(Tw / math.pi) * (U - uw)
+        errs.append(O.lid_shear(f) / want - 1.0)
+    assert abs(errs[0]) < 1e-3
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
+
+
+# ------------------------------------------------------------------ twin
+
+
+@pytest.mark.parametrize("kind", ["shock", "periodic1d", "periodic2d", "cavity"])
+@pytest.mark.parametrize("splitting,limiter", [("strang", "minmod"), ("lie", "none"), ("strang", "none")])
+def test_twin_agrees(oracle_mod, kind, splitting, limiter):
+    """Brute force on tiny inputs: the C oracle and the separately written
+    NumPy twin agree to rounding after three steps."""
+    from oracle.twin import Twin
+    cfg = prob(kind=kind, nx=5, ny=4, nv=(4, 4, 2), vlo=(-3, -3, -2), vhi=(3, 3, 2), kn=0.4,
+               mach=1.5, x0=-1.0 if kind == "shock" else 0.0, lid_mach=0.25, t_wall=1.2,
+               splitting=splitting, limiter=limiter)
+    O, W = oracle_mod.Oracle(cfg), Twin(cfg)
+    f = O.initial_state() * (1 + 0.3 * inputs.uniform(O.shape, seed=29, lo=-1, hi=1))
+    assert W.dt == pytest.approx(O.dt, rel=1e-15)
+    np.testing.assert_allclose(O.step(f, 3), W.step(f, 3), rtol=1e-12, atol=1e-15)
+
+
+def test_time_step_rule(oracle_mod):
+    """dt = CFL / max sum_d |v_d| / dx_d over velocity cell centres."""
+    O = oracle_mod.Oracle(inputs.config("shock_m1.5_fp64"))
+    assert O.dt == pytest.approx(0.5 * (40 / 256) / (6 - 6 / 32), rel=1e-15)
+    O = oracle_mod.Oracle(inputs.config("cavity_128_fp32"))
+    assert O.dt == pytest.approx(0.5 / (2 * 128 * (5 - 5 / 24)), rel=1e-15)
+
+
+def test_steady_shock_connects_rankine_hugoniot_states(oracle_mod):
+    """Sec. 4.1: the long-time solution is a steady shock joining the two
+    far-field states of Eq. (RH).  Steadiness of the 1D BGK equation means the
+    fluxes of mass, x-momentum and energy are the same at every x; they must
+    equal the Rankine-Hugoniot fluxes (to the discretisation error of this
+    coarse grid, which decays as the transient leaves)."""
+    cfg = inputs.config("shock_m1.5_fp64", nx=64, nv=(16, 16, 16))
+    O = oracle_mod.Oracle(cfg)
+    f = O.step(O.initial_state(), 1200)  # t = 66.7 upstream collision times
+    vx, vy, vz = O.velocity_nodes()
+    dV = (12 / 16) ** 3
+    up, dn = oracle_mod.Oracle.rankine_hugoniot(1.5)
+    n, V, T = up
+    fluxes = {
+        "mass": ((f * vx).sum(1) * dV, n * V),
+        "momentum": ((f * vx * vx).sum(1) * dV, n * V * V + n * T / 2),
+        "energy": ((f * vx * (vx * vx + vy * vy + vz * vz)).sum(1) * dV, n * V * (V * V + 2.5 * T)),
+    }
+    for name, (prof, want) in fluxes.items():
+        assert np.max(np.abs(prof / want - 1.0)) < 2.5e-3, name
+    m = O.moments(f)
+    np.testing.assert_allclose(m[0, [0, 1, 4]], up, rtol=2e-3)
+    np.testing.assert_allclose(m[-1, [0, 1, 4]], dn, rtol=2e-3)
