@@ -1,0 +1,145 @@
+/*
+ * bgk.h -- C ABI of the MI355X BGK discrete-velocity stepper (libbgk.so).
+ *
+ * The library advances the distribution function f(x, v) of the BGKW model
+ * kinetic equation (Frezzotti, Ghiroldi and Gibelli, "Solving Kinetic
+ * Equations on GPUs I: Model Kinetic Equations", arXiv:0903.4044, Sec. 2,
+ * Eq. (BGKW)) on a spatial grid times a uniform 3D velocity grid (Sec. 2.1),
+ * for the paper's two problems: the 1D normal shock (Sec. 4.1) and the 2D
+ * lid-driven cavity with diffuse walls (Sec. 5.1), plus periodic test boxes.
+ *
+ * One time step is R_{dt/2} S_dt R_{dt/2} (Strang) or R_dt S_dt (Lie, the
+ * order of Sec. 2.1), where R_tau is the exact homogeneous relaxation of
+ * Eq. (relaxation) towards the local Maxwellian of Eq. (Maxw), built from the
+ * moments of Eq. (macroscopic) of R's own input, and S_dt is free streaming
+ * (Eq. freestreaming) by a minmod-limited upwind scheme in flux form whose
+ * first-order special case is Eq. (upwind).
+ *
+ * Units are those of Sec. 4.1: velocity in sqrt(2 R T_r), so the Maxwellian
+ * is n (pi T)^(-3/2) exp(-|v - V|^2 / T) and the collision frequency of
+ * Eq. (frequency) with mu ~ T^omega is nu = n T^(1 - omega) / Kn.
+ *
+ * Memory.  All arrays passed to the calls below are DEVICE pointers owned by
+ * the caller (typically torch tensors).  f holds every instance of the
+ * context back to back; instance k starts at element f_offset(k) and is
+ * laid out f[cell][jz][jy][jx] (velocity fastest, jx fastest of all;
+ * cell = iy * nx + ix).  Elements are double for BGK_FP64 and float for
+ * BGK_FP32.  The context owns only its own device work space (one extra f
+ * buffer, per-cell tables and moment partials), allocated in bgk_init.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Work is enqueued asynchronously; no call below synchronises the
+ * host except bgk_check, bgk_timing and bgk_free.
+ *
+ * Errors.  Every call returns a status code (BGK_OK = 0).  No exception or
+ * abort crosses the ABI.  bgk_last_error(ctx) describes the last failure on
+ * that context; bgk_last_error(NULL) describes the last failed bgk_init of
+ * the calling thread.
+ */
+#ifndef BGK_H
+#define BGK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define BGK_OK 0
+#define BGK_E_INVALID 1     /* bad argument (NULL, size, kind, non-positive parameter) */
+#define BGK_E_CFL 2         /* Courant sum above 2/3: positivity not guaranteed */
+#define BGK_E_UNSUPPORTED 3 /* valid but outside what this build handles */
+#define BGK_E_HIP 4         /* a HIP runtime call failed */
+#define BGK_E_NONFINITE 5   /* bgk_check: a moment is NaN or infinite */
+#define BGK_E_NEGATIVE 6    /* bgk_check: a density or temperature is <= 0 */
+#define BGK_E_ALIAS 7       /* input and output buffers are the same */
+
+/* Problem kinds. */
+#define BGK_SHOCK_1D 0      /* Sec. 4.1: far-field Maxwellians of Eq. (bc_shock) at both ends */
+#define BGK_CAVITY_2D 1     /* Sec. 5.1: four diffuse walls of Eq. (bc_cavity), moving lid on top */
+#define BGK_PERIODIC_1D 2   /* periodic test box */
+#define BGK_PERIODIC_2D 3   /* periodic test box */
+
+#define BGK_STRANG 0        /* R_{dt/2} S_dt R_{dt/2} */
+#define BGK_LIE 1           /* R_dt S_dt (Sec. 2.1) */
+#define BGK_MINMOD 0        /* second-order minmod-limited upwind */
+#define BGK_NOLIMIT 1       /* first-order upwind, Eq. (upwind) */
+
+#define BGK_FP64 0          /* f stored and streamed in double */
+#define BGK_FP32 1          /* f stored and streamed in float; moments, Maxwellian
+                               parameters and all reductions in double */
+
+/* One problem instance (Sec. 2.1 grid, Sec. 4.1 / 5.1 boundary data). */
+typedef struct bgk_problem {
+    int kind;               /* BGK_SHOCK_1D, BGK_CAVITY_2D, BGK_PERIODIC_1D/2D */
+    int nx, ny;             /* spatial cells (ny ignored for 1D kinds) */
+    double x0, x1, y0, y1;  /* spatial box */
+    int nv[3];              /* velocity cells per component (even, 2..128) */
+    double vlo[3], vhi[3];  /* velocity box; nodes at cell centres */
+    double kn;              /* Knudsen number, > 0 */
+    double omega;           /* viscosity exponent: nu = n T^(1-omega) / Kn */
+    double cfl;             /* used when dt <= 0: dt = cfl / max_j sum_d |v_d|/dx_d */
+    double dt;              /* > 0: time step as given */
+    double mach;            /* shock: upstream Mach number (Eq. RH), > 1 */
+    double lid_mach;        /* cavity: lid speed as a Mach number at T_r, U_W = Ma sqrt(5/6) */
+    double t_wall;          /* cavity: wall temperature, > 0 */
+    int splitting;          /* BGK_STRANG or BGK_LIE */
+    int limiter;            /* BGK_MINMOD or BGK_NOLIMIT */
+} bgk_problem;
+
+typedef struct bgk_ctx bgk_ctx;
+
+/* Create a context for n_probs instances stepped together (one launch per
+ * kernel for all of them).  All instances must share the velocity grid and
+ * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
+ * instance's dt, and allocates the context's device work space on the current
+ * device.  precision: BGK_FP64 or BGK_FP32.
+ * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3), BGK_E_UNSUPPORTED,
+ * BGK_E_HIP.  On failure *out is NULL. */
+int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out);
+
+/* Release the context and its device memory (synchronises the device). */
+int bgk_free(bgk_ctx *ctx);
+
+/* Human-readable description of the last error (never NULL). */
+const char *bgk_last_error(const bgk_ctx *ctx);
+
+/* Sizes: total f elements over all instances, total spatial cells. */
+int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells);
+
+/* Per-instance layout: element offset of the instance in f, index of its
+ * first cell in per-cell arrays, and its time step. */
+int bgk_instance_info(const bgk_ctx *ctx, int inst, size_t *f_offset, size_t *cell_offset, double *dt);
+
+/* Write the initial state into f (device, f_elems elements): the
+ * Rankine-Hugoniot step of Sec. 4.1 for shocks (upstream state for x < 0,
+ * downstream for x >= 0), the gas at rest (n = T = 1) otherwise. */
+int bgk_initial_state(bgk_ctx *ctx, void *f, void *stream);
+
+/* Advance all instances by n_steps >= 0 time steps:
+ * f_out = (one step)^n_steps (f_in).  f_in is read only; f_out must not
+ * alias f_in (BGK_E_ALIAS).  Both hold f_elems elements on the device. */
+int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *stream);
+
+/* Moments of Eq. (macroscopic) of f, per cell: mom[cell][5] =
+ * (n, Vx, Vy, Vz, T), double, device, n_cells * 5 elements. */
+int bgk_moments(bgk_ctx *ctx, const void *f, double *mom, void *stream);
+
+/* Check f: computes its moments and returns BGK_E_NONFINITE or
+ * BGK_E_NEGATIVE if any cell has a non-finite moment or n <= 0 or T <= 0
+ * (synchronises the stream). */
+int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
+
+/* Timing of the streaming kernel: when on, bgk_step records a pair of HIP
+ * events around every launch of it on `stream`.  bgk_timing synchronises
+ * and returns the summed device time (ms) and the launch count since the
+ * last reset, then resets. */
+int bgk_set_timing(bgk_ctx *ctx, int on);
+int bgk_timing(bgk_ctx *ctx, double *ms, int *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BGK_H */

@@ -1,0 +1,194 @@
+"""ctypes binding of libbgk.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module turns problem dicts
+into ``bgk_problem`` structs, passes device pointers of torch tensors and the
+current torch stream, and raises on non-zero status codes.  It fails loudly
+when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbgk.so")
+
+OK, E_INVALID, E_CFL, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_NEGATIVE, E_ALIAS = range(8)
+KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3}
+FP64, FP32 = 0, 1
+
+
+class BGKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bgk error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("nv", ctypes.c_int * 3),
+        ("vlo", ctypes.c_double * 3), ("vhi", ctypes.c_double * 3),
+        ("kn", ctypes.c_double), ("omega", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
+        ("mach", ctypes.c_double), ("lid_mach", ctypes.c_double),
+        ("t_wall", ctypes.c_double),
+        ("splitting", ctypes.c_int), ("limiter", ctypes.c_int),
+    ]
+
+
+EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_info",
+           "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
+           "bgk_timing")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbgk.so and declare its signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_0903_4044_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, sz, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double), \
+        ctypes.POINTER(ctypes.c_int)
+    L.bgk_init.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.bgk_free.argtypes = [vp]
+    L.bgk_last_error.argtypes = [vp]
+    L.bgk_last_error.restype = ctypes.c_char_p
+    L.bgk_sizes.argtypes = [vp, sz, sz]
+    L.bgk_instance_info.argtypes = [vp, ctypes.c_int, sz, sz, dp]
+    L.bgk_initial_state.argtypes = [vp, vp, vp]
+    L.bgk_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    L.bgk_moments.argtypes = [vp, vp, vp, vp]
+    L.bgk_check.argtypes = [vp, vp, vp]
+    L.bgk_set_timing.argtypes = [vp, ctypes.c_int]
+    L.bgk_timing.argtypes = [vp, dp, ip]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
+    L.bgk_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def to_struct(cfg: dict) -> Problem:
+    p = Problem()
+    p.kind = KINDS[cfg["kind"]]
+    p.nx = int(cfg["nx"])
+    p.ny = int(cfg.get("ny", 1))
+    p.x0, p.x1 = float(cfg["x0"]), float(cfg["x1"])
+    p.y0, p.y1 = float(cfg.get("y0", 0.0)), float(cfg.get("y1", 1.0))
+    for a in range(3):
+        p.nv[a] = int(cfg["nv"][a])
+        p.vlo[a] = float(cfg["vlo"][a])
+        p.vhi[a] = float(cfg["vhi"][a])
+    p.kn, p.omega = float(cfg["kn"]), float(cfg["omega"])
+    p.cfl, p.dt = float(cfg.get("cfl", 0.5)), float(cfg.get("dt", 0.0))
+    p.mach = float(cfg.get("mach", 0.0))
+    p.lid_mach = float(cfg.get("lid_mach", 0.0))
+    p.t_wall = float(cfg.get("t_wall", 1.0))
+    p.splitting = 0 if cfg.get("splitting", "strang") == "strang" else 1
+    p.limiter = 0 if cfg.get("limiter", "minmod") == "minmod" else 1
+    return p
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> int:
+    assert t.is_cuda and t.is_contiguous()
+    return int(t.data_ptr())
+
+
+class Context:
+    """Owns a bgk_ctx for one or more instances stepped together."""
+
+    def __init__(self, problems, precision: str | None = None):
+        if isinstance(problems, dict):
+            problems = [problems]
+        self.problems = [dict(p) for p in problems]
+        prec = precision or self.problems[0].get("precision", "fp64")
+        self.precision = prec
+        self.code = FP64 if prec == "fp64" else FP32
+        self.dtype = torch.float64 if prec == "fp64" else torch.float32
+        self.L = load()
+        arr = (Problem * len(self.problems))(*[to_struct(p) for p in self.problems])
+        h = ctypes.c_void_p()
+        rc = self.L.bgk_init(arr, len(self.problems), self.code, ctypes.byref(h))
+        if rc != OK:
+            raise BGKError(rc, self.L.bgk_last_error(None).decode())
+        self.h = h
+        fe, nc = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.L.bgk_sizes(self.h, ctypes.byref(fe), ctypes.byref(nc)))
+        self.f_elems, self.ncells = fe.value, nc.value
+        self.nvel = inputs.nvel(self.problems[0])
+        self.offsets, self.cell_offsets, self.dts = [], [], []
+        for i in range(len(self.problems)):
+            fo, co, dt = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_double()
+            self._check(self.L.bgk_instance_info(self.h, i, ctypes.byref(fo), ctypes.byref(co), ctypes.byref(dt)))
+            self.offsets.append(fo.value)
+            self.cell_offsets.append(co.value)
+            self.dts.append(dt.value)
+
+    def _check(self, rc):
+        if rc != OK:
+            raise BGKError(rc, self.L.bgk_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bgk_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers --------------------------------------------------------
+    def empty(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.f_elems, dtype=self.dtype, device=device)
+
+    def instance_view(self, f: torch.Tensor, i: int) -> torch.Tensor:
+        n = inputs.ncells(self.problems[i]) * self.nvel
+        o = self.offsets[i]
+        return f[o:o + n].view(inputs.ncells(self.problems[i]), self.nvel)
+
+    # -- calls ----------------------------------------------------------
+    def initial_state(self, f: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        f = self.empty() if f is None else f
+        self._check(self.L.bgk_initial_state(self.h, _ptr(f), _stream_handle(stream)))
+        return f
+
+    def step(self, f_in: torch.Tensor, f_out: torch.Tensor | None = None, n: int = 1, stream=None) -> torch.Tensor:
+        f_out = torch.empty_like(f_in) if f_out is None else f_out
+        assert f_in.dtype == self.dtype and f_in.numel() == self.f_elems and f_out.numel() == self.f_elems
+        self._check(self.L.bgk_step(self.h, _ptr(f_in), _ptr(f_out), int(n), _stream_handle(stream)))
+        return f_out
+
+    def moments(self, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        out = torch.empty((self.ncells, 5), dtype=torch.float64, device=f.device) if out is None else out
+        self._check(self.L.bgk_moments(self.h, _ptr(f), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def check(self, f: torch.Tensor, stream=None) -> int:
+        return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))
+
+    def set_timing(self, on: bool):
+        self._check(self.L.bgk_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        self._check(self.L.bgk_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

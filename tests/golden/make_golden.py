@@ -1,0 +1,41 @@
+"""Write the oracle's moments of long full-size runs to tests/golden/.
+
+Calls only the FP64 oracle and the problem statements; the stored values are
+what the parity tests compare the HIP path with at full size and full step
+count, where running the oracle inside a test would take too long.
+
+    python tests/golden/make_golden.py shock_m3_fp32 1,10,100,500,1000,2000
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_0903_4044_amd import inputs  # noqa: E402
+
+
+def main(name: str, marks: list[int]):
+    cfg = inputs.config(name)
+    O = oracle.Oracle(cfg)
+    f = O.initial_state()
+    out = {"dt": np.array(O.dt), "steps": np.array(marks)}
+    done = 0
+    t0 = time.time()
+    for m in marks:
+        f = O.step(f, m - done) if m > done else f
+        done = m
+        out[f"moments_{m}"] = O.moments(f)
+        out[f"totals_{m}"] = O.totals(f)
+        print(f"{name}: step {m} ({time.time() - t0:.0f} s)", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
+    np.savez_compressed(path, **out)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], [int(s) for s in sys.argv[2].split(",")])

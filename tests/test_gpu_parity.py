@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (written here, derived in the design notes):
+  FP64 path: every f value within 1e-12 * max|f_ref|, moments within 1e-12;
+  FP32 path: moments within 1e-5 (n and T relative, V over the problem's
+  speed scale: the upstream speed for shocks, the lid speed for cavities).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_0903_4044_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 5.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_0903_4044_amd import binding
+    binding.load()
+    return binding
+
+
+def small(kind, **kw):
+    d = dict(kind=kind, nx=9, ny=7, x0=-2.0 if kind == "shock" else 0.0, x1=2.0 if kind == "shock" else 1.0,
+             y0=0.0, y1=1.0, nv=(12, 10, 6), vlo=(-4.0, -4.0, -3.0), vhi=(4.0, 4.0, 3.0), kn=0.3, omega=0.5,
+             cfl=0.5, dt=0.0, mach=1.5, lid_mach=0.2, t_wall=1.1, splitting="strang", limiter="minmod")
+    d.update(kw)
+    return d
+
+
+def speed_scale(cfg):
+    if cfg["kind"] == "shock":
+        return cfg["mach"] * math.sqrt(GAMMA / 2)
+    if cfg["kind"] == "cavity" and cfg.get("lid_mach", 0.0) != 0.0:
+        return abs(cfg["lid_mach"]) * math.sqrt(GAMMA / 2)
+    return 1.0
+
+
+def moment_errors(got, ref, cfg):
+    """(e_n, e_V, e_T): relative density / temperature, velocity over the speed scale."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    e_n = np.max(np.abs(got[:, 0] - ref[:, 0]) / np.abs(ref[:, 0]))
+    e_T = np.max(np.abs(got[:, 4] - ref[:, 4]) / np.abs(ref[:, 4]))
+    e_V = np.max(np.abs(got[:, 1:4] - ref[:, 1:4])) / speed_scale(cfg)
+    return e_n, e_V, e_T
+
+
+def to_dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=dtype, device="cuda")
+
+
+def perturbed_initial(O, seed, amp=0.2):
+    return O.initial_state() * (1 + amp * inputs.uniform(O.shape, seed=seed, lo=-1, hi=1))
+
+
+def check_fp64(y, ref, O, cfg, tol=1e-12):
+    y = y.cpu().numpy().reshape(O.shape)
+    assert np.max(np.abs(y - ref)) <= tol * np.max(np.abs(ref)), np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    e = moment_errors(O.moments(y), O.moments(ref), cfg)
+    assert max(e) <= tol, e
+
+
+# --------------------------------------------------------------- small cases
+
+CASES = [
+    ("shock", {}), ("shock", dict(nx=1)), ("shock", dict(nx=2, mach=3.0)),
+    ("shock", dict(splitting="lie", limiter="none")), ("shock", dict(limiter="none")),
+    ("periodic1d", dict(nx=5)), ("periodic1d", dict(splitting="lie")),
+    ("cavity", {}), ("cavity", dict(nx=1, ny=1)), ("cavity", dict(nx=2, ny=5, lid_mach=-0.3, t_wall=0.8)),
+    ("cavity", dict(splitting="lie", limiter="none")),
+    ("periodic2d", dict(nx=4, ny=3)),
+    ("shock", dict(nv=(16, 16, 8))), ("cavity", dict(nv=(24, 24, 24), nx=3, ny=4)),
+    ("shock", dict(nv=(128, 4, 2), nx=3, vlo=(-6, -3, -3), vhi=(6, 3, 3))),
+]
+
+
+@pytest.mark.parametrize("kind,over", CASES)
+@pytest.mark.parametrize("nsteps", [1, 4, 7])
+def test_fp64_small(B, oracle_mod, kind, over, nsteps):
+    cfg = small(kind, **over)
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp64")
+    f0 = perturbed_initial(O, seed=100 + nsteps)
+    ref = O.step(f0, nsteps)
+    y = C.step(to_dev(f0, torch.float64), n=nsteps)
+    torch.cuda.synchronize()
+    assert C.dts[0] == pytest.approx(O.dt, rel=1e-14)
+    check_fp64(y, ref, O, cfg)
+
+
+@pytest.mark.parametrize("kind,over", [c for c in CASES if not c[1].get("nx") == 1])
+def test_fp32_small(B, oracle_mod, kind, over):
+    cfg = small(kind, **over)
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp32")
+    f0 = perturbed_initial(O, seed=7)
+    ref = O.step(f0, 12)
+    y = C.step(to_dev(f0, torch.float32), n=12)
+    got = C.moments(y).cpu().numpy()
+    e = moment_errors(got, O.moments(ref), cfg)
+    assert max(e) <= 1e-5, e
+
+
+def test_zero_steps_copies(B):
+    cfg = small("shock")
+    C = B.Context(cfg, "fp64")
+    x = C.initial_state()
+    y = C.step(x, n=0)
+    assert torch.equal(x, y)
+
+
+def test_initial_state_and_moments(B, oracle_mod):
+    for name in ("shock_m1.5_fp64", "cavity_64_adjoint"):
+        cfg = inputs.config(name)
+        O = oracle_mod.Oracle(cfg)
+        C = B.Context(cfg, "fp64")
+        f = C.initial_state()
+        ref = O.initial_state()
+        np.testing.assert_allclose(f.cpu().numpy().reshape(O.shape), ref, rtol=1e-13, atol=1e-300)
+        np.testing.assert_allclose(C.moments(f).cpu().numpy(), O.moments(ref), rtol=1e-12, atol=1e-13)
+
+
+def test_batched_matches_single_and_oracle(B, oracle_mod):
+    """Uneven instances in one context: each equals its own oracle run and
+    its own single-instance context bit for bit."""
+    cfgs = [small("cavity", nx=n, ny=m, kn=k, lid_mach=u)
+            for n, m, k, u in [(3, 3, 0.1, 0.1), (6, 5, 1.0, 0.3), (2, 7, 0.05, 0.05), (9, 9, 0.4, 0.2)]]
+    C = B.Context(cfgs, "fp64")
+    f0s = [perturbed_initial(oracle_mod.Oracle(c), seed=40 + i) for i, c in enumerate(cfgs)]
+    x = torch.cat([to_dev(f, torch.float64) for f in f0s])
+    y = C.step(x, n=5)
+    for i, c in enumerate(cfgs):
+        O = oracle_mod.Oracle(c)
+        yi = C.instance_view(y, i)
+        check_fp64(yi, O.step(f0s[i], 5), O, c)
+        Ci = B.Context(c, "fp64")
+        assert torch.equal(Ci.step(to_dev(f0s[i], torch.float64), n=5).view_as(yi), yi)
+
+
+# --------------------------------------------------------------- full size
+
+
+def test_shock_m15_fp64_full_run(B, oracle_mod):
+    """Mach 1.5 shock, 256 x 32^3, FP64, all 200 Strang steps."""
+    cfg = inputs.config("shock_m1.5_fp64")
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp64")
+    f0 = O.initial_state()
+    x = C.initial_state()
+    np.testing.assert_allclose(x.cpu().numpy().reshape(O.shape), f0, rtol=1e-13, atol=1e-300)
+    y = C.step(x, n=cfg["steps"])
+    ref = O.step(f0, cfg["steps"])
+    check_fp64(y, ref, O, cfg)
+
+
+@pytest.mark.parametrize("name,precision,nsteps", [
+    ("shock_m3_fp32", "fp32", 2), ("shock_m3_fp32", "fp64", 1),
+    ("cavity_128_fp32", "fp32", 2), ("cavity_128_fp32", "fp64", 1)])
+def test_full_size_few_steps(B, oracle_mod, name, precision, nsteps):
+    """Full-size grids in the benchmark's launch configuration, a few steps."""
+    cfg = inputs.config(name)
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, precision)
+    x = C.initial_state()
+    y = C.step(x, n=nsteps)
+    ref = O.step(O.initial_state(), nsteps)
+    if precision == "fp64":
+        check_fp64(y, ref, O, cfg)
+    else:
+        e = moment_errors(C.moments(y).cpu().numpy(), O.moments(ref), cfg)
+        assert max(e) <= 1e-5, e
+
+
+def test_shock_m3_fp32_golden(B):
+    """Mach 3 shock, 1024 x 48^3, FP32 f: moments against stored oracle runs
+    (tests/golden/make_golden.py) up to the full 2000 steps."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "shock_m3_fp32_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    G = np.load(path)
+    cfg = inputs.config("shock_m3_fp32")
+    C = B.Context(cfg, "fp32")
+    assert C.dts[0] == pytest.approx(float(G["dt"]), rel=1e-14)
+    f = C.initial_state()
+    done = 0
+    for m in [int(s) for s in G["steps"]]:
+        f = C.step(f, n=m - done)
+        done = m
+        e = moment_errors(C.moments(f).cpu().numpy(), G[f"moments_{m}"], cfg)
+        assert max(e) <= 1e-5, (m, e)
+
+
+# --------------------------------------------------------------- errors
+
+
+def test_alias_rejected(B):
+    C = B.Context(small("shock"), "fp64")
+    x = C.initial_state()
+    with pytest.raises(B.BGKError) as ei:
+        C.step(x, x, n=1)
+    assert ei.value.code == B.E_ALIAS
+
+
+def test_check_flags_nonfinite_and_negative(B):
+    C = B.Context(small("cavity"), "fp32")
+    x = C.initial_state()
+    assert C.check(x) == B.OK
+    y = x.clone()
+    y[5 * C.nvel + 3] = float("nan")
+    assert C.check(y) == B.E_NONFINITE
+    z = x.clone()
+    z[2 * C.nvel:3 * C.nvel] *= -1.0
+    assert C.check(z) == B.E_NEGATIVE
