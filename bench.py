@@ -1,0 +1,204 @@
+"""Benchmark of the BGK step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Times K BGK time steps (one bgk_step call; every step is the whole hot path:
+relaxation, moments, Maxwellian, minmod streaming with boundary fluxes) of the
+Mach-3 shock workload (1024 cells x 48^3 velocities, FP32 f, FP64 moments)
+with the state resident in HBM, and prints one JSON line with
+  value     phase-space point updates per second (cells x velocities x steps / s),
+  roofline  algorithmic HBM bytes of the streaming kernel / its average
+            duration (HIP events around each launch), against 8 TB/s,
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample,
+  extras    the other single-GPU workloads (FP64 shock, cavity, batch),
+            each with its own rate and roofline fraction.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+DESCRIPTIONS = {
+    "shock_m3_fp32": "1D normal shock, Mach 3, Kn 1, Nx 1024 on [-20,20], 48^3 velocities on [-8,8]^3, "
+                     "RH step initial state, Strang + minmod upwind, CFL 0.5; f FP32, moments FP64",
+    "shock_m1.5_fp64": "1D normal shock, Mach 1.5, Kn 1, Nx 256 on [-20,20], 32^3 velocities on [-6,6]^3, "
+                       "FP64 throughout, Strang + minmod upwind, CFL 0.5",
+    "cavity_128_fp32": "2D lid-driven cavity 128x128, lid Mach 0.1, Kn 0.1, T_w 1, 24^3 velocities on [-5,5]^3, "
+                       "diffuse walls; f FP32, moments FP64",
+}
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources: traffic counters are reported only while
+    the kernels are the ones they were taken from."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0903_4044_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(workload: str):
+    """HBM bytes per streaming launch from a committed counter summary
+    (profiles/<kernel>_<workload>_counters.txt), if taken from these kernels."""
+    path = os.path.join(PROFILES, f"k_stream_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bytes_per_update(precision: str) -> int:
+    # the streaming kernel reads h once and writes it once per time step
+    return 8 if precision == "fp32" else 16
+
+
+def run_workload(binding, inputs, torch, problems, precision, steps, warmup):
+    """Returns (seconds for `steps`, kernel ms per launch, points)."""
+    ctx = binding.Context(problems, precision)
+    points = ctx.f_elems
+    x = ctx.initial_state()
+    y = ctx.empty()
+    ctx.set_timing(steps + warmup + 4)
+    if warmup:
+        ctx.step(x, y, n=warmup)
+    torch.cuda.synchronize()
+    ctx.timing()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(x, y, n=steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches = ctx.timing()
+    ctx.set_timing(0)
+    rc = ctx.check(y)
+    ctx.close()
+    if rc != 0:
+        raise RuntimeError(f"state check failed after the timed run (status {rc})")
+    return t1 - t0, ms / max(launches, 1), points
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """The FP64 oracle on the same grid: one step, then as many as fit in the
+    budget; returns updates/s and the sample description."""
+    import oracle
+    O = oracle.Oracle(cfg)
+    f = O.initial_state()
+    t0 = time.perf_counter()
+    f = O.step(f, 1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    O.step(f, n)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    return {"value": O.ncell * O.nvel * n / t, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} time steps of the full {O.ncell} x {O.nvel} grid in FP64 after one untimed step "
+                      f"({t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="shock_m3_fp32")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this size 3 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the stepper has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0903_4044_amd import binding, inputs
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    cfg = inputs.config(args.workload)
+    prec = cfg["precision"]
+    secs, kms, points = run_workload(binding, inputs, torch, cfg, prec, args.steps, args.warmup)
+    value = points * args.steps / secs
+    bpu = bytes_per_update(prec)
+    achieved = bpu * points / (kms * 1e-3) / 1e9
+    traffic = read_traffic(args.workload)
+    out = {
+        "metric": "phase-space point updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic: analytic Rankine-Hugoniot initial state, no dataset",
+        "config": {"workload": args.workload, "description": DESCRIPTIONS.get(args.workload, ""),
+                   "cells": inputs.ncells(cfg), "velocities": inputs.nvel(cfg), "points": points,
+                   "moments": "f64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_stream", "kernel_ms": kms, "bytes_per_update": bpu},
+    }
+    print(f"# {args.workload}: {value:.4g} updates/s, k_stream {kms * 1e3:.1f} us, "
+          f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
+
+    if not args.no_extras:
+        extras = {}
+        plain = None
+        for name, steps in (("shock_m1.5_fp64", 200), ("cavity_128_fp32", 200)):
+            c = inputs.config(name)
+            s, k, pts = run_workload(binding, inputs, torch, c, c["precision"], steps, 10)
+            a = bytes_per_update(c["precision"]) * pts / (k * 1e-3) / 1e9
+            extras[name] = {"updates_per_s": pts * steps / s, "steps": steps, "kernel_ms": k,
+                            "achieved_GBs": a, "frac": a / PEAK_HBM_GBS}
+            if name == "shock_m1.5_fp64":
+                plain = pts * steps / s
+            print(f"# {name}: {pts * steps / s:.4g} updates/s, {a:.0f} GB/s", file=sys.stderr, flush=True)
+        extras["plain_fp64_updates_per_s"] = plain
+        extras["ratio_vs_plain_fp64"] = {k: v["updates_per_s"] / plain for k, v in extras.items()
+                                         if isinstance(v, dict)}
+        out["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

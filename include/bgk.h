@@ -131,11 +131,13 @@ int bgk_moments(bgk_ctx *ctx, const void *f, double *mom, void *stream);
  * (synchronises the stream). */
 int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
 
-/* Timing of the streaming kernel: when on, bgk_step records a pair of HIP
- * events around every launch of it on `stream`.  bgk_timing synchronises
- * and returns the summed device time (ms) and the launch count since the
- * last reset, then resets. */
-int bgk_set_timing(bgk_ctx *ctx, int on);
+/* Timing of the streaming kernel.  capacity > 0 turns timing on and creates
+ * that many HIP event pairs up front (more are created on demand); while on,
+ * bgk_step records a pair around every launch of the streaming kernel on
+ * `stream`.  capacity = 0 turns timing off.  bgk_timing synchronises and
+ * returns the summed device time (ms) and the launch count since the last
+ * reset, then resets. */
+int bgk_set_timing(bgk_ctx *ctx, int capacity);
 int bgk_timing(bgk_ctx *ctx, double *ms, int *launches);
 
 #ifdef __cplusplus

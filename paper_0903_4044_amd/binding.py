@@ -185,8 +185,9 @@ class Context:
     def check(self, f: torch.Tensor, stream=None) -> int:
         return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))
 
-    def set_timing(self, on: bool):
-        self._check(self.L.bgk_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, capacity: int):
+        """capacity > 0: time every streaming launch (events made up front); 0: off."""
+        self._check(self.L.bgk_set_timing(self.h, int(capacity)))
 
     def timing(self):
         ms, n = ctypes.c_double(), ctypes.c_int()

@@ -443,11 +443,17 @@ extern "C" int bgk_check(bgk_ctx *ctx, const void *f, void *stream)
     return BGK_OK;
 }
 
-extern "C" int bgk_set_timing(bgk_ctx *ctx, int on)
+extern "C" int bgk_set_timing(bgk_ctx *ctx, int capacity)
 {
-    if (!ctx) return BGK_E_INVALID;
-    ctx->timing = on != 0;
+    if (!ctx || capacity < 0) return BGK_E_INVALID;
+    ctx->timing = capacity > 0;
     ctx->ev_used = 0;
+    while (ctx->events.size() < (size_t)capacity) {
+        hipEvent_t a, b;
+        HIP_TRY(ctx, hipEventCreate(&a));
+        HIP_TRY(ctx, hipEventCreate(&b));
+        ctx->events.push_back({a, b});
+    }
     return BGK_OK;
 }
 
