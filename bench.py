@@ -74,29 +74,41 @@ def bytes_per_update(precision: str) -> int:
     return 8 if precision == "fp32" else 16
 
 
-def run_workload(binding, inputs, torch, problems, precision, steps, warmup):
-    """Returns (seconds for `steps`, kernel ms per launch, points)."""
+def run_workload(binding, torch, problems, precision, steps, warmup, kernel_timing=True, tune=True, graph=False):
+    """Returns (seconds for `steps`, kernel ms per launch, points, launch shape)."""
     ctx = binding.Context(problems, precision)
     points = ctx.f_elems
     x = ctx.initial_state()
     y = ctx.empty()
-    ctx.set_timing(steps + warmup + 4)
-    if warmup:
-        ctx.step(x, y, n=warmup)
     torch.cuda.synchronize()
-    ctx.timing()  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(x, y, n=steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, launches = ctx.timing()
-    ctx.set_timing(0)
-    rc = ctx.check(y)
+    if tune:
+        ctx.autotune(x)
+    shape = ctx.launch()
+    stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        ctx.set_graph(graph)
+        ctx.set_timing(steps + warmup + 4 if kernel_timing and not graph else 0)
+        if warmup:
+            ctx.step(x, y, n=warmup)
+        torch.cuda.synchronize()
+        ctx.timing()  # reset
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(x, y, n=steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms, launches = ctx.timing()
+        if not kernel_timing or graph:
+            ms, launches = float("nan"), 1
+        ctx.set_timing(0)
+        ctx.set_graph(False)
+        rc = ctx.check(y)
     ctx.close()
+    del x, y
+    torch.cuda.empty_cache()
     if rc != 0:
         raise RuntimeError(f"state check failed after the timed run (status {rc})")
-    return t1 - t0, ms / max(launches, 1), points
+    return t1 - t0, ms / max(launches, 1), points, shape
 
 
 def cpu_baseline(cfg, budget_s: float):
@@ -127,6 +139,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no HIP events around the streaming launches (roofline not reported)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this size 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -150,7 +165,8 @@ def main():
         del a, b
     cfg = inputs.config(args.workload)
     prec = cfg["precision"]
-    secs, kms, points = run_workload(binding, inputs, torch, cfg, prec, args.steps, args.warmup)
+    secs, kms, points, shape = run_workload(binding, torch, cfg, prec, args.steps, args.warmup,
+                                            not args.no_kernel_timing, not args.no_tune)
     value = points * args.steps / secs
     bpu = bytes_per_update(prec)
     achieved = bpu * points / (kms * 1e-3) / 1e9
@@ -170,7 +186,7 @@ def main():
         "data": "synthetic: analytic Rankine-Hugoniot initial state, no dataset",
         "config": {"workload": args.workload, "description": DESCRIPTIONS.get(args.workload, ""),
                    "cells": inputs.ncells(cfg), "velocities": inputs.nvel(cfg), "points": points,
-                   "moments": "f64"},
+                   "moments": "f64", "launch": shape},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_stream", "kernel_ms": kms, "bytes_per_update": bpu},
@@ -180,19 +196,24 @@ def main():
 
     if not args.no_extras:
         extras = {}
-        plain = None
-        for name, steps in (("shock_m1.5_fp64", 200), ("cavity_128_fp32", 200)):
-            c = inputs.config(name)
-            s, k, pts = run_workload(binding, inputs, torch, c, c["precision"], steps, 10)
-            a = bytes_per_update(c["precision"]) * pts / (k * 1e-3) / 1e9
-            extras[name] = {"updates_per_s": pts * steps / s, "steps": steps, "kernel_ms": k,
-                            "achieved_GBs": a, "frac": a / PEAK_HBM_GBS}
-            if name == "shock_m1.5_fp64":
-                plain = pts * steps / s
-            print(f"# {name}: {pts * steps / s:.4g} updates/s, {a:.0f} GB/s", file=sys.stderr, flush=True)
+        runs = [("shock_m1.5_fp64", [inputs.config("shock_m1.5_fp64")], "fp64", 200, 10, False),
+                ("cavity_128_fp32", [inputs.config("cavity_128_fp32")], "fp32", 200, 10, False),
+                ("batch_64_cavities_fp32", inputs.batch_cavities(), "fp32", 20, 2, False),
+                ("batch_64_cavities_fp32_graph", inputs.batch_cavities(), "fp32", 20, 2, True)]
+        for name, probs, p, steps, warm, graph in runs:
+            s, k, pts, shp = run_workload(binding, torch, probs, p, steps, warm, True, True, graph)
+            e = {"updates_per_s": pts * steps / s, "steps": steps, "points": pts, "launch": shp,
+                 "precision": p, "graph": graph}
+            if k == k:  # timed kernels (not NaN)
+                a = bytes_per_update(p) * pts / (k * 1e-3) / 1e9
+                e.update({"kernel_ms": k, "achieved_GBs": a, "frac": a / PEAK_HBM_GBS})
+            extras[name] = e
+            print(f"# {name}: {e['updates_per_s']:.4g} updates/s" +
+                  (f", {e['achieved_GBs']:.0f} GB/s" if "achieved_GBs" in e else ""), file=sys.stderr, flush=True)
+        plain = extras["shock_m1.5_fp64"]["updates_per_s"]
         extras["plain_fp64_updates_per_s"] = plain
         extras["ratio_vs_plain_fp64"] = {k: v["updates_per_s"] / plain for k, v in extras.items()
-                                         if isinstance(v, dict)}
+                                         if isinstance(v, dict) and "updates_per_s" in v}
         out["extras"] = extras
 
     if not args.no_cpu_baseline:

@@ -131,6 +131,34 @@ int bgk_moments(bgk_ctx *ctx, const void *f, double *mom, void *stream);
  * (synchronises the stream). */
 int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
 
+/* Launch shape of the streaming kernel (engineering interface; results do
+ * not depend on it beyond rounding of the moment sums).  A shape is
+ * (vec, unroll, vsplit, persist): jx values per lane task (1, 2 or 4; 4 only
+ * for BGK_FP32, and only if it divides Nvx with one v_x sign per group), jz
+ * values per software-pipeline stage (1 or 2), jz chunks per cell (one work
+ * item each, 1 .. a context-dependent maximum), and persist: 0 launches one
+ * workgroup per work item, k > 0 launches k workgroups per compute unit that
+ * walk the items of all instances (one persistent launch for a batch).
+ * bgk_init picks a default.  bgk_autotune times every valid shape on the
+ * state f (device, f_elems elements, read only; synchronises the stream) and
+ * keeps the fastest; bgk_get_launch reports the shape in use and, after
+ * autotuning, the streaming kernel's time in microseconds; bgk_set_launch
+ * applies a shape (BGK_E_INVALID if not valid for the context). */
+int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream);
+int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us);
+int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int persist);
+
+/* Graph replay.  When on (default off), bgk_step captures the steady
+ * two-step part of its launch sequence (streaming pass, table preparation,
+ * streaming pass, table preparation) into a hipGraph the first time a given
+ * output buffer is used, and replays it for the middle steps; graphs are
+ * kept until the launch shape changes, graph replay is switched off or the
+ * context is freed.  Ignored while kernel timing is on and on the NULL
+ * (legacy default) stream, which cannot be captured.  The output buffer's
+ * address is part of the graph: do not free and reuse it for another buffer
+ * while graph replay is on. */
+int bgk_set_graph(bgk_ctx *ctx, int on);
+
 /* Timing of the streaming kernel.  capacity > 0 turns timing on and creates
  * that many HIP event pairs up front (more are created on demand); while on,
  * bgk_step records a pair around every launch of the streaming kernel on

@@ -46,7 +46,9 @@ class Problem(ctypes.Structure):
 
 EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_info",
            "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
-           "bgk_timing")
+           "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph")
+
+TUNED_PATH = os.path.join(HERE, "tuned.json")
 
 _lib = None
 
@@ -73,6 +75,10 @@ def load(path: str = LIB_PATH):
     L.bgk_check.argtypes = [vp, vp, vp]
     L.bgk_set_timing.argtypes = [vp, ctypes.c_int]
     L.bgk_timing.argtypes = [vp, dp, ip]
+    L.bgk_autotune.argtypes = [vp, vp, vp]
+    L.bgk_get_launch.argtypes = [vp, ip, ip, ip, ip, dp]
+    L.bgk_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.bgk_set_graph.argtypes = [vp, ctypes.c_int]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -101,6 +107,25 @@ def to_struct(cfg: dict) -> Problem:
     return p
 
 
+def size_class(problems, precision: str) -> str:
+    """Key of the tuned-shape table: dimension, precision, velocity grid and
+    the power-of-two bucket of the total cell count."""
+    import math
+    p0 = problems[0]
+    cells = sum(inputs.ncells(p) for p in problems)
+    bucket = 1 << max(0, math.ceil(math.log2(max(cells, 1))))
+    nv = "x".join(str(int(v)) for v in p0["nv"])
+    return f"{2 if inputs.is_2d(p0) else 1}d/{precision}/nv{nv}/cells<={bucket}"
+
+
+def load_tuned() -> dict:
+    import json
+    if os.path.exists(TUNED_PATH):
+        with open(TUNED_PATH) as fh:
+            return json.load(fh)
+    return {}
+
+
 def _stream_handle(stream=None) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
@@ -112,9 +137,14 @@ def _ptr(t: torch.Tensor) -> int:
 
 
 class Context:
-    """Owns a bgk_ctx for one or more instances stepped together."""
+    """Owns a bgk_ctx for one or more instances stepped together.
 
-    def __init__(self, problems, precision: str | None = None):
+    tune: "table" applies the launch shape recorded for this size class in
+    tuned.json (if any), "off" keeps the library default; call autotune() to
+    time all shapes on the current device.
+    """
+
+    def __init__(self, problems, precision: str | None = None, tune: str = "table"):
         if isinstance(problems, dict):
             problems = [problems]
         self.problems = [dict(p) for p in problems]
@@ -140,6 +170,11 @@ class Context:
             self.offsets.append(fo.value)
             self.cell_offsets.append(co.value)
             self.dts.append(dt.value)
+        self.key = size_class(self.problems, self.precision)
+        if tune == "table":
+            shape = load_tuned().get(self.key)
+            if shape:
+                self.set_launch(shape["vec"], shape["unroll"], shape["vsplit"], shape.get("persist", 0))
 
     def _check(self, rc):
         if rc != OK:
@@ -184,6 +219,24 @@ class Context:
 
     def check(self, f: torch.Tensor, stream=None) -> int:
         return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))
+
+    def autotune(self, f: torch.Tensor, stream=None) -> dict:
+        """Time every valid streaming-kernel shape on state f; keep the fastest."""
+        self._check(self.L.bgk_autotune(self.h, _ptr(f), _stream_handle(stream)))
+        return self.launch()
+
+    def launch(self) -> dict:
+        v, u, s, p, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self.L.bgk_get_launch(self.h, ctypes.byref(v), ctypes.byref(u), ctypes.byref(s), ctypes.byref(p),
+                                          ctypes.byref(us)))
+        return {"vec": v.value, "unroll": u.value, "vsplit": s.value, "persist": p.value, "tuned_us": us.value}
+
+    def set_launch(self, vec: int, unroll: int, vsplit: int, persist: int = 0):
+        self._check(self.L.bgk_set_launch(self.h, int(vec), int(unroll), int(vsplit), int(persist)))
+
+    def set_graph(self, on: bool):
+        """Replay the steady two-step launch sequence from a captured hipGraph."""
+        self._check(self.L.bgk_set_graph(self.h, 1 if on else 0))
 
     def set_timing(self, capacity: int):
         """capacity > 0: time every streaming launch (events made up front); 0: off."""

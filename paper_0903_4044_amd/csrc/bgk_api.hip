@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -14,6 +15,7 @@
 #include "../../include/bgk.h"
 
 using namespace bgk;
+
 
 struct bgk_ctx {
     int precision = BGK_FP64;
@@ -26,14 +28,29 @@ struct bgk_ctx {
     Geo geo{};
     int ncells = 0, npseudo = 0;
     size_t f_elems = 0;
-    int vsplit = 1;
-    int block = 256;
+    int vsplit = 1;            // jz chunks per cell (one workgroup each)
+    int vsplit_max = 1;        // largest vsplit the partial-sum buffer holds
+    int block = 256;           // moments / final / init kernels
+    int vec = 1;               // streaming kernel: jx per lane task
+    int zr = 1;                // streaming kernel: jz residues per workgroup
+    int sblock = 256;          // streaming kernel: threads per workgroup
+    int unroll = 1;            // streaming kernel: jz values whose loads are issued together
+    int persist = 0;           // streaming kernel: 0 one workgroup per item, else resident workgroups per CU
+    // hipGraph replay of two-step chunks (stream, prep, stream, prep); key:
+    // (f_out, which buffer the chunk starts from, table parity)
+    bool use_graph = false;
+    struct Chunk { const void *f_out; int from_out; int parity; hipGraphExec_t exec; };
+    std::vector<Chunk> chunks;
+    int ncu = 256;             // compute units of the device
+    double tuned_us = 0.0;     // streaming-kernel time of the chosen shape when autotuned
+    // current streaming pass: table parity it reads
+    int pass_parity = 0;
     size_t esize = 8;
     // device memory owned by the context
     Inst *d_inst = nullptr;
     int *d_cell_prefix = nullptr, *d_pseudo_prefix = nullptr;
     void *work = nullptr;      // one f-sized buffer for the ping-pong
-    void *params = nullptr;    // (ncells + npseudo) * pe elements
+    void *params = nullptr;    // 2 x (ncells + npseudo) * pe elements (parity buffers)
     double *partial = nullptr; // ncells * vsplit * NQ
     double *mom = nullptr;     // ncells * 5 (bgk_check)
     int *flags = nullptr;
@@ -74,6 +91,8 @@ static Args make_args(const bgk_ctx *c)
     a.ncells = c->ncells;
     a.npseudo = c->npseudo;
     a.vsplit = c->vsplit;
+    a.zr = c->zr;
+    a.nparts = c->vsplit;
     a.g = c->geo;
     return a;
 }
@@ -93,6 +112,7 @@ static void release(bgk_ctx *c)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (auto &k : c->chunks) (void)hipGraphExecDestroy(k.exec);
     delete c;
 }
 
@@ -146,6 +166,74 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     return BGK_OK;
 }
 
+// Launch shape of the streaming kernel.
+//  vec:    jx values per lane task (16-byte loads where the grid allows);
+//          valid when it divides Nvx and every group of vec consecutive v_x
+//          has one sign;
+//  vsplit: jz chunks per cell, one workgroup each;
+//  unroll: jz values per software-pipeline stage;
+//  zr, sblock: lane tasks = (Nvx/vec) * Nvy * zr fill whole waves; the block is
+//          the largest multiple of 64 up to 256 dividing the task count.
+static bool vec_valid(const bgk_ctx *c, int v)
+{
+    const Geo &g = c->geo;
+    if (v == 1) return true;
+    if (v == 4 && c->precision == BGK_FP64) return false;
+    if (g.nvx % v) return false;
+    for (int k = 0; k < g.nvx; k += v) {
+        const double a = g.lo[0] + (k + 0.5) * g.dv[0], b = g.lo[0] + (k + v - 0.5) * g.dv[0];
+        if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return false;
+    }
+    return true;
+}
+
+static void drop_graphs(bgk_ctx *c)
+{
+    for (auto &k : c->chunks) (void)hipGraphExecDestroy(k.exec);
+    c->chunks.clear();
+}
+
+static void set_shape(bgk_ctx *c, int vec, int unroll, int vsplit, int persist = 0)
+{
+    drop_graphs(c);
+    const Geo &g = c->geo;
+    c->vec = vec;
+    c->unroll = unroll;
+    c->persist = persist;
+    c->vsplit = std::max(1, std::min(c->vsplit_max, vsplit));
+    const int zchunk = g.nvz / c->vsplit;
+    const int groups = g.npl / c->vec;
+    c->zr = 1;
+    c->sblock = 256;
+    for (int zr = 1; zr <= std::max(1, zchunk / 2); ++zr) {
+        const int t = groups * zr;
+        if (t % 64) continue;
+        c->zr = zr;
+        for (int b = 256; b >= 64; b -= 64)
+            if (t % b == 0) { c->sblock = b; break; }
+        break;
+    }
+}
+
+static int vsplit_for(const bgk_ctx *c, int target_wg)
+{
+    return std::max(1, std::min(c->geo.nvz, (target_wg + c->ncells - 1) / c->ncells));
+}
+
+// Default shape (measured on MI355X for the paper's grids; bgk_autotune refines it).
+static void choose_launch(bgk_ctx *c)
+{
+    c->vsplit_max = vsplit_for(c, 8192);
+    int vec = 1;
+    for (int v : {4, 2})
+        if (vec_valid(c, v)) { vec = v; break; }
+    if (c->dim == 2) vec = 1;
+    const int unroll = (c->dim == 1 && c->precision == BGK_FP32) ? 2 : 1;
+    const int target = c->dim == 1 ? (c->precision == BGK_FP32 ? 1024 : 512) : 2048;
+    set_shape(c, vec, unroll, vsplit_for(c, target));
+    c->block = 256;
+}
+
 extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out)
 {
     if (!out) return fail(nullptr, BGK_E_INVALID, "out is NULL");
@@ -170,6 +258,11 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     c->dim = is2d_kind(probs[0].kind) ? 2 : 1;
     c->probs.assign(probs, probs + n_probs);
     (void)hipGetDevice(&c->device);
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+            c->ncu = ncu;
+    }
 
     Geo &g = c->geo;
     g.nvx = probs[0].nv[0];
@@ -240,10 +333,7 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     for (int i = 0; i < n_probs; ++i) c->h_inst[i].pseudo0 = c->ncells + c->h_pseudo_prefix[i];
     c->f_elems = (size_t)f_off;
 
-    // Velocity chunks per cell: enough workgroups to fill 256 CUs several times.
-    const int target = 4096;
-    c->vsplit = std::max(1, std::min(g.nvz, (target + c->ncells - 1) / c->ncells));
-    c->block = 256;
+    choose_launch(c);
 
 #define ALLOC(ptr, bytes)                                                         \
     do {                                                                          \
@@ -258,8 +348,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     ALLOC(c->d_cell_prefix, sizeof(int) * (n_probs + 1));
     ALLOC(c->d_pseudo_prefix, sizeof(int) * (n_probs + 1));
     ALLOC(c->work, c->f_elems * c->esize);
-    ALLOC(c->params, (size_t)(c->ncells + c->npseudo) * g.pe * c->esize);
-    ALLOC(c->partial, sizeof(double) * (size_t)c->ncells * c->vsplit * NQ);
+    ALLOC(c->params, 2 * (size_t)(c->ncells + c->npseudo) * g.pe * c->esize);
+    ALLOC(c->partial, sizeof(double) * (size_t)c->ncells * c->vsplit_max * NQ);
     ALLOC(c->mom, sizeof(double) * (size_t)c->ncells * 5);
     ALLOC(c->flags, sizeof(int));
 #undef ALLOC
@@ -308,6 +398,12 @@ extern "C" int bgk_instance_info(const bgk_ctx *ctx, int inst, size_t *f_offset,
 // ------------------------------------------------------------- launches
 
 template <typename real>
+static real *params_buf(bgk_ctx *c, int parity)
+{
+    return (real *)c->params + (size_t)parity * (c->ncells + c->npseudo) * c->geo.pe;
+}
+
+template <typename real>
 static int launch_moments(bgk_ctx *c, const void *f, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
@@ -317,18 +413,45 @@ static int launch_moments(bgk_ctx *c, const void *f, hipStream_t s)
 }
 
 template <typename real>
-static int launch_prep(bgk_ctx *c, int mode, hipStream_t s)
+static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t s)
 {
-    const int nb = c->ncells + (mode == MODE_FINAL ? 0 : c->npseudo);
-    hipLaunchKernelGGL(k_prep<real>, dim3(nb), dim3(64), 0, s, make_args(c), c->partial, (real *)c->params, mode);
+    const int ne = c->ncells + (mode == MODE_FINAL ? 0 : c->npseudo);
+    Args a = make_args(c);
+    a.nparts = nparts;
+    real *copy = mode == MODE_FIRST ? params_buf<real>(c, 1 - parity) : nullptr;
+    hipLaunchKernelGGL(k_prep<real>, dim3((ne + 3) / 4), dim3(256), 0, s, a, c->partial, params_buf<real>(c, parity),
+                       mode, ne, copy);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
+}
+
+template <typename real, int DIM, int VEC, int UNR>
+static void stream_kernel_u(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR>), dim3(nb), dim3(c->sblock), lds, s, make_args(c),
+                       (const real *)src, (real *)dst, (const real *)params_buf<real>(c, c->pass_parity), c->partial);
+}
+
+template <typename real, int DIM, int VEC>
+static void stream_kernel(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
+{
+    if (c->unroll == 2) stream_kernel_u<real, DIM, VEC, 2>(c, nb, lds, src, dst, s);
+    else stream_kernel_u<real, DIM, VEC, 1>(c, nb, lds, src, dst, s);
+}
+
+template <typename real, int DIM>
+static void stream_dispatch(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
+{
+    if (c->vec == 4 && sizeof(real) == 4) stream_kernel<real, DIM, 4>(c, nb, lds, src, dst, s);
+    else if (c->vec == 2) stream_kernel<real, DIM, 2>(c, nb, lds, src, dst, s);
+    else stream_kernel<real, DIM, 1>(c, nb, lds, src, dst, s);
 }
 
 template <typename real>
 static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
 {
-    const int nb = c->ncells * c->vsplit;
+    const int items = c->ncells * c->vsplit;
+    const int nb = c->persist ? std::min(items, c->persist * c->ncu) : items;
     const int nslot = c->dim == 1 ? 7 : 13;
     const size_t lds = (size_t)nslot * c->geo.pe * sizeof(real);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -344,23 +467,19 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         c->ev_used++;
         HIP_TRY(c, hipEventRecord(e0, s));
     }
-    if (c->dim == 1)
-        hipLaunchKernelGGL((k_stream<real, 1>), dim3(nb), dim3(c->block), lds, s, make_args(c), (const real *)src,
-                           (real *)dst, (const real *)c->params, c->partial);
-    else
-        hipLaunchKernelGGL((k_stream<real, 2>), dim3(nb), dim3(c->block), lds, s, make_args(c), (const real *)src,
-                           (real *)dst, (const real *)c->params, c->partial);
+    if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
+    else stream_dispatch<real, 1>(c, nb, lds, src, dst, s);
     HIP_TRY(c, hipGetLastError());
     if (c->timing) HIP_TRY(c, hipEventRecord(e1, s));
     return BGK_OK;
 }
 
 template <typename real>
-static int launch_final(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
+static int launch_final(bgk_ctx *c, const void *src, void *dst, int parity, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
     hipLaunchKernelGGL(k_final<real>, dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src, (real *)dst,
-                       (const real *)c->params);
+                       (const real *)params_buf<real>(c, parity));
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -371,20 +490,140 @@ static int launch_final(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         if (rc_) return rc_;     \
     } while (0)
 
+// Launch sequence of n >= 1 steps.  Tables alternate between two parity
+// buffers: pass k reads buffer (k - 1) % 2 and the preparation after it fills
+// buffer k % 2.  Pass k writes X_k = f_out when n - k is even, else the work
+// buffer, so the last pass lands in f_out.
+template <typename real>
+static int one_pass(bgk_ctx *c, int k, int n, const void *src, void *dst, hipStream_t s)
+{
+    c->pass_parity = (k - 1) % 2;
+    TRY(launch_stream<real>(c, src, dst, s));
+    return launch_prep<real>(c, k < n ? MODE_MID : MODE_FINAL, c->vsplit, k % 2, s);
+}
+
 template <typename real>
 static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t s)
 {
     TRY(launch_moments<real>(c, f_in, s));
-    TRY(launch_prep<real>(c, MODE_FIRST, s));
-    const void *src = f_in;
-    for (int k = 1; k <= n; ++k) {
-        // The last streaming pass lands in f_out; earlier ones alternate with the work buffer.
-        void *dst = ((n - k) % 2 == 0) ? f_out : c->work;
-        TRY(launch_stream<real>(c, src, dst, s));
-        TRY(launch_prep<real>(c, k < n ? MODE_MID : MODE_FINAL, s));
-        src = dst;
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    auto X = [&](int k) -> void * { return k == 0 ? const_cast<void *>(f_in) : ((n - k) % 2 == 0 ? f_out : c->work); };
+    int k = 1;
+    TRY(one_pass<real>(c, k, n, X(0), X(1), s));
+    if (c->use_graph && !c->timing && s != nullptr) {  // the legacy default stream cannot be captured
+        for (k = 2; k + 1 <= n - 1; k += 2) {
+            // passes k, k+1: X(k-1) -> X(k) -> X(k+1) == X(k-1); tables (k-1)%2 -> k%2 -> (k-1)%2
+            const int from_out = X(k - 1) == f_out ? 1 : 0;
+            const int parity = (k - 1) % 2;
+            hipGraphExec_t exec = nullptr;
+            for (auto &ch : c->chunks)
+                if (ch.f_out == f_out && ch.from_out == from_out && ch.parity == parity) exec = ch.exec;
+            if (!exec) {
+                hipGraph_t graph;
+                HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                int rc = one_pass<real>(c, k, n, X(k - 1), X(k), s);
+                if (!rc) rc = one_pass<real>(c, k + 1, n, X(k), X(k + 1), s);
+                hipError_t e = hipStreamEndCapture(s, &graph);
+                if (rc) return rc;
+                if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                c->chunks.push_back({f_out, from_out, parity, exec});
+            }
+            HIP_TRY(c, hipGraphLaunch(exec, s));
+        }
+    } else {
+        k = 2;
     }
-    return launch_final<real>(c, f_out, f_out, s);
+    for (; k <= n; ++k) TRY(one_pass<real>(c, k, n, X(k - 1), X(k), s));
+    return launch_final<real>(c, f_out, f_out, n % 2, s);
+}
+
+// ------------------------------------------------------------- autotuning
+
+template <typename real>
+static int time_stream(bgk_ctx *c, const void *f, hipStream_t s, int reps, double *us)
+{
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    HIP_TRY(c, hipEventCreate(&b));
+    c->pass_parity = 0;
+    const bool timing = c->timing;
+    c->timing = false;
+    int rc = launch_stream<real>(c, f, c->work, s);  // warm
+    if (!rc) rc = hipEventRecord(a, s) == hipSuccess ? 0 : BGK_E_HIP;
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_stream<real>(c, f, c->work, s);
+    if (!rc) rc = hipEventRecord(b, s) == hipSuccess ? 0 : BGK_E_HIP;
+    float ms = 0.0f;
+    if (!rc) rc = hipEventSynchronize(b) == hipSuccess ? 0 : BGK_E_HIP;
+    if (!rc) rc = hipEventElapsedTime(&ms, a, b) == hipSuccess ? 0 : BGK_E_HIP;
+    c->timing = timing;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return fail(c, rc, "autotune: timing failed");
+    *us = 1e3 * ms / reps;
+    return BGK_OK;
+}
+
+// Try the candidate shapes on f and keep the fastest streaming kernel.
+template <typename real>
+static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
+{
+    TRY(launch_moments<real>(c, f, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    const int v0 = c->vec, u0 = c->unroll, s0 = c->vsplit, p0 = c->persist;
+    double best = 1e300;
+    int bv = v0, bu = u0, bs = s0, bp = p0;
+    std::vector<int> splits;
+    for (int t : {256, 512, 1024, 2048, 4096, 8192}) {
+        const int v = std::min(vsplit_for(c, t), c->vsplit_max);
+        if (std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
+    }
+    for (int vec : {4, 2, 1}) {
+        if (!vec_valid(c, vec)) continue;
+        for (int unroll : {1, 2})
+            for (int vs : splits)
+                for (int ps : {0, 2, 4}) {
+                    if (ps && c->ncells * vs <= ps * c->ncu) continue;  // grid already resident
+                    set_shape(c, vec, unroll, vs, ps);
+                    double us = 0.0;
+                    TRY(time_stream<real>(c, f, s, 3, &us));
+                    if (us < best) { best = us; bv = vec; bu = unroll; bs = vs; bp = ps; }
+                }
+    }
+    set_shape(c, bv, bu, bs, bp);
+    c->tuned_us = best;
+    return BGK_OK;
+}
+
+extern "C" int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f) return fail(ctx, BGK_E_INVALID, "bgk_autotune: NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    return ctx->precision == BGK_FP64 ? autotune<double>(ctx, f, s) : autotune<float>(ctx, f, s);
+}
+
+extern "C" int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (vec) *vec = ctx->vec;
+    if (unroll) *unroll = ctx->unroll;
+    if (vsplit) *vsplit = ctx->vsplit;
+    if (persist) *persist = ctx->persist;
+    if (tuned_us) *tuned_us = ctx->tuned_us;
+    return BGK_OK;
+}
+
+extern "C" int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int persist)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!(vec == 1 || vec == 2 || vec == 4) || !vec_valid(ctx, vec) || !(unroll == 1 || unroll == 2) || vsplit < 1 ||
+        vsplit > ctx->vsplit_max || persist < 0 || persist > 64)
+        return fail(ctx, BGK_E_INVALID, "bgk_set_launch: shape not valid for this context");
+    set_shape(ctx, vec, unroll, vsplit, persist);
+    return BGK_OK;
 }
 
 extern "C" int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *stream)
@@ -440,6 +679,14 @@ extern "C" int bgk_check(bgk_ctx *ctx, const void *f, void *stream)
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (flags & 1) return fail(ctx, BGK_E_NONFINITE, "bgk_check: non-finite moment");
     if (flags & 2) return fail(ctx, BGK_E_NEGATIVE, "bgk_check: density or temperature <= 0");
+    return BGK_OK;
+}
+
+extern "C" int bgk_set_graph(bgk_ctx *ctx, int on)
+{
+    if (!ctx) return BGK_E_INVALID;
+    ctx->use_graph = on != 0;
+    if (!ctx->use_graph) drop_graphs(ctx);
     return BGK_OK;
 }
 

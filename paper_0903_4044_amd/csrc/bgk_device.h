@@ -69,6 +69,8 @@ struct Args {
     int ncells;                 // total cells
     int npseudo;                // total pseudo entries
     int vsplit;                 // velocity chunks (along jz) per cell
+    int zr;                     // jz residues per streaming workgroup (lane tasks)
+    int nparts;                 // partial moment sums per cell that consumers add up
     Geo g;
 };
 
@@ -168,8 +170,8 @@ __global__ void k_macro(Args A, const double *__restrict__ partial, double *__re
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= A.ncells) return;
     double s[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < A.vsplit; ++k)
-        for (int q = 0; q < 5; ++q) s[q] += partial[((long long)c * A.vsplit + k) * NQ + q];
+    for (int k = 0; k < A.nparts; ++k)
+        for (int q = 0; q < 5; ++q) s[q] += partial[((long long)c * A.nparts + k) * NQ + q];
     const double n = s[0] * A.g.dV;
     const double vx = s[1] / s[0], vy = s[2] / s[0], vz = s[3] / s[0];
     const double T = 2.0 / 3.0 * (s[4] / s[0] - (vx * vx + vy * vy + vz * vz));
@@ -193,9 +195,12 @@ __global__ void k_check(int ncells, const double *__restrict__ mom, int *__restr
 }
 
 // ---------------------------------------------------------------- prep
-// One 64-thread workgroup per params entry.
+// One wave per table entry, four entries per 256-thread workgroup.  Each lane
+// owns slots k = lane and k = lane + 64 of the 1D tables of every velocity
+// component; the 1D sums the relaxations need are butterfly wave reductions,
+// so the whole computation stays in registers (no LDS, no block barrier).
 
-// Relaxation times of the two relaxations folded into a table entry.
+// Relaxation times of the relaxations folded into a table entry.
 //   FIRST: g = R1(f0)        (Strang: R_{dt/2}; Lie: identity)
 //   MID:   g = R1(R2(h))     (Strang: R_{dt/2} R_{dt/2}; Lie: R_dt)
 //   FINAL: f = R2(h)         (Strang: R_{dt/2}; Lie: R_dt)
@@ -233,38 +238,62 @@ __device__ __forceinline__ void finish_relax(const Inst &I, double tau, Relax *r
     r->P = r->n * pow(M_PI * r->T, -1.5);
 }
 
-// e[a * NVMAX + k] = exp(-(v_a(k) - V_a)^2 / T) for all three components.
-__device__ __forceinline__ void exp_tables(const Geo &g, const double V[3], double T, double *e)
+__device__ __forceinline__ double wave_sum(double x)
 {
-    const int n = g.nvx + g.nvy + g.nvz;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        int a, k;
-        if (t < g.nvx) { a = 0; k = t; }
-        else if (t < g.nvx + g.nvy) { a = 1; k = t - g.nvx; }
-        else { a = 2; k = t - g.nvx - g.nvy; }
-        const double d = vnode(g, a, k) - V[a];
-        e[a * NVMAX + k] = exp(-d * d / T);
-    }
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
 }
 
-// Serial 1D sums of a table (one thread per component, fixed order):
-// s[a][0] = sum e, s[a][1] = sum v e, s[a][2] = sum v^2 e,
-// s[a][3] = sum_{v<0} |v| e, s[a][4] = sum_{v>0} v e.
-__device__ __forceinline__ void table_sums(const Geo &g, const double *e, double (*s)[5])
+__device__ __forceinline__ int nv_of(const Geo &g, int a) { return a == 0 ? g.nvx : (a == 1 ? g.nvy : g.nvz); }
+
+// This lane's slots of e_a(k) = exp(-(v_a(k) - V_a)^2 / T).
+struct Tables {
+    double e[3][2];
+};
+
+__device__ __forceinline__ void lane_tables(const Geo &g, const double V[3], double T, Tables &t)
 {
-    const int a = threadIdx.x;
-    if (a < 3) {
-        const int n = a == 0 ? g.nvx : (a == 1 ? g.nvy : g.nvz);
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int k = lane + 64 * s;
+            const double d = vnode(g, a, k) - V[a];
+            t.e[a][s] = k < nv_of(g, a) ? exp(-d * d / T) : 0.0;
+        }
+}
+
+__device__ __forceinline__ void zero_tables(Tables &t)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.e[a][0] = t.e[a][1] = 0.0;
+}
+
+// Wave-reduced 1D sums of a table: s[a][0] = sum e, s[a][1] = sum v e,
+// s[a][2] = sum v^2 e, s[a][3] = sum_{v<0} |v| e, s[a][4] = sum_{v>0} v e.
+__device__ __forceinline__ void wave_table_sums(const Geo &g, const Tables &t, double (*s)[5], bool half)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
         double s0 = 0, s1 = 0, s2 = 0, sm = 0, sp = 0;
-        for (int k = 0; k < n; ++k) {
-            const double v = vnode(g, a, k), x = e[a * NVMAX + k];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double v = vnode(g, a, lane + 64 * q), x = t.e[a][q];
             s0 += x;
             s1 += v * x;
             s2 += v * v * x;
             if (v < 0.0) sm += -v * x;
-            else if (v > 0.0) sp += v * x;
+            else sp += v * x;
         }
-        s[a][0] = s0; s[a][1] = s1; s[a][2] = s2; s[a][3] = sm; s[a][4] = sp;
+        s[a][0] = wave_sum(s0);
+        s[a][1] = wave_sum(s1);
+        s[a][2] = wave_sum(s2);
+        if (half) {
+            s[a][3] = wave_sum(sm);
+            s[a][4] = wave_sum(sp);
+        }
     }
 }
 
@@ -279,84 +308,79 @@ __device__ __forceinline__ void maxwell_raw(double P, double dV, const double (*
     m[4] = w * (s[0][2] * s[1][0] * s[2][0] + s[0][0] * s[1][2] * s[2][0] + s[0][0] * s[1][0] * s[2][2]);
 }
 
-// Shared state of one prep workgroup.
-struct PrepShared {
-    double raw[NQ];
-    double e1[3 * NVMAX], e2[3 * NVMAX];
-    double s1[3][5], s2[3][5];
+// Everything one wave knows about the relaxations of one cell.
+struct Coef {
+    double raw[NQ];     // moment sums (with dV) of the cell's input
     Relax r1, r2;       // r1 applied first, r2 second
-    double c0, cA, cB;  // g = c0 h + cA * Phi_1 + cB * Phi_2 (cA, cB include P)
+    double c0, cA, cB;  // g = c0 h + cA e1 + cB e2 (cA, cB include a and P)
     int nr;
+    Tables t1, t2;
+    double s1[3][5], s2[3][5];
 };
 
 // Coefficients of the relaxations folded into one cell's entry, from that
-// cell's partial moment sums.  All threads of the workgroup take part.
-__device__ void cell_coefficients(const Args &A, const Inst &I, int gc, int mode, const double *partial, PrepShared &S,
-                                  bool want_sums)
+// cell's partial moment sums (A.nparts per cell).  Wave-uniform control flow.
+__device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, int gc, int mode,
+                                                  const double *partial, Coef &C, bool want_sums)
 {
     const Geo &g = A.g;
-    if (threadIdx.x < NQ) {
-        double s = 0.0;
-        for (int k = 0; k < A.vsplit; ++k) s += partial[((long long)gc * A.vsplit + k) * NQ + threadIdx.x];
-        S.raw[threadIdx.x] = s * g.dV;
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    double mine = 0.0;
+    if (lane < NQ)
+        for (int k = 0; k < A.nparts; ++k) mine += partial[((long long)gc * A.nparts + k) * NQ + lane];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) C.raw[q] = __shfl(mine, q, 64) * g.dV;
     double ta, tb;
-    const int nr = relax_times(I, mode, &ta, &tb);
-    if (threadIdx.x == 0) {
-        S.nr = nr;
-        S.c0 = 1.0; S.cA = 0.0; S.cB = 0.0;
-        if (nr >= 1) { moments_from_raw(S.raw, &S.r1); finish_relax(I, ta, &S.r1); }
-    }
-    __syncthreads();
-    if (nr >= 1) {
-        exp_tables(g, S.r1.V, S.r1.T, S.e1);
-        __syncthreads();
-        if (nr == 2 || want_sums) { table_sums(g, S.e1, S.s1); __syncthreads(); }
-        if (nr == 2) {
-            if (threadIdx.x == 0) {
-                double mp[5], m2[5];
-                maxwell_raw(S.r1.P, g.dV, S.s1, mp);
-                for (int q = 0; q < 5; ++q) m2[q] = S.r1.a * mp[q] + (1.0 - S.r1.a) * S.raw[q];
-                moments_from_raw(m2, &S.r2);
-                finish_relax(I, tb, &S.r2);
-            }
-            __syncthreads();
-            exp_tables(g, S.r2.V, S.r2.T, S.e2);
-            __syncthreads();
-            if (want_sums) { table_sums(g, S.e2, S.s2); __syncthreads(); }
-        }
-        if (threadIdx.x == 0) {
-            if (nr == 2) {
-                S.c0 = (1.0 - S.r1.a) * (1.0 - S.r2.a);
-                S.cA = S.r1.a * (1.0 - S.r2.a) * S.r1.P;
-                S.cB = S.r2.a * S.r2.P;
-            } else {
-                S.c0 = 1.0 - S.r1.a;
-                S.cA = S.r1.a * S.r1.P;
-            }
-        }
-        __syncthreads();
+    C.nr = relax_times(I, mode, &ta, &tb);
+    C.c0 = 1.0;
+    C.cA = C.cB = 0.0;
+    zero_tables(C.t1);
+    zero_tables(C.t2);
+    if (C.nr == 0) return;
+    moments_from_raw(C.raw, &C.r1);
+    finish_relax(I, ta, &C.r1);
+    lane_tables(g, C.r1.V, C.r1.T, C.t1);
+    if (C.nr == 2 || want_sums) wave_table_sums(g, C.t1, C.s1, want_sums);
+    if (C.nr == 2) {
+        double mp[5], m2[5];
+        maxwell_raw(C.r1.P, g.dV, C.s1, mp);
+        for (int q = 0; q < 5; ++q) m2[q] = C.r1.a * mp[q] + (1.0 - C.r1.a) * C.raw[q];
+        moments_from_raw(m2, &C.r2);
+        finish_relax(I, tb, &C.r2);
+        lane_tables(g, C.r2.V, C.r2.T, C.t2);
+        if (want_sums) wave_table_sums(g, C.t2, C.s2, true);
+        C.c0 = (1.0 - C.r1.a) * (1.0 - C.r2.a);
+        C.cA = C.r1.a * (1.0 - C.r2.a) * C.r1.P;
+        C.cB = C.r2.a * C.r2.P;
+    } else {
+        C.c0 = 1.0 - C.r1.a;
+        C.cA = C.r1.a * C.r1.P;
     }
 }
 
+// Write one entry: c0, TX1 = cA eA_x, TY1 = eA_y, TX2 = cB eB_x, TY2 = eB_y,
+// TZ = (eA_z, eB_z) interleaved.
 template <typename real>
-__device__ void write_entry(const Geo &g, real *E, double c0, double cA, const double *eA, double cB, const double *eB,
-                            bool hasA, bool hasB)
+__device__ __forceinline__ void write_entry(const Geo &g, real *E, double c0, double cA, const Tables &tA, double cB,
+                                            const Tables &tB)
 {
-    for (int t = threadIdx.x; t < g.pe; t += blockDim.x) {
-        double v = 0.0;
-        if (t == 0) v = c0;
-        else if (t >= g.tx1 && t < g.tx1 + g.nvx) v = hasA ? cA * eA[t - g.tx1] : 0.0;
-        else if (t >= g.ty1 && t < g.ty1 + g.nvy) v = hasA ? eA[NVMAX + t - g.ty1] : 0.0;
-        else if (t >= g.tx2 && t < g.tx2 + g.nvx) v = hasB ? cB * eB[t - g.tx2] : 0.0;
-        else if (t >= g.ty2 && t < g.ty2 + g.nvy) v = hasB ? eB[NVMAX + t - g.ty2] : 0.0;
-        else if (t >= g.tz && t < g.tz + 2 * g.nvz) {
-            const int k = (t - g.tz) >> 1;
-            if ((t - g.tz) & 1) v = hasB ? eB[2 * NVMAX + k] : 0.0;
-            else v = hasA ? eA[2 * NVMAX + k] : 0.0;
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) E[0] = (real)c0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = lane + 64 * q;
+        if (k < g.nvx) {
+            E[g.tx1 + k] = (real)(cA * tA.e[0][q]);
+            E[g.tx2 + k] = (real)(cB * tB.e[0][q]);
         }
-        E[t] = (real)v;
+        if (k < g.nvy) {
+            E[g.ty1 + k] = (real)tA.e[1][q];
+            E[g.ty2 + k] = (real)tB.e[1][q];
+        }
+        if (k < g.nvz) {
+            E[g.tz + 2 * k] = (real)tA.e[2][q];
+            E[g.tz + 2 * k + 1] = (real)tB.e[2][q];
+        }
     }
 }
 
@@ -372,19 +396,18 @@ __device__ __forceinline__ int wall_of_entry(const Inst &I, int k, int *pos)
     return 3;
 }
 
+// Table entry e (a cell, or a ghost source after the ncells cells), computed by
+// the calling wave from the partial moment sums of the streaming input.
 template <typename real>
-__global__ void __launch_bounds__(64) k_prep(Args A, const double *__restrict__ partial, real *__restrict__ params, int mode)
+__device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const double *partial, real *params)
 {
-    __shared__ PrepShared S;
-    __shared__ double ew[3 * NVMAX];
-    __shared__ double sw[3][5];
     const Geo &g = A.g;
-    const int e = blockIdx.x;
+    real *E = params + (long long)e * g.pe;
+    Coef C;
     if (e < A.ncells) {
         const int ii = find_inst(A.cell_prefix, A.ninst, e);
-        const Inst &I = A.inst[ii];
-        cell_coefficients(A, I, e, mode, partial, S, false);
-        write_entry<real>(g, params + (long long)e * g.pe, S.c0, S.cA, S.e1, S.cB, S.e2, S.nr >= 1, S.nr == 2);
+        cell_coefficients(A, A.inst[ii], e, mode, partial, C, false);
+        write_entry<real>(g, E, C.c0, C.cA, C.t1, C.cB, C.t2);
         return;
     }
     // ghost sources
@@ -392,46 +415,62 @@ __global__ void __launch_bounds__(64) k_prep(Args A, const double *__restrict__ 
     const int ii = find_inst(A.pseudo_prefix, A.ninst, pe);
     const Inst &I = A.inst[ii];
     const int k = pe - A.pseudo_prefix[ii];
-    real *E = params + (long long)e * g.pe;
+    Tables z;
+    zero_tables(z);
     if (I.kind == KIND_SHOCK) {
         // Far-field Maxwellian of Eq. (bc_shock): k = 0 upstream (x < x0), 1 downstream.
         const double *st = k == 0 ? I.up : I.dn;
         const double V[3] = {st[1], 0.0, 0.0};
-        exp_tables(g, V, st[2], S.e1);
-        __syncthreads();
-        write_entry<real>(g, E, 0.0, st[0] * pow(M_PI * st[2], -1.5), S.e1, 0.0, S.e2, true, false);
+        Tables t;
+        lane_tables(g, V, st[2], t);
+        write_entry<real>(g, E, 0.0, st[0] * pow(M_PI * st[2], -1.5), t, 0.0, z);
         return;
     }
     // Diffuse wall face, Eq. (bc_cavity): ghost = n_W Phi_W for velocities
     // leaving the wall.  n_W makes the discrete net mass flux zero:
     //   n_W = sum_{v.n<0} |v.n| g0 / sum_{v.n>0} v.n Phi_W,
-    // g0 being the wall-adjacent cell of the streaming input, g0 = c0 h + cA Phi_1 + cB Phi_2.
+    // g0 being the wall-adjacent cell of the streaming input, g0 = c0 h + cA e1 + cB e2.
     int pos;
     const int w = wall_of_entry(I, k, &pos);
     const int axis = w < 2 ? 0 : 1;
     const int adj = w == 0 ? pos * I.nx : w == 1 ? pos * I.nx + I.nx - 1 : w == 2 ? pos : (I.ny - 1) * I.nx + pos;
-    cell_coefficients(A, I, I.cell0 + adj, mode, partial, S, true);
+    cell_coefficients(A, I, I.cell0 + adj, mode, partial, C, true);
     const double VW[3] = {w == 3 ? I.uw : 0.0, 0.0, 0.0};
-    exp_tables(g, VW, I.tw, ew);
-    __syncthreads();
-    table_sums(g, ew, sw);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int b1 = axis == 0 ? 1 : 0;  // the two other components
-        const int b2 = 2;
-        // incident: v_axis < 0 for walls 0, 2 (index 3 of the sums), v_axis > 0 for walls 1, 3 (index 4)
-        const int in = (w == 0 || w == 2) ? 3 : 4, out = (w == 0 || w == 2) ? 4 : 3;
-        const double hraw = S.raw[5 + (w == 0 ? 0 : w == 1 ? 1 : w == 2 ? 2 : 3)];
-        double flux = S.c0 * hraw;
-        if (S.nr >= 1) flux += S.cA * g.dV * S.s1[axis][in] * S.s1[b1][0] * S.s1[b2][0];
-        if (S.nr == 2) flux += S.cB * g.dV * S.s2[axis][in] * S.s2[b1][0] * S.s2[b2][0];
-        const double pw = pow(M_PI * I.tw, -1.5);
-        const double den = pw * g.dV * sw[axis][out] * sw[b1][0] * sw[b2][0];
-        S.r2.n = flux / den;  // n_W (r2 is free here)
-        S.r2.P = S.r2.n * pw;
+    Tables tw;
+    lane_tables(g, VW, I.tw, tw);
+    double sw[3][5];
+    wave_table_sums(g, tw, sw, true);
+    const int b1 = axis == 0 ? 1 : 0, b2 = 2;  // the two other components
+    // incident: v_axis < 0 for walls 0, 2 (sum index 3), v_axis > 0 for walls 1, 3 (index 4)
+    const bool lowwall = (w == 0 || w == 2);
+    const double hin1 = axis == 0 ? (lowwall ? C.s1[0][3] : C.s1[0][4]) : (lowwall ? C.s1[1][3] : C.s1[1][4]);
+    const double hin2 = axis == 0 ? (lowwall ? C.s2[0][3] : C.s2[0][4]) : (lowwall ? C.s2[1][3] : C.s2[1][4]);
+    const double out_w = axis == 0 ? (lowwall ? sw[0][4] : sw[0][3]) : (lowwall ? sw[1][4] : sw[1][3]);
+    const double o1 = axis == 0 ? C.s1[1][0] : C.s1[0][0], o2 = axis == 0 ? C.s2[1][0] : C.s2[0][0];
+    const double ow = axis == 0 ? sw[1][0] : sw[0][0];
+    const double hraw = w == 0 ? C.raw[5] : w == 1 ? C.raw[6] : w == 2 ? C.raw[7] : C.raw[8];
+    double flux = C.c0 * hraw;
+    if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * C.s1[b2][0];
+    if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * C.s2[b2][0];
+    const double pw = pow(M_PI * I.tw, -1.5);
+    const double den = pw * g.dV * out_w * ow * sw[b2][0];
+    (void)b1;
+    write_entry<real>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
+}
+
+// Table preparation between streaming passes: one wave per entry.
+template <typename real>
+__global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__ partial, real *__restrict__ params,
+                                              int mode, int nentries, real *__restrict__ params_shock_copy)
+{
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= nentries) return;  // the whole wave leaves; no block barrier follows
+    prep_entry<real>(A, e, mode, partial, params);
+    // Far-field entries never change: give the other parity buffer a copy.
+    if (params_shock_copy && e >= A.ncells) {
+        const int ii = find_inst(A.pseudo_prefix, A.ninst, e - A.ncells);
+        if (A.inst[ii].kind == KIND_SHOCK) prep_entry<real>(A, e, mode, partial, params_shock_copy);
     }
-    __syncthreads();
-    write_entry<real>(g, E, 0.0, S.r2.P, ew, 0.0, S.e2, true, false);
 }
 
 // ---------------------------------------------------------------- stream
@@ -470,53 +509,87 @@ __device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int pos, i
     }
 }
 
-template <typename real>
-struct Tap {           // one stencil input for the current lane
-    const real *src;   // h at (slot cell, jz = 0, this p)
+template <typename T, int N>
+using vec_t = T __attribute__((ext_vector_type(N)));
+
+// Byte-offset load/store from a uniform base (SGPR base + 32-bit VGPR offset).
+template <typename V>
+__device__ __forceinline__ V ld(const void *base, uint32_t off)
+{
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// One stencil input for the current lane: VEC consecutive jx at one jy.
+template <typename real, int VEC>
+struct Tap {
+    using V = vec_t<real, VEC>;
+    uint32_t off;      // byte offset of h at (slot cell, jz = 0, first jx of the group)
     const real *tz;    // TZ of the slot entry (LDS)
-    real c0, l1, l2;
-    __device__ __forceinline__ real eval(int jz, long long zoff) const
+    real c0;
+    V l1, l2;
+    __device__ __forceinline__ V load(const real *base, uint32_t zoff) const { return ld<V>(base, off + zoff); }
+    __device__ __forceinline__ V relax(V h, int jz) const
     {
-        const real h = src[zoff];
         const real a = tz[2 * jz], b = tz[2 * jz + 1];
         return c0 * h + (l1 * a + l2 * b);
     }
 };
 
-template <typename real>
-__device__ __forceinline__ Tap<real> make_tap(const Geo &g, const real *sp, const SlotInfo &SI, int slot, const real *base,
-                                              int p, int jx, int jy)
+template <typename real, int VEC>
+__device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp, const SlotInfo &SI, int slot, int p0,
+                                                   int jx0, int jy)
 {
-    Tap<real> t;
+    Tap<real, VEC> t;
     const real *E = sp + slot * g.pe;
-    t.src = base + (long long)SI.cell[slot] * g.nv + p;
+    t.off = (uint32_t)(((long long)SI.cell[slot] * g.nv + p0) * sizeof(real));
     t.tz = E + g.tz;
     t.c0 = E[0];
-    t.l1 = E[g.tx1 + jx] * E[g.ty1 + jy];
-    t.l2 = E[g.tx2 + jx] * E[g.ty2 + jy];
+    const real y1 = E[g.ty1 + jy], y2 = E[g.ty2 + jy];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        t.l1[k] = E[g.tx1 + jx0 + k] * y1;
+        t.l2[k] = E[g.tx2 + jx0 + k] * y2;
+    }
     return t;
 }
 
 // Upwind flux difference along one direction, values in upwind order
-// (u_{-2}, u_{-1}, u_0, u_1) for Courant magnitude C and slope factor k = (1 - C)/2.
-template <typename real>
-__device__ __forceinline__ real flux_diff(real um2, real um1, real u0, real u1, real C, real k)
+// (u_{-2}, u_{-1}, u_0, u_1), Courant magnitudes C and slope factors k = (1 - C)/2.
+template <typename real, int VEC>
+__device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_t<real, VEC> um1, vec_t<real, VEC> u0,
+                                                      vec_t<real, VEC> u1, vec_t<real, VEC> C, vec_t<real, VEC> k)
 {
-    const real fp = u0 + k * minmod3(u1 - u0, u0 - um1);
-    const real fm = um1 + k * minmod3(u0 - um1, um1 - um2);
-    return C * (fp - fm);
+    vec_t<real, VEC> r;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const real fp = u0[e] + k[e] * minmod3(u1[e] - u0[e], u0[e] - um1[e]);
+        const real fm = um1[e] + k[e] * minmod3(u0[e] - um1[e], um1[e] - um2[e]);
+        r[e] = C[e] * (fp - fm);
+    }
+    return r;
 }
 
-template <typename real, int DIM>
-__global__ void __launch_bounds__(256) k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst,
-                                                const real *__restrict__ params, double *__restrict__ partial)
+// Lane tasks.  A task is (group of VEC consecutive jx at one jy, residue zr of
+// jz modulo ZR); it loops over jz = z0 + zr, z0 + zr + ZR, ... < z1.  The host
+// picks VEC so that all v_x of a group share a sign, and ZR so that the task
+// count fills whole waves.
+template <typename real, int DIM, int VEC, int UNR>
+__global__ void __launch_bounds__(256)
+    k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
+             double *__restrict__ partial)
 {
+    using V = vec_t<real, VEC>;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NSLOT = DIM == 1 ? 7 : 13;
     real *sp = reinterpret_cast<real *>(smem);
     __shared__ SlotInfo SI;
     const Geo &g = A.g;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    // Work items (cell, jz chunk).  A grid smaller than the item count makes
+    // the kernel persistent: each workgroup walks items gridDim.x apart (a
+    // multiple of 8 keeps every workgroup on one XCD's contiguous range).
+    const int nitems = A.ncells * A.vsplit;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int L = xcd_remap(item, nitems);
     const int gc = L / A.vsplit, split = L % A.vsplit;
     const int ii = find_inst(A.cell_prefix, A.ninst, gc);
     const Inst &I = A.inst[ii];
@@ -544,47 +617,103 @@ __global__ void __launch_bounds__(256) k_stream(Args A, const real *__restrict__
     __syncthreads();
 
     const real *base = src + I.f0;
-    real *out = dst + I.f0 + (long long)c * g.nv;
+    real *outb = dst + I.f0;
+    const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     const bool lim = I.minmod != 0;
+    const int ngx = g.nvx / VEC, ngroups = ngx * g.nvy, ntask = ngroups * A.zr;
+    const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-    for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
-        const int jx = p % g.nvx, jy = p / g.nvx;
-        const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
-        const int sx = vx > 0.0 ? 0 : 1;
-        const real Cx = (real)(fabs(vx) * I.cx);
-        const real kx = lim ? (real)0.5 * ((real)1 - Cx) : (real)0;
-        const Tap<real> tc = make_tap<real>(g, sp, SI, 0, base, p, jx, jy);
-        const Tap<real> xa = make_tap<real>(g, sp, SI, 1 + 3 * sx + 0, base, p, jx, jy);
-        const Tap<real> xb = make_tap<real>(g, sp, SI, 1 + 3 * sx + 1, base, p, jx, jy);
-        const Tap<real> xd = make_tap<real>(g, sp, SI, 1 + 3 * sx + 2, base, p, jx, jy);
-        Tap<real> ya, yb, yd;
-        real Cy = 0, ky = 0;
+    for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const int pg = task % ngroups, zr = task / ngroups;
+        const int jy = pg / ngx, jx0 = (pg - jy * ngx) * VEC;
+        const int p0 = jy * g.nvx + jx0;
+        V Cx, kx;
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            Cx[k] = (real)(fabs(vnode(g, 0, jx0 + k)) * I.cx);
+            kx[k] = lim ? (real)0.5 * ((real)1 - Cx[k]) : (real)0;
+        }
+        const double vy = vnode(g, 1, jy);
+        const int sx = vnode(g, 0, jx0) > 0.0 ? 0 : 1;
+        const Tap<real, VEC> tc = make_tap<real, VEC>(g, sp, SI, 0, p0, jx0, jy);
+        const Tap<real, VEC> xa = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 0, p0, jx0, jy);
+        const Tap<real, VEC> xb = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 1, p0, jx0, jy);
+        const Tap<real, VEC> xd = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 2, p0, jx0, jy);
+        Tap<real, VEC> ya, yb, yd;
+        V Cy = 0, ky = 0;
         if constexpr (DIM == 2) {
             const int sy = vy > 0.0 ? 0 : 1;
-            Cy = (real)(fabs(vy) * I.cy);
-            ky = lim ? (real)0.5 * ((real)1 - Cy) : (real)0;
-            ya = make_tap<real>(g, sp, SI, 7 + 3 * sy + 0, base, p, jx, jy);
-            yb = make_tap<real>(g, sp, SI, 7 + 3 * sy + 1, base, p, jx, jy);
-            yd = make_tap<real>(g, sp, SI, 7 + 3 * sy + 2, base, p, jx, jy);
+            const real cy = (real)(fabs(vy) * I.cy);
+            Cy = cy;
+            ky = lim ? (real)0.5 * ((real)1 - cy) : (real)0;
+            ya = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 0, p0, jx0, jy);
+            yb = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 1, p0, jx0, jy);
+            yd = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 2, p0, jx0, jy);
         }
-        double A0 = 0, Az = 0, Azz = 0;
-        for (int jz = z0; jz < z1; ++jz) {
-            const long long zo = (long long)jz * g.npl;
-            const real u0 = tc.eval(jz, zo);
-            real r = u0 - flux_diff<real>(xa.eval(jz, zo), xb.eval(jz, zo), u0, xd.eval(jz, zo), Cx, kx);
+        double A0[VEC];
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) A0[k] = 0.0;
+        double Az = 0.0, Azz = 0.0;
+        constexpr int NT = DIM == 1 ? 4 : 7;
+        const Tap<real, VEC> *taps[7] = {&tc, &xa, &xb, &xd, &ya, &yb, &yd};
+        // One jz: relax the loaded taps, stream, store, accumulate moments.
+        auto finish = [&](const V (&hv)[NT], int jz) {
+            const uint32_t zo = (uint32_t)jz * zstep;
+            const V u0 = tc.relax(hv[0], jz);
+            V r = u0 - flux_diff<real, VEC>(xa.relax(hv[1], jz), xb.relax(hv[2], jz), u0, xd.relax(hv[3], jz), Cx, kx);
             if constexpr (DIM == 2)
-                r -= flux_diff<real>(ya.eval(jz, zo), yb.eval(jz, zo), u0, yd.eval(jz, zo), Cy, ky);
-            out[zo + p] = r;
-            const double hd = (double)r, vz = vnode(g, 2, jz);
-            A0 += hd;
-            Az += vz * hd;
-            Azz += vz * vz * hd;
+                r -= flux_diff<real, VEC>(ya.relax(hv[4], jz), yb.relax(hv[5], jz), u0, yd.relax(hv[6], jz), Cy, ky);
+            __builtin_nontemporal_store(r, reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo +
+                                                                  (uint32_t)(p0 * sizeof(real))));
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const double hk = (double)r[k];
+                A0[k] += hk;
+                s += hk;
+            }
+            const double vz = vnode(g, 2, jz);
+            Az += vz * s;
+            Azz += vz * vz * s;
+        };
+        // Software pipeline: the loads of the next UNR jz values are issued
+        // before the current ones are relaxed and streamed, so every wave keeps
+        // one group of loads in flight while it computes.
+        const int zs = UNR * A.zr;
+        int jz = z0 + zr;
+        if (jz < z1) {
+            const int zlast = z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);  // last jz of this lane's residue
+            V hv[UNR][NT];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    hv[u][t] = taps[t]->load(base, (uint32_t)min(jz + u * A.zr, zlast) * zstep);
+            for (; jz < z1; jz += zs) {
+                V hn[UNR][NT];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        hn[u][t] = taps[t]->load(base, (uint32_t)min(jz + zs + u * A.zr, zlast) * zstep);
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    if (jz + u * A.zr < z1) finish(hv[u], jz + u * A.zr);
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) hv[u][t] = hn[u][t];
+            }
         }
-        fold_column(acc, vx, vy, A0, Az, Azz);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            fold_column(acc, vnode(g, 0, jx0 + k), vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
     }
     block_sum_store<NQ>(acc, partial + (long long)L * NQ);
+    __syncthreads();  // LDS (slots, tables, reduction) is reused by the next item
+    }
 }
 
 // ---------------------------------------------------------------- final

@@ -1,0 +1,45 @@
+"""Autotune the streaming kernel for the standard workloads on this GPU and
+record the shapes in tuned.json (read by binding.Context(tune="table")).
+
+    python -m paper_0903_4044_amd.tune
+"""
+from __future__ import annotations
+
+import json
+import sys
+
+import torch
+
+from . import binding, inputs
+
+
+def workloads():
+    yield "shock_m1.5_fp64", [inputs.config("shock_m1.5_fp64")], "fp64"
+    yield "shock_m3_fp32", [inputs.config("shock_m3_fp32")], "fp32"
+    yield "cavity_128_fp32", [inputs.config("cavity_128_fp32")], "fp32"
+    yield "cavity_128_fp64", [inputs.config("cavity_128_fp32")], "fp64"
+    yield "cavity_64_fp32", [inputs.config("cavity_64_adjoint")], "fp32"
+    yield "batch_64_fp32", inputs.batch_cavities(), "fp32"
+
+
+def main() -> int:
+    torch.cuda.set_device(0)
+    table = binding.load_tuned()
+    for name, probs, prec in workloads():
+        ctx = binding.Context(probs, prec, tune="off")
+        f = ctx.initial_state()
+        torch.cuda.synchronize()
+        shape = ctx.autotune(f)
+        table[ctx.key] = {k: shape[k] for k in ("vec", "unroll", "vsplit", "persist")} | {"us": round(shape["tuned_us"], 2),
+                                                                                "workload": name}
+        print(f"{name}: {ctx.key} -> {table[ctx.key]}", flush=True)
+        del f
+        ctx.close()
+        torch.cuda.empty_cache()
+    with open(binding.TUNED_PATH, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -34,6 +34,13 @@ def test_header_symbols_exported(B):
     assert set(names) <= set(B.EXPORTS) | {"bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad"}
 
 
+def test_size_class_keys(B):
+    k1 = B.size_class([inputs.config("shock_m3_fp32")], "fp32")
+    assert k1 == "1d/fp32/nv48x48x48/cells<=1024"
+    k4 = B.size_class(inputs.batch_cavities(), "fp32")
+    assert k4.startswith("2d/fp32/nv24x24x24/cells<=")
+
+
 def init_code(B, cfg, precision=0):
     arr = (B.Problem * 1)(B.to_struct(cfg))
     h = ctypes.c_void_p()

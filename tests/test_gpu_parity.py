@@ -139,7 +139,17 @@ def test_batched_matches_single_and_oracle(B, oracle_mod):
         yi = C.instance_view(y, i)
         check_fp64(yi, O.step(f0s[i], 5), O, c)
         Ci = B.Context(c, "fp64")
-        assert torch.equal(Ci.step(to_dev(f0s[i], torch.float64), n=5).view_as(yi), yi)
+        shape = {k: v for k, v in C.launch().items() if k != "tuned_us"}
+        try:
+            Ci.set_launch(**shape)
+            same = True
+        except B.BGKError:  # the shape's jz chunking is not available to the smaller context
+            same = False
+        yi1 = Ci.step(to_dev(f0s[i], torch.float64), n=5).view_as(yi)
+        if same:
+            assert torch.equal(yi1, yi)
+        else:
+            check_fp64(yi1, yi.cpu().numpy(), O, c)
 
 
 # --------------------------------------------------------------- full size
@@ -217,3 +227,66 @@ def test_check_flags_nonfinite_and_negative(B):
     z = x.clone()
     z[2 * C.nvel:3 * C.nvel] *= -1.0
     assert C.check(z) == B.E_NEGATIVE
+
+
+# --------------------------------------------------------------- launch shapes
+
+
+def test_autotune_keeps_parity(B, oracle_mod):
+    cfg = small("cavity", nx=6, ny=5, nv=(16, 16, 8))
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp64", tune="off")
+    f0 = perturbed_initial(O, seed=61)
+    x = to_dev(f0, torch.float64)
+    shape = C.autotune(x)
+    assert shape["tuned_us"] > 0
+    check_fp64(C.step(x, n=5), O.step(f0, 5), O, cfg)
+
+
+@pytest.mark.parametrize("kind", ["shock", "cavity"])
+def test_every_shape_matches_oracle(B, oracle_mod, kind):
+    """Each launch shape (vector width, pipeline depth, jz chunks, persistent
+    grid) computes the same step to rounding."""
+    cfg = small(kind, nv=(16, 16, 8), nx=7, ny=6)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed_initial(O, seed=62)
+    ref = O.step(f0, 3)
+    for prec, tol in (("fp64", 1e-12), ("fp32", None)):
+        C = B.Context(cfg, prec, tune="off")
+        x = to_dev(f0, C.dtype)
+        for vec in (1, 2, 4):
+            for unroll in (1, 2):
+                for vsplit in (1, 3):
+                    for persist in (0, 1):
+                        try:
+                            C.set_launch(vec, unroll, vsplit, persist)
+                        except B.BGKError:
+                            continue
+                        y = C.step(x, n=3)
+                        if tol:
+                            check_fp64(y, ref, O, cfg, tol)
+                        else:
+                            e = moment_errors(C.moments(y).cpu().numpy(), O.moments(ref), cfg)
+                            assert max(e) <= 1e-5, (vec, unroll, vsplit, persist, e)
+
+
+def test_graph_replay_matches_eager(B):
+    """Graph replay of the steady two-step sequence gives the eager result bit
+    for bit, on repeated calls with eager work and syncs in between."""
+    cfg = small("cavity", nx=8, ny=6, nv=(16, 16, 8))
+    C = B.Context(cfg, "fp32")
+    x = C.initial_state()
+    torch.cuda.synchronize()
+    ref = {n: C.step(x, n=n).clone() for n in (5, 6, 9)}
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        C.set_graph(True)
+        out = torch.empty_like(x)
+        for rep in range(3):
+            for n in (5, 6, 9):
+                C.step(x, out, n=n)
+                side.synchronize()
+                assert torch.equal(out, ref[n]), (rep, n)
+                C.moments(out)  # eager work between replays
+        C.set_graph(False)
+    torch.cuda.synchronize()
