@@ -80,6 +80,10 @@ def lib():
         L.orc_totals.argtypes = [P, dp, dp]
         L.orc_lid_shear.argtypes = [P, dp]
         L.orc_lid_shear.restype = ctypes.c_double
+        L.orc_relax_adjoint.argtypes = [P, dp, dp, dp, ctypes.c_double, dp]
+        L.orc_stream_adjoint.argtypes = [P, dp, dp, dp, ctypes.c_double, dp]
+        L.orc_step_adjoint.argtypes = [P, dp, dp, dp, dp]
+        L.orc_lid_shear_grad.argtypes = [P, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -195,6 +199,49 @@ class Oracle:
     def lid_shear(self, f) -> float:
         f = self._f(f)
         return self.L.orc_lid_shear(ctypes.byref(self.p), _ptr(f))
+
+    # -- reverse sweep (hand-derived adjoint) -----------------------------
+    def relax_adjoint(self, x, mu, tau):
+        """(dR_tau/dx)^T mu at x, and dL/dKn."""
+        x, mu = self._f(x), self._f(mu)
+        out, g = np.empty(self.shape), np.zeros(1)
+        self.L.orc_relax_adjoint(ctypes.byref(self.p), _ptr(x), _ptr(mu), _ptr(out), float(tau), _ptr(g))
+        return out, float(g[0])
+
+    def stream_adjoint(self, g_in, mu, dt=None):
+        """(dS/dg)^T mu at g_in, and dL/dT_w."""
+        g_in, mu = self._f(g_in), self._f(mu)
+        out, gt = np.empty(self.shape), np.zeros(1)
+        self.L.orc_stream_adjoint(ctypes.byref(self.p), _ptr(g_in), _ptr(mu), _ptr(out),
+                                  float(self.dt if dt is None else dt), _ptr(gt))
+        return out, float(gt[0])
+
+    def step_adjoint(self, f, lam_next):
+        """lam_n = (d step/df)^T lam_next and (dL/dKn, dL/dT_w) of this step."""
+        f, lam_next = self._f(f), self._f(lam_next)
+        out, grad = np.empty(self.shape), np.zeros(2)
+        self.L.orc_step_adjoint(ctypes.byref(self.p), _ptr(f), _ptr(lam_next), _ptr(out), _ptr(grad))
+        return out, grad
+
+    def lid_shear_grad(self, f):
+        """dL/df of the lid shear and its explicit (dL/dKn, dL/dT_w)."""
+        f = self._f(f)
+        lam, grad = np.empty(self.shape), np.zeros(2)
+        self.L.orc_lid_shear_grad(ctypes.byref(self.p), _ptr(f), _ptr(lam), _ptr(grad))
+        return lam, grad
+
+    def rollout_gradient(self, f0, nsteps):
+        """Loss = lid shear of f^nsteps; returns (L, dL/df0, dL/dKn, dL/dT_w)
+        by storing every state and sweeping back."""
+        states = [self._f(f0).copy()]
+        for _ in range(nsteps):
+            states.append(self.step(states[-1]))
+        L = self.lid_shear(states[-1])
+        lam, grad = self.lid_shear_grad(states[-1])
+        for n in range(nsteps - 1, -1, -1):
+            lam, gs = self.step_adjoint(states[n], lam)
+            grad = grad + gs
+        return L, lam, grad[0], grad[1]
 
     @staticmethod
     def rankine_hugoniot(mach):

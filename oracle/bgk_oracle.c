@@ -527,3 +527,344 @@ double orc_lid_shear(const orc_problem *p, const double *f)
     free_velgrid(&g);
     return L;
 }
+
+/* ================================================================ adjoint
+ *
+ * Reverse sweep of the discrete map above, derived by hand.  For a scalar
+ * loss L of f^N the adjoint state lambda^n = dL/df^n obeys
+ *     lambda^n = (d f^{n+1} / d f^n)^T lambda^{n+1},
+ * with the plain sum over all (cell, velocity) entries as inner product.
+ * Parameter gradients (Kn and the wall temperature T_w) accumulate the
+ * partial derivatives of every sub-step.  The minmod slope is differentiated
+ * on the branch the forward step takes (zero where the two differences
+ * disagree in sign, else the difference of smaller magnitude, the second one
+ * on a tie).
+ */
+
+/* Relaxation R_tau (Eq. relaxation) of one cell, y = (1 - E) Phi + E x with
+ * E = exp(-nu tau), Phi and nu from the moments of x.  Given mu = dL/dy,
+ * writes xbar = (dy/dx)^T mu and adds dL/dKn to *gkn. */
+static void relax_adjoint_cell(const orc_problem *p, const velgrid *g, double dV, const double *x,
+                               const double *mu, double tau, double *xbar, double *gkn, double *phi)
+{
+    double n, V[3], T;
+    cell_moments(g, dV, x, &n, V, &T);
+    maxwellian_on(g, n, V, T, phi);
+    const double nu = orc_collision_frequency(p, n, T), E = exp(-nu * tau);
+    double A = 0, B[3] = {0, 0, 0}, C = 0, D = 0;
+    for (long j = 0; j < g->nv; ++j) {
+        const double c[3] = {g->vx[j] - V[0], g->vy[j] - V[1], g->vz[j] - V[2]};
+        const double w = mu[j] * phi[j];
+        A += w;
+        for (int a = 0; a < 3; ++a) B[a] += w * c[a];
+        C += w * (c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        D += mu[j] * (x[j] - phi[j]);
+    }
+    /* adjoints of n, V, T:  dPhi/dn = Phi/n, dPhi/dV = 2 Phi (v - V)/T,
+     * dPhi/dT = Phi (|v - V|^2/T^2 - 3/(2T)), dE/dn = -tau E nu/n,
+     * dE/dT = -tau E (1 - omega) nu/T, and dy/dE = x - Phi. */
+    const double Gn = (1.0 - E) * A / n - tau * E * nu / n * D;
+    double GV[3];
+    for (int a = 0; a < 3; ++a) GV[a] = (1.0 - E) * 2.0 * B[a] / T;
+    const double GT = (1.0 - E) * (C / (T * T) - 1.5 * A / T) - tau * E * (1.0 - p->omega) * nu / T * D;
+    *gkn += tau * E * nu / p->kn * D;  /* dE/dKn = tau E nu / Kn */
+    /* chain to the raw sums M0 = n, M1 = n V, M2 = n (|V|^2 + 3T/2), whose
+     * derivatives with respect to x_k are dV (1, v_k, |v_k|^2) */
+    const double V2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    double G0 = Gn + GT * (2.0 / 3.0) * (V2 - 1.5 * T) / n;
+    double G1[3];
+    for (int a = 0; a < 3; ++a) {
+        G0 -= GV[a] * V[a] / n;
+        G1[a] = GV[a] / n - GT * (4.0 / 3.0) * V[a] / n;
+    }
+    const double G2 = GT * (2.0 / 3.0) / n;
+    for (long j = 0; j < g->nv; ++j)
+        xbar[j] = E * mu[j] + dV * (G0 + G1[0] * g->vx[j] + G1[1] * g->vy[j] + G1[2] * g->vz[j] +
+                                    G2 * (g->vx[j] * g->vx[j] + g->vy[j] * g->vy[j] + g->vz[j] * g->vz[j]));
+}
+
+void orc_relax_adjoint(const orc_problem *p, const double *x, const double *mu, double *xbar, double tau, double *gkn)
+{
+    velgrid g = make_velgrid(p);
+    const long nc = ncell(p), nv = nvel(p);
+    const double dV = dvol(p);
+    double total = 0.0;
+#pragma omp parallel reduction(+ : total)
+    {
+        double *phi = malloc(sizeof(double) * nv);
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            double gk = 0.0;
+            relax_adjoint_cell(p, &g, dV, x + c * nv, mu + c * nv, tau, xbar + c * nv, &gk, phi);
+            total += gk;
+        }
+        free(phi);
+    }
+    *gkn += total;
+    free_velgrid(&g);
+}
+
+/* Branch the minmod of (a, b) takes: 0 (slope zero), 1 (a), 2 (b). */
+static int minmod_branch(double a, double b)
+{
+    if (a * b <= 0.0) return 0;
+    return fabs(a) < fabs(b) ? 1 : 2;
+}
+
+/* Adjoint of one face value (see face_value) for Courant number C: the
+ * face depends on (um1, u0, u1, u2) = padded cells (m-1, m, m+1, m+2); w is
+ * the adjoint of the face value, accumulated into the padded adjoint. */
+static void face_adjoint(double *Gb_m1, double *Gb_0, double *Gb_1, double *Gb_2, double um1, double u0, double u1,
+                         double u2, double C, int limit, double w)
+{
+    if (C > 0.0) {
+        *Gb_0 += w;
+        if (!limit) return;
+        const double s = 0.5 * (1.0 - C) * w;
+        const int br = minmod_branch(u1 - u0, u0 - um1);
+        if (br == 1) { *Gb_1 += s; *Gb_0 -= s; }
+        else if (br == 2) { *Gb_0 += s; *Gb_m1 -= s; }
+    } else if (C < 0.0) {
+        *Gb_1 += w;
+        if (!limit) return;
+        const double s = -0.5 * (1.0 + C) * w;
+        const int br = minmod_branch(u2 - u1, u1 - u0);
+        if (br == 1) { *Gb_2 += s; *Gb_1 -= s; }
+        else if (br == 2) { *Gb_1 += s; *Gb_0 -= s; }
+    }
+}
+
+/* Adjoint of orc_stream at input gs: given mu = dL/d(out), writes
+ * gbar = dL/dgs and adds dL/dT_w (through the wall Maxwellian and n_W) to
+ * *gtw.  Scatter form over a padded adjoint array, then the transpose of the
+ * ghost construction. */
+void orc_stream_adjoint(const orc_problem *p, const double *gs, const double *mu, double *gbar, double dt, double *gtw)
+{
+    velgrid g = make_velgrid(p);
+    const int two = is2d(p);
+    const int nx = p->nx, ny = two ? p->ny : 1;
+    const long nv = nvel(p);
+    const int px = nx + 4, py = two ? ny + 4 : 1, oy = two ? 2 : 0;
+    const long npad = (long)px * py * nv;
+    double *G = malloc(sizeof(double) * npad);
+    double *Gb = calloc(npad, sizeof(double));
+#define PAD(A, ix, iy) ((A) + ((long)((iy) + oy) * px + (ix) + 2) * nv)
+#define SRC(ix, iy) (gs + ((long)(iy) * nx + (ix)) * nv)
+    /* forward padded input, built exactly as in orc_stream */
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) memcpy(PAD(G, ix, iy), SRC(ix, iy), sizeof(double) * nv);
+    double *rest = malloc(sizeof(double) * nv), *lid = malloc(sizeof(double) * nv);
+    const int Lw = nx > ny ? nx : ny;
+    double *nW_store = malloc(sizeof(double) * 4 * Lw);
+    if (p->kind == ORC_SHOCK) {
+        double up[3], dn[3];
+        orc_rankine_hugoniot(p->mach, up, dn);
+        double Vu[3] = {up[1], 0, 0}, Vd[3] = {dn[1], 0, 0};
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(G, -2, 0));
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(G, -1, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(G, nx, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(G, nx + 1, 0));
+    } else if (p->kind == ORC_PERIODIC1 || p->kind == ORC_PERIODIC2) {
+        for (int iy = 0; iy < ny; ++iy) {
+            memcpy(PAD(G, -2, iy), SRC(nx - 2, iy), sizeof(double) * nv);
+            memcpy(PAD(G, -1, iy), SRC(nx - 1, iy), sizeof(double) * nv);
+            memcpy(PAD(G, nx, iy), SRC(0, iy), sizeof(double) * nv);
+            memcpy(PAD(G, nx + 1, iy), SRC(1, iy), sizeof(double) * nv);
+        }
+        if (two)
+            for (int ix = 0; ix < nx; ++ix) {
+                memcpy(PAD(G, ix, -2), SRC(ix, ny - 2), sizeof(double) * nv);
+                memcpy(PAD(G, ix, -1), SRC(ix, ny - 1), sizeof(double) * nv);
+                memcpy(PAD(G, ix, ny), SRC(ix, 0), sizeof(double) * nv);
+                memcpy(PAD(G, ix, ny + 1), SRC(ix, 1), sizeof(double) * nv);
+            }
+    } else {
+        wall_maxwellian(p, &g, 0.0, rest);
+        wall_maxwellian(p, &g, lid_speed(p), lid);
+        for (int w = 0; w < 4; ++w) {
+            int axis; double sign;
+            wall_normal(w, &axis, &sign);
+            const double *va = axis == 0 ? g.vx : g.vy;
+            const double *phiw = w == 3 ? lid : rest;
+            int len = axis == 0 ? ny : nx;
+            for (int k = 0; k < len; ++k) {
+                int ax, ay, gx1, gy1, gx2, gy2;
+                if (w == 0) { ax = 0; ay = k; gx1 = -1; gx2 = -2; gy1 = gy2 = k; }
+                else if (w == 1) { ax = nx - 1; ay = k; gx1 = nx; gx2 = nx + 1; gy1 = gy2 = k; }
+                else if (w == 2) { ax = k; ay = 0; gy1 = -1; gy2 = -2; gx1 = gx2 = k; }
+                else { ax = k; ay = ny - 1; gy1 = ny; gy2 = ny + 1; gx1 = gx2 = k; }
+                const double *g0 = SRC(ax, ay);
+                double nW = wall_density(&g, axis, sign, g0, phiw);
+                nW_store[w * Lw + k] = nW;
+                double *d1 = PAD(G, gx1, gy1), *d2 = PAD(G, gx2, gy2);
+                for (long j = 0; j < nv; ++j) {
+                    double v = sign * va[j] > 0.0 ? nW * phiw[j] : g0[j];
+                    d1[j] = v;
+                    d2[j] = v;
+                }
+            }
+        }
+    }
+
+    /* transpose of the stencil: out_i = G_i - C (face_{i+1/2} - face_{i-1/2}) */
+    const double dx = dxs(p), dy = two ? dys(p) : 1.0;
+    const int limit = p->minmod;
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) {
+            const double *m = mu + ((long)iy * nx + ix) * nv;
+            for (long j = 0; j < nv; ++j) {
+                PAD(Gb, ix, iy)[j] += m[j];
+                const double Cx = g.vx[j] * dt / dx;
+                /* face i+1/2 from padded (ix-1, ix, ix+1, ix+2), face i-1/2 from (ix-2 .. ix+1) */
+                face_adjoint(&PAD(Gb, ix - 1, iy)[j], &PAD(Gb, ix, iy)[j], &PAD(Gb, ix + 1, iy)[j],
+                             &PAD(Gb, ix + 2, iy)[j], PAD(G, ix - 1, iy)[j], PAD(G, ix, iy)[j], PAD(G, ix + 1, iy)[j],
+                             PAD(G, ix + 2, iy)[j], Cx, limit, -Cx * m[j]);
+                face_adjoint(&PAD(Gb, ix - 2, iy)[j], &PAD(Gb, ix - 1, iy)[j], &PAD(Gb, ix, iy)[j],
+                             &PAD(Gb, ix + 1, iy)[j], PAD(G, ix - 2, iy)[j], PAD(G, ix - 1, iy)[j], PAD(G, ix, iy)[j],
+                             PAD(G, ix + 1, iy)[j], Cx, limit, Cx * m[j]);
+                if (two) {
+                    const double Cy = g.vy[j] * dt / dy;
+                    face_adjoint(&PAD(Gb, ix, iy - 1)[j], &PAD(Gb, ix, iy)[j], &PAD(Gb, ix, iy + 1)[j],
+                                 &PAD(Gb, ix, iy + 2)[j], PAD(G, ix, iy - 1)[j], PAD(G, ix, iy)[j],
+                                 PAD(G, ix, iy + 1)[j], PAD(G, ix, iy + 2)[j], Cy, limit, -Cy * m[j]);
+                    face_adjoint(&PAD(Gb, ix, iy - 2)[j], &PAD(Gb, ix, iy - 1)[j], &PAD(Gb, ix, iy)[j],
+                                 &PAD(Gb, ix, iy + 1)[j], PAD(G, ix, iy - 2)[j], PAD(G, ix, iy - 1)[j],
+                                 PAD(G, ix, iy)[j], PAD(G, ix, iy + 1)[j], Cy, limit, Cy * m[j]);
+                }
+            }
+        }
+
+    /* interior adjoint */
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) memcpy(gbar + ((long)iy * nx + ix) * nv, PAD(Gb, ix, iy), sizeof(double) * nv);
+    /* transpose of the ghost construction */
+    if (p->kind == ORC_PERIODIC1 || p->kind == ORC_PERIODIC2) {
+        for (int iy = 0; iy < ny; ++iy)
+            for (long j = 0; j < nv; ++j) {
+                gbar[((long)iy * nx + nx - 2) * nv + j] += PAD(Gb, -2, iy)[j];
+                gbar[((long)iy * nx + nx - 1) * nv + j] += PAD(Gb, -1, iy)[j];
+                gbar[((long)iy * nx + 0) * nv + j] += PAD(Gb, nx, iy)[j];
+                gbar[((long)iy * nx + 1) * nv + j] += PAD(Gb, nx + 1, iy)[j];
+            }
+        if (two)
+            for (int ix = 0; ix < nx; ++ix)
+                for (long j = 0; j < nv; ++j) {
+                    gbar[((long)(ny - 2) * nx + ix) * nv + j] += PAD(Gb, ix, -2)[j];
+                    gbar[((long)(ny - 1) * nx + ix) * nv + j] += PAD(Gb, ix, -1)[j];
+                    gbar[((long)0 * nx + ix) * nv + j] += PAD(Gb, ix, ny)[j];
+                    gbar[((long)1 * nx + ix) * nv + j] += PAD(Gb, ix, ny + 1)[j];
+                }
+    } else if (p->kind == ORC_CAVITY) {
+        /* ghost(j) = g0(j) for incident j; n_W Phi_W(j) for emitted j, with
+         * n_W = sum_inc |v.n| g0 / D_W, D_W = sum_em (v.n) Phi_W(T_w). */
+        for (int w = 0; w < 4; ++w) {
+            int axis; double sign;
+            wall_normal(w, &axis, &sign);
+            const double *va = axis == 0 ? g.vx : g.vy;
+            const double *phiw = w == 3 ? lid : rest;
+            const double uw = w == 3 ? lid_speed(p) : 0.0;
+            const double Tw = p->t_wall;
+            double D = 0.0, Dp = 0.0;
+            for (long j = 0; j < nv; ++j) {
+                const double vn = sign * va[j];
+                if (vn > 0.0) {
+                    const double c2 = (g.vx[j] - uw) * (g.vx[j] - uw) + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j];
+                    D += vn * phiw[j];
+                    Dp += vn * phiw[j] * (c2 / (Tw * Tw) - 1.5 / Tw);
+                }
+            }
+            int len = axis == 0 ? ny : nx;
+            for (int k = 0; k < len; ++k) {
+                int ax, ay, gx1, gy1, gx2, gy2;
+                if (w == 0) { ax = 0; ay = k; gx1 = -1; gx2 = -2; gy1 = gy2 = k; }
+                else if (w == 1) { ax = nx - 1; ay = k; gx1 = nx; gx2 = nx + 1; gy1 = gy2 = k; }
+                else if (w == 2) { ax = k; ay = 0; gy1 = -1; gy2 = -2; gx1 = gx2 = k; }
+                else { ax = k; ay = ny - 1; gy1 = ny; gy2 = ny + 1; gx1 = gx2 = k; }
+                const double nW = nW_store[w * Lw + k];
+                double *gb0 = gbar + ((long)ay * nx + ax) * nv;
+                const double *b1 = PAD(Gb, gx1, gy1), *b2 = PAD(Gb, gx2, gy2);
+                double nWbar = 0.0;
+                for (long j = 0; j < nv; ++j) {
+                    const double gam = b1[j] + b2[j];
+                    const double vn = sign * va[j];
+                    if (vn > 0.0) {
+                        const double c2 = (g.vx[j] - uw) * (g.vx[j] - uw) + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j];
+                        const double dphi = phiw[j] * (c2 / (Tw * Tw) - 1.5 / Tw);
+                        nWbar += gam * phiw[j];
+                        *gtw += gam * nW * (dphi - phiw[j] * Dp / D);
+                    } else {
+                        gb0[j] += gam;
+                    }
+                }
+                for (long j = 0; j < nv; ++j) {
+                    const double vn = sign * va[j];
+                    if (vn < 0.0) gb0[j] += nWbar * (-vn) / D;
+                }
+            }
+        }
+    }
+#undef PAD
+#undef SRC
+    free(rest); free(lid); free(nW_store);
+    free(G); free(Gb);
+    free_velgrid(&g);
+}
+
+/* Adjoint of one time step at f (Strang: R_{dt/2} S R_{dt/2}; Lie: R_dt S):
+ * lam_n = (d step / d f)^T lam_next; grad[0] += dL/dKn, grad[1] += dL/dT_w. */
+void orc_step_adjoint(const orc_problem *p, const double *f, const double *lam_next, double *lam_n, double *grad)
+{
+    const double dt = orc_dt(p);
+    const long n = ncell(p) * nvel(p);
+    double *a = malloc(sizeof(double) * n), *h = malloc(sizeof(double) * n), *t = malloc(sizeof(double) * n);
+    if (p->strang) {
+        orc_relax(p, f, a, 0.5 * dt);
+        orc_stream(p, a, h, dt);
+        orc_relax_adjoint(p, h, lam_next, t, 0.5 * dt, &grad[0]);
+        double *u = malloc(sizeof(double) * n);
+        orc_stream_adjoint(p, a, t, u, dt, &grad[1]);
+        orc_relax_adjoint(p, f, u, lam_n, 0.5 * dt, &grad[0]);
+        free(u);
+    } else {
+        orc_stream(p, f, h, dt);
+        orc_relax_adjoint(p, h, lam_next, t, dt, &grad[0]);
+        orc_stream_adjoint(p, f, t, lam_n, dt, &grad[1]);
+    }
+    free(a); free(h); free(t);
+}
+
+/* Gradient of orc_lid_shear: lam = dL/df (zero outside the top row),
+ * grad[1] += dL/dT_w.  With N_i = sum_{vy>0} vy f_top,i, K = sum_{vy<0} vx vy Phi_W,
+ * D = sum_{vy<0} |vy| Phi_W:  L = sum_i dx dV [sum_{vy>0} vx vy f_top,i + N_i K / D]. */
+void orc_lid_shear_grad(const orc_problem *p, const double *f, double *lam, double *grad)
+{
+    velgrid g = make_velgrid(p);
+    const int nx = p->nx, ny = p->ny;
+    const long nv = nvel(p);
+    const double dV = dvol(p), dx = dxs(p), Tw = p->t_wall, uw = lid_speed(p);
+    double *lid = malloc(sizeof(double) * nv);
+    wall_maxwellian(p, &g, uw, lid);
+    double K = 0, D = 0, Kp = 0, Dp = 0;
+    for (long j = 0; j < nv; ++j)
+        if (g.vy[j] < 0.0) {
+            const double c2 = (g.vx[j] - uw) * (g.vx[j] - uw) + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j];
+            const double dphi = lid[j] * (c2 / (Tw * Tw) - 1.5 / Tw);
+            K += g.vx[j] * g.vy[j] * lid[j];
+            D += -g.vy[j] * lid[j];
+            Kp += g.vx[j] * g.vy[j] * dphi;
+            Dp += -g.vy[j] * dphi;
+        }
+    memset(lam, 0, sizeof(double) * ncell(p) * nv);
+    for (int ix = 0; ix < nx; ++ix) {
+        const long c = (long)(ny - 1) * nx + ix;
+        double N = 0.0;
+        for (long j = 0; j < nv; ++j)
+            if (g.vy[j] > 0.0) {
+                lam[c * nv + j] = dx * dV * (g.vx[j] * g.vy[j] + g.vy[j] * K / D);
+                N += g.vy[j] * f[c * nv + j];
+            }
+        grad[1] += dx * dV * N * (Kp / D - K * Dp / (D * D));
+    }
+    free(lid);
+    free_velgrid(&g);
+}
