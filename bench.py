@@ -39,15 +39,11 @@ DESCRIPTIONS = {
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources: traffic counters are reported only while
-    the kernels are the ones they were taken from."""
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_0903_4044_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()
+    """sha256 of the source of the streaming kernel (bgk_device.h holds
+    k_stream and everything it inlines): traffic counters are reported only
+    while the kernel is the one they were taken from."""
+    with open(os.path.join(ROOT, "paper_0903_4044_amd", "csrc", "bgk_device.h"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
 
 
 def read_traffic(workload: str):
@@ -109,6 +105,44 @@ def run_workload(binding, torch, problems, precision, steps, warmup, kernel_timi
     if rc != 0:
         raise RuntimeError(f"state check failed after the timed run (status {rc})")
     return t1 - t0, ms / max(launches, 1), points, shape
+
+
+def run_adjoint(binding, torch, cfg, precision, every=20):
+    """Differentiated rollout of the adjoint workload: forward with checkpoints
+    every `every` steps, then the checkpointed reverse sweep (segment
+    recomputation + one bgk_step_adjoint per step) down to dL/df0, dL/dKn and
+    dL/dT_w.  Returns (forward s, backward s, points, steps)."""
+    from paper_0903_4044_amd import inputs, solver
+    ctx = binding.Context(cfg, precision)
+    nsteps = cfg["steps"]
+    xi = torch.tensor(inputs.noise((ctx.f_elems,)), dtype=ctx.dtype, device="cuda")
+    f0 = ctx.initial_state() * (1 + 1e-3 * xi)
+    del xi
+    ctx.autotune(f0)
+
+    def once(n):
+        x = f0.clone().requires_grad_(True)
+        kn = torch.tensor(cfg["kn"], dtype=torch.float64, requires_grad=True)
+        tw = torch.tensor(cfg["t_wall"], dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = solver.lid_shear(solver.rollout(x, kn, tw, ctx, n, every=every), tw, ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if not all(torch.isfinite(t.grad).all() for t in (x, kn, tw)):
+            raise RuntimeError("non-finite gradient in the adjoint run")
+        return t1 - t0, t2 - t1
+
+    once(every)  # warm-up: one segment
+    fwd, bwd = once(nsteps)
+    points = ctx.f_elems
+    ctx.close()
+    del f0
+    torch.cuda.empty_cache()
+    return fwd, bwd, points, nsteps
 
 
 def cpu_baseline(cfg, budget_s: float):
@@ -210,6 +244,15 @@ def main():
             extras[name] = e
             print(f"# {name}: {e['updates_per_s']:.4g} updates/s" +
                   (f", {e['achieved_GBs']:.0f} GB/s" if "achieved_GBs" in e else ""), file=sys.stderr, flush=True)
+        for p in ("fp32", "fp64"):
+            fwd, bwd, pts, n = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
+            e = {"updates_per_s": pts * n / (fwd + bwd), "steps": n, "points": pts, "precision": p,
+                 "forward_s": fwd, "reverse_s": bwd, "reverse_updates_per_s": pts * n / bwd,
+                 "checkpoint_every": 20,
+                 "note": "updates/s counts each of the rollout's steps once over forward + checkpointed reverse"}
+            extras[f"adjoint_cavity_64_{p}"] = e
+            print(f"# adjoint_cavity_64_{p}: {e['updates_per_s']:.4g} updates/s (forward {fwd * 1e3:.1f} ms, "
+                  f"reverse {bwd * 1e3:.1f} ms)", file=sys.stderr, flush=True)
         plain = extras["shock_m1.5_fp64"]["updates_per_s"]
         extras["plain_fp64_updates_per_s"] = plain
         extras["ratio_vs_plain_fp64"] = {k: v["updates_per_s"] / plain for k, v in extras.items()

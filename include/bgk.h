@@ -68,7 +68,9 @@ extern "C" {
 
 #define BGK_FP64 0          /* f stored and streamed in double */
 #define BGK_FP32 1          /* f stored and streamed in float; moments, Maxwellian
-                               parameters and all reductions in double */
+                               parameters and all reductions in double; each stored
+                               value is computed in double and rounded to float
+                               stochastically (unbiased), see bgk_set_rounding_seed */
 
 /* One problem instance (Sec. 2.1 grid, Sec. 4.1 / 5.1 boundary data). */
 typedef struct bgk_problem {
@@ -167,6 +169,59 @@ int bgk_set_graph(bgk_ctx *ctx, int on);
  * reset, then resets. */
 int bgk_set_timing(bgk_ctx *ctx, int capacity);
 int bgk_timing(bgk_ctx *ctx, double *ms, int *launches);
+
+/* Rounding seed of the BGK_FP32 path.  Stored values are rounded up or down
+ * to a neighbouring float with probabilities proportional to their distance
+ * (unbiased stochastic rounding), because round-to-nearest loses the
+ * sub-ulp change per step of a nearly uniform, nearly Maxwellian region and
+ * so freezes its slow drift.  The random bits are a hash of (element index
+ * within its instance, rounding counter), so results do not depend on the
+ * launch shape or on batching.  A call bgk_step(..., n, ...) uses counters
+ * seed .. seed + n - 1 for its streaming passes and seed + n for its closing
+ * relaxation, then advances the context's seed by n; bgk_set_rounding_seed
+ * sets it (0 after bgk_init) so that a run can be repeated bit for bit.
+ * No effect on BGK_FP64. */
+int bgk_set_rounding_seed(bgk_ctx *ctx, unsigned int seed);
+int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
+
+/* Reverse sweep of one time step (the discrete adjoint of the step defined
+ * above: Sec. 2.1 splitting, Eq. (relaxation) with the moments of
+ * Eq. (macroscopic) differentiated through Eq. (Maxw) and Eq. (frequency),
+ * the minmod flux-form streaming with the diffuse-wall re-emission of
+ * Eq. (bc_cavity), whose wall density makes the net wall mass flux zero).
+ *   lam_n = (d step / d f)^T lam_next   evaluated at f_n,
+ *   grad_params[2k]   += sum lam_next . d step / d Kn     (instance k),
+ *   grad_params[2k+1] += sum lam_next . d step / d T_w    (instance k; 0 for
+ *                                                           non-cavity kinds).
+ * The inner product is the plain element sum over f's layout (no dV weight).
+ * f_n, lam_next and lam_n are device arrays of f_elems elements in the
+ * context's precision (FP32: f and the adjoint stored in float, every
+ * moment, table and reduction in double); lam_n must not alias either input
+ * (BGK_E_ALIAS).  grad_params is a device array of 2 * n_probs doubles that
+ * the call ACCUMULATES into (zero it before the first step of a sweep).
+ * Minmod branch decisions are those of the forward map at f_n; at a kink
+ * (equal slopes or a zero product) the branch taken by the forward
+ * limiter's own tie rule is differentiated.  The first call allocates the
+ * context's reverse-sweep work space (three extra f buffers); BGK_E_HIP if
+ * that fails.  Asynchronous on `stream`. */
+int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
+                     void *stream);
+
+/* Shear stress on the moving lid (Sec. 5.1 cavity; the xy momentum flux
+ * through the top wall, integrated along it):
+ *   L_k = dx * dV * sum_{top cells} [ sum_{v_y>0} v_x v_y f
+ *                                     + n_W sum_{v_y<0} v_x v_y Phi_W ],
+ * with Phi_W the unit-density wall Maxwellian at (U_W, 0, 0) and T_w and n_W
+ * the per-cell wall density that balances the incident flux
+ * sum_{v_y>0} v_y f.  Written to L[k] (device, n_probs doubles); 0 for
+ * non-cavity instances.  f: device, f_elems elements. */
+int bgk_lid_shear(bgk_ctx *ctx, const void *f, double *L, void *stream);
+
+/* Gradient of bgk_lid_shear: lam = dL/df (device, f_elems elements in the
+ * context's precision, overwritten, zero outside the top row of each
+ * cavity; must not alias f) and grad_params[2k+1] += dL_k/dT_w
+ * (grad_params[2k] unchanged: L has no explicit Kn dependence). */
+int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double *grad_params, void *stream);
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,9 @@ class Problem(ctypes.Structure):
 
 EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_info",
            "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
-           "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph")
+           "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph",
+           "bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad", "bgk_set_rounding_seed",
+           "bgk_get_rounding_seed")
 
 TUNED_PATH = os.path.join(HERE, "tuned.json")
 
@@ -74,11 +76,16 @@ def load(path: str = LIB_PATH):
     L.bgk_moments.argtypes = [vp, vp, vp, vp]
     L.bgk_check.argtypes = [vp, vp, vp]
     L.bgk_set_timing.argtypes = [vp, ctypes.c_int]
+    L.bgk_set_rounding_seed.argtypes = [vp, ctypes.c_uint]
+    L.bgk_get_rounding_seed.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
     L.bgk_timing.argtypes = [vp, dp, ip]
     L.bgk_autotune.argtypes = [vp, vp, vp]
     L.bgk_get_launch.argtypes = [vp, ip, ip, ip, ip, dp]
     L.bgk_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.bgk_set_graph.argtypes = [vp, ctypes.c_int]
+    L.bgk_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.bgk_lid_shear.argtypes = [vp, vp, vp, vp]
+    L.bgk_lid_shear_grad.argtypes = [vp, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -217,6 +224,35 @@ class Context:
         self._check(self.L.bgk_moments(self.h, _ptr(f), _ptr(out), _stream_handle(stream)))
         return out
 
+    # -- reverse sweep ----------------------------------------------------
+    def grad_buffer(self, device="cuda") -> torch.Tensor:
+        """Per-instance (dL/dKn, dL/dT_w) accumulator, float64 [ninst, 2]."""
+        return torch.zeros((len(self.problems), 2), dtype=torch.float64, device=device)
+
+    def step_adjoint(self, f_n: torch.Tensor, lam_next: torch.Tensor, lam_n: torch.Tensor | None = None,
+                     grad: torch.Tensor | None = None, stream=None):
+        """lam_n = (d step / d f_n)^T lam_next; adds this step's parameter
+        gradients to grad (created if None).  Returns (lam_n, grad)."""
+        lam_n = torch.empty_like(lam_next) if lam_n is None else lam_n
+        grad = self.grad_buffer(f_n.device) if grad is None else grad
+        self._check(self.L.bgk_step_adjoint(self.h, _ptr(f_n), _ptr(lam_next), _ptr(lam_n), _ptr(grad),
+                                            _stream_handle(stream)))
+        return lam_n, grad
+
+    def lid_shear(self, f: torch.Tensor, stream=None) -> torch.Tensor:
+        """Lid shear of every cavity instance (0 for other kinds), float64 [ninst]."""
+        out = torch.empty(len(self.problems), dtype=torch.float64, device=f.device)
+        self._check(self.L.bgk_lid_shear(self.h, _ptr(f), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def lid_shear_grad(self, f: torch.Tensor, lam: torch.Tensor | None = None, grad: torch.Tensor | None = None,
+                       stream=None):
+        """dL/df of the lid shear (summed over instances) and its explicit T_w term."""
+        lam = torch.empty_like(f) if lam is None else lam
+        grad = self.grad_buffer(f.device) if grad is None else grad
+        self._check(self.L.bgk_lid_shear_grad(self.h, _ptr(f), _ptr(lam), _ptr(grad), _stream_handle(stream)))
+        return lam, grad
+
     def check(self, f: torch.Tensor, stream=None) -> int:
         return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))
 
@@ -233,6 +269,16 @@ class Context:
 
     def set_launch(self, vec: int, unroll: int, vsplit: int, persist: int = 0):
         self._check(self.L.bgk_set_launch(self.h, int(vec), int(unroll), int(vsplit), int(persist)))
+
+    def set_seed(self, seed: int):
+        """Rounding seed of the FP32 path (stochastic rounding of stored values);
+        bgk_step advances it by its step count."""
+        self._check(self.L.bgk_set_rounding_seed(self.h, int(seed) & 0xFFFFFFFF))
+
+    def seed(self) -> int:
+        v = ctypes.c_uint()
+        self._check(self.L.bgk_get_rounding_seed(self.h, ctypes.byref(v)))
+        return v.value
 
     def set_graph(self, on: bool):
         """Replay the steady two-step launch sequence from a captured hipGraph."""

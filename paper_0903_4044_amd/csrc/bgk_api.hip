@@ -1,5 +1,6 @@
 // bgk_api.hip -- host side of libbgk.so: validation, layout, launches.
 // The C ABI is declared in include/bgk.h.
+#include "bgk_adjoint.h"
 #include "bgk_device.h"
 
 #include <hip/hip_runtime.h>
@@ -15,6 +16,12 @@
 #include "../../include/bgk.h"
 
 using namespace bgk;
+
+// Start value of the rounding counter (a vector store by one lane).
+__global__ void k_set_pass(uint32_t *pass, uint32_t v)
+{
+    if (threadIdx.x == 0) pass[0] = v;
+}
 
 
 struct bgk_ctx {
@@ -53,7 +60,21 @@ struct bgk_ctx {
     void *params = nullptr;    // 2 x (ncells + npseudo) * pe elements (parity buffers)
     double *partial = nullptr; // ncells * vsplit * NQ
     double *mom = nullptr;     // ncells * 5 (bgk_check)
+    // reverse sweep (allocated at the first bgk_step_adjoint / bgk_lid_shear call)
+    bool adj_ready = false;
+    void *adj_h = nullptr, *adj_hb = nullptr;                     // f-sized: h = S(R_a f), abar
+    double *info_f = nullptr, *info_h = nullptr;                  // ncells * NINFO
+    double *adj_sums = nullptr, *adj_wsum = nullptr;              // ncells * vsplit_max * (NSUM, NWALL)
+    double *adj_coef = nullptr;                                   // ncells * NCOEF
+    double *adj_dw = nullptr;                                     // ninst * 4 walls * (D, D')
+    int *wall_cells = nullptr;                                    // perimeter cells of the cavities
+    int n_wall_cells = 0;
+    double *gk = nullptr, *gt = nullptr, *lid = nullptr;          // ncells, ncells, 2 * ncells
     int *flags = nullptr;
+    // stochastic rounding of FP32 stores: device pass counter and the value
+    // the next bgk_step starts it from
+    uint32_t *pass = nullptr;
+    uint32_t seed = 0;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -93,6 +114,7 @@ static Args make_args(const bgk_ctx *c)
     a.vsplit = c->vsplit;
     a.zr = c->zr;
     a.nparts = c->vsplit;
+    a.pass = c->pass;
     a.g = c->geo;
     return a;
 }
@@ -107,7 +129,12 @@ static void release(bgk_ctx *c)
     (void)hipFree(c->params);
     (void)hipFree(c->partial);
     (void)hipFree(c->mom);
+    for (void *q : {c->adj_h, c->adj_hb}) (void)hipFree(q);
+    for (double *q : {c->info_f, c->info_h, c->adj_sums, c->adj_wsum, c->adj_coef, c->adj_dw, c->gk, c->gt, c->lid})
+        (void)hipFree(q);
+    (void)hipFree(c->wall_cells);
     (void)hipFree(c->flags);
+    (void)hipFree(c->pass);
     for (auto &e : c->events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -352,11 +379,13 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     ALLOC(c->partial, sizeof(double) * (size_t)c->ncells * c->vsplit_max * NQ);
     ALLOC(c->mom, sizeof(double) * (size_t)c->ncells * 5);
     ALLOC(c->flags, sizeof(int));
+    ALLOC(c->pass, sizeof(uint32_t));
 #undef ALLOC
     hipError_t e1 = hipMemcpy(c->d_inst, c->h_inst.data(), sizeof(Inst) * n_probs, hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(c->d_cell_prefix, c->h_cell_prefix.data(), sizeof(int) * (n_probs + 1), hipMemcpyHostToDevice);
     hipError_t e3 = hipMemcpy(c->d_pseudo_prefix, c->h_pseudo_prefix.data(), sizeof(int) * (n_probs + 1), hipMemcpyHostToDevice);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    hipError_t e4 = hipMemset(c->pass, 0, sizeof(uint32_t));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
         release(c);
         return fail(nullptr, BGK_E_HIP, "hipMemcpy of instance tables failed");
     }
@@ -505,6 +534,11 @@ static int one_pass(bgk_ctx *c, int k, int n, const void *src, void *dst, hipStr
 template <typename real>
 static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t s)
 {
+    // rounding counter of pass k (1-based) is seed + k - 1; the tables after
+    // each pass advance it on the device, so graph replays advance it too
+    hipLaunchKernelGGL(k_set_pass, dim3(1), dim3(64), 0, s, c->pass, c->seed);
+    HIP_TRY(c, hipGetLastError());
+    c->seed += (uint32_t)n;
     TRY(launch_moments<real>(c, f_in, s));
     TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
     auto X = [&](int k) -> void * { return k == 0 ? const_cast<void *>(f_in) : ((n - k) % 2 == 0 ? f_out : c->work); };
@@ -538,6 +572,177 @@ static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t
     }
     for (; k <= n; ++k) TRY(one_pass<real>(c, k, n, X(k - 1), X(k), s));
     return launch_final<real>(c, f_out, f_out, n % 2, s);
+}
+
+// ------------------------------------------------------------- reverse sweep
+
+static int ensure_adjoint(bgk_ctx *c)
+{
+    if (c->adj_ready) return BGK_OK;
+    const size_t fb = c->f_elems * c->esize, nc = (size_t)c->ncells, np = nc * c->vsplit_max;
+    HIP_TRY(c, hipMalloc(&c->adj_h, fb));
+    HIP_TRY(c, hipMalloc(&c->adj_hb, fb));
+    HIP_TRY(c, hipMalloc((void **)&c->info_f, sizeof(double) * nc * NINFO));
+    HIP_TRY(c, hipMalloc((void **)&c->info_h, sizeof(double) * nc * NINFO));
+    HIP_TRY(c, hipMalloc((void **)&c->adj_sums, sizeof(double) * np * NSUM));
+    HIP_TRY(c, hipMalloc((void **)&c->adj_wsum, sizeof(double) * np * NWALL));
+    HIP_TRY(c, hipMalloc((void **)&c->adj_coef, sizeof(double) * nc * NCOEF));
+    HIP_TRY(c, hipMalloc((void **)&c->adj_dw, sizeof(double) * c->ninst * 8));
+    HIP_TRY(c, hipMalloc((void **)&c->gk, sizeof(double) * nc));
+    HIP_TRY(c, hipMalloc((void **)&c->gt, sizeof(double) * nc));
+    HIP_TRY(c, hipMalloc((void **)&c->lid, sizeof(double) * 2 * nc));
+    std::vector<int> wc;
+    for (const Inst &I : c->h_inst) {
+        if (I.kind != KIND_CAVITY) continue;
+        for (int iy = 0; iy < I.ny; ++iy)
+            for (int ix = 0; ix < I.nx; ++ix)
+                if (ix == 0 || ix == I.nx - 1 || iy == 0 || iy == I.ny - 1) wc.push_back(I.cell0 + iy * I.nx + ix);
+    }
+    c->n_wall_cells = (int)wc.size();
+    if (!wc.empty()) {
+        HIP_TRY(c, hipMalloc((void **)&c->wall_cells, sizeof(int) * wc.size()));
+        HIP_TRY(c, hipMemcpy(c->wall_cells, wc.data(), sizeof(int) * wc.size(), hipMemcpyHostToDevice));
+    }
+    c->adj_ready = true;
+    return BGK_OK;
+}
+
+static int fill(bgk_ctx *c, double *x, long long n, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+// Coefficients (c->adj_coef) of the transpose of a relaxation at x applied
+// to mu, with the per-cell relaxation data in info; adds dL/dKn to c->gk.
+template <typename real>
+static int relax_coef(bgk_ctx *c, const void *x, const void *mu, const double *info, hipStream_t s)
+{
+    const int nb = c->ncells * c->vsplit;
+    hipLaunchKernelGGL(k_adj_sums<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)x, (const real *)mu,
+                       info, c->adj_sums);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_adj_coef, dim3((c->ncells + 255) / 256), dim3(256), 0, s, make_args(c), info, c->adj_sums,
+                       c->adj_coef, c->gk);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+template <typename real>
+static int relax_info(bgk_ctx *c, double *info, int which, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_relax_info, dim3((c->ncells + 255) / 256), dim3(256), 0, s, make_args(c), c->partial, info,
+                       which);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+template <typename real, int DIM>
+static void adj_stream_dispatch(bgk_ctx *c, const void *f, const void *lam, hipStream_t s)
+{
+    const int nb = c->ncells * c->vsplit;
+    const size_t lds = (size_t)(DIM == 1 ? 9 : 17) * c->geo.pe * sizeof(real);
+    const real *p0 = params_buf<real>(c, 0);
+    const real *fr = (const real *)f, *lr = (const real *)lam;
+    real *o = (real *)c->adj_hb;
+    if (c->vec == 4 && sizeof(real) == 4)
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 4>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
+                           c->adj_coef, o, c->adj_wsum);
+    else if (c->vec == 2)
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 2>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
+                           c->adj_coef, o, c->adj_wsum);
+    else
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 1>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
+                           c->adj_coef, o, c->adj_wsum);
+}
+
+// One reverse step.  The first streaming pass of the step is recomputed
+// (h = S(R_a f) with the opening tables in parity buffer 0, which stay valid
+// for the rest of the call), then
+//   abar = S^T(R_b^T lambda^{n+1})   (k_adj_stream, k_adj_wall),
+//   lambda^n = R_a^T(abar)           (k_adj_sums, k_adj_coef, k_adj_apply).
+template <typename real>
+static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam_n, double *grad, hipStream_t s)
+{
+    TRY(ensure_adjoint(c));
+    TRY(fill(c, c->gk, c->ncells, 0.0, s));
+    TRY(fill(c, c->gt, c->ncells, 0.0, s));
+    TRY(launch_moments<real>(c, f, s));
+    TRY(relax_info<real>(c, c->info_f, 0, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    c->pass_parity = 0;
+    const bool timing = c->timing;
+    c->timing = false;
+    int rc = launch_stream<real>(c, f, c->adj_h, s);
+    c->timing = timing;
+    TRY(rc);
+    TRY(relax_info<real>(c, c->info_h, 1, s));
+    TRY(relax_coef<real>(c, c->adj_h, lam_next, c->info_h, s));
+    if (c->dim == 1) adj_stream_dispatch<real, 1>(c, f, lam_next, s);
+    else adj_stream_dispatch<real, 2>(c, f, lam_next, s);
+    HIP_TRY(c, hipGetLastError());
+    if (c->n_wall_cells > 0) {
+        const real *p0 = params_buf<real>(c, 0);
+        hipLaunchKernelGGL(k_adj_wall_flux<real>, dim3(4 * c->ninst), dim3(256), 0, s, make_args(c), p0, c->adj_dw);
+        HIP_TRY(c, hipGetLastError());
+        hipLaunchKernelGGL(k_adj_wall<real>, dim3(c->n_wall_cells), dim3(256), 0, s, make_args(c), c->wall_cells, p0,
+                           c->adj_dw, c->adj_wsum, (real *)c->adj_hb, c->gt);
+        HIP_TRY(c, hipGetLastError());
+    }
+    TRY(relax_coef<real>(c, f, c->adj_hb, c->info_f, s));
+    const int nb = c->ncells * c->vsplit;
+    hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)c->adj_hb,
+                       c->adj_coef, (real *)lam_n);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_grad_reduce, dim3(c->ninst), dim3(256), 0, s, make_args(c), c->gk, c->gt, grad);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
+                                void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f_n || !lam_next || !lam_n || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_step_adjoint: NULL buffer");
+    if (lam_n == f_n || lam_n == lam_next) return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: lam_n must not alias inputs");
+    hipStream_t s = (hipStream_t)stream;
+    return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
+                                      : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
+}
+
+template <typename real>
+static int lid(bgk_ctx *c, const void *f, double *L, void *lam, double *grad, hipStream_t s)
+{
+    TRY(ensure_adjoint(c));
+    hipLaunchKernelGGL(k_lid_sums<real>, dim3(c->ncells), dim3(256), 0, s, make_args(c), (const real *)f, c->lid);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_lid_finish, dim3(c->ninst), dim3(64), 0, s, make_args(c), c->lid, L, grad);
+    HIP_TRY(c, hipGetLastError());
+    if (lam) {
+        hipLaunchKernelGGL(k_lid_seed<real>, dim3(c->ncells), dim3(256), 0, s, make_args(c), (real *)lam);
+        HIP_TRY(c, hipGetLastError());
+    }
+    return BGK_OK;
+}
+
+extern "C" int bgk_lid_shear(bgk_ctx *ctx, const void *f, double *L, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f || !L) return fail(ctx, BGK_E_INVALID, "bgk_lid_shear: NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, L, nullptr, nullptr, s)
+                                      : lid<float>(ctx, f, L, nullptr, nullptr, s);
+}
+
+extern "C" int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double *grad_params, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f || !lam || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_lid_shear_grad: NULL buffer");
+    if (lam == f) return fail(ctx, BGK_E_ALIAS, "bgk_lid_shear_grad: lam must not alias f");
+    hipStream_t s = (hipStream_t)stream;
+    return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, nullptr, lam, grad_params, s)
+                                      : lid<float>(ctx, f, nullptr, lam, grad_params, s);
 }
 
 // ------------------------------------------------------------- autotuning
@@ -679,6 +884,20 @@ extern "C" int bgk_check(bgk_ctx *ctx, const void *f, void *stream)
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (flags & 1) return fail(ctx, BGK_E_NONFINITE, "bgk_check: non-finite moment");
     if (flags & 2) return fail(ctx, BGK_E_NEGATIVE, "bgk_check: density or temperature <= 0");
+    return BGK_OK;
+}
+
+extern "C" int bgk_set_rounding_seed(bgk_ctx *ctx, unsigned int seed)
+{
+    if (!ctx) return BGK_E_INVALID;
+    ctx->seed = seed;
+    return BGK_OK;
+}
+
+extern "C" int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed)
+{
+    if (!ctx || !seed) return BGK_E_INVALID;
+    *seed = ctx->seed;
     return BGK_OK;
 }
 

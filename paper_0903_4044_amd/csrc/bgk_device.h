@@ -35,7 +35,7 @@ namespace bgk {
 
 constexpr int NVMAX = 128;        // per velocity component
 constexpr int KIND_SHOCK = 0, KIND_CAVITY = 1, KIND_PER1 = 2, KIND_PER2 = 3;
-constexpr int MODE_FIRST = 0, MODE_MID = 1, MODE_FINAL = 2;
+constexpr int MODE_FIRST = 0, MODE_MID = 1, MODE_FINAL = 2, MODE_IDENT = 3;
 constexpr int NQ = 9;             // moment sums per cell: 1, vx, vy, vz, |v|^2, 4 half fluxes
 
 struct Inst {
@@ -71,6 +71,7 @@ struct Args {
     int vsplit;                 // velocity chunks (along jz) per cell
     int zr;                     // jz residues per streaming workgroup (lane tasks)
     int nparts;                 // partial moment sums per cell that consumers add up
+    uint32_t *pass;             // rounding counter: advanced once per streaming pass
     Geo g;
 };
 
@@ -98,6 +99,47 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
 
 __device__ __forceinline__ float minmod3(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+
+// ---------------------------------------------------------------- rounding
+// FP32 storage of f rounds each stored value stochastically: up or down to
+// a neighbouring float with probabilities that make the rounding unbiased.
+// Round-to-nearest would stall a near-equilibrium region: the change of f
+// per step there is far below half an ulp, so every step rounds back to the
+// same float and the slow drift of the FP64 dynamics is lost.  The random
+// bits come from a counter-based hash of (element index within its
+// instance, streaming pass), so results do not depend on launch shape or
+// batching and repeat exactly for the same rounding seed.
+
+// 32-bit integer hash ("lowbias32", C. Wellons, Prospecting for Hash
+// Functions, 2018): xorshift-multiply rounds with constants 0x7feb352d and
+// 0x846ca68b.
+__device__ __forceinline__ uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Key of one rounding pass; `stream` separates the streaming kernel (0) from
+// the closing relaxation (1).
+__device__ __forceinline__ uint32_t pass_key(const uint32_t *pass, uint32_t stream)
+{
+    return hash32(*pass * 2u + stream + 0x9e3779b9u);
+}
+
+// Stochastic rounding of x to float: add 29 uniform bits below the float's
+// last mantissa bit of |x| and truncate (sign-magnitude, so the magnitude
+// rounds away from zero with probability equal to the dropped fraction).
+__device__ __forceinline__ float round_stochastic(double x, uint32_t r)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    b += (unsigned long long)(r >> 3);
+    b &= ~((1ull << 29) - 1ull);
+    return (float)__longlong_as_double((long long)b);
+}
 __device__ __forceinline__ double minmod3(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
 
 // Deterministic block reduction of NQ doubles; thread q < NQ writes out[q].
@@ -204,10 +246,15 @@ __global__ void k_check(int ncells, const double *__restrict__ mom, int *__restr
 //   FIRST: g = R1(f0)        (Strang: R_{dt/2}; Lie: identity)
 //   MID:   g = R1(R2(h))     (Strang: R_{dt/2} R_{dt/2}; Lie: R_dt)
 //   FINAL: f = R2(h)         (Strang: R_{dt/2}; Lie: R_dt)
+//   IDENT: g = h             (no relaxation; the reverse sweep streams R_a(f) itself)
 // Returned in application order: ta is applied first, tb second; nr relaxations.
 __device__ __forceinline__ int relax_times(const Inst &I, int mode, double *ta, double *tb)
 {
     const double h = 0.5 * I.dt;
+    if (mode == MODE_IDENT) {
+        *ta = *tb = 0.0;
+        return 0;
+    }
     if (I.strang) {
         *ta = h;
         *tb = h;
@@ -365,7 +412,13 @@ __device__ __forceinline__ void write_entry(const Geo &g, real *E, double c0, do
                                             const Tables &tB)
 {
     const int lane = threadIdx.x & 63;
-    if (lane == 0) E[0] = (real)c0;
+    if (lane == 0) {
+        E[0] = (real)c0;
+        // float entries also keep c0 in double (slots 2-3, 8-byte aligned): the
+        // centre value's relaxation uses it, since c0 rounded to float would
+        // gain or lose that rounding error of mass at every relaxation
+        if constexpr (sizeof(real) == 4) *reinterpret_cast<double *>(E + 2) = c0;
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int k = lane + 64 * q;
@@ -456,6 +509,7 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     const double den = pw * g.dV * out_w * ow * sw[b2][0];
     (void)b1;
     write_entry<real>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
+    if ((threadIdx.x & 63) == 1) E[1] = (real)(flux / den);  // n_W, read by the reverse sweep
 }
 
 // Table preparation between streaming passes: one wave per entry.
@@ -463,6 +517,9 @@ template <typename real>
 __global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__ partial, real *__restrict__ params,
                                               int mode, int nentries, real *__restrict__ params_shock_copy)
 {
+    // Tables of these modes follow a streaming pass: advance the rounding
+    // counter once (stream order puts this after that pass's reads).
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (mode == MODE_MID || mode == MODE_FINAL)) A.pass[0] = A.pass[0] + 1u;
     const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= nentries) return;  // the whole wave leaves; no block barrier follows
     prep_entry<real>(A, e, mode, partial, params);
@@ -623,6 +680,9 @@ __global__ void __launch_bounds__(256)
     const bool lim = I.minmod != 0;
     const int ngx = g.nvx / VEC, ngroups = ngx * g.nvy, ntask = ngroups * A.zr;
     const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
+    const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;  // element index of (cell, 0) in the instance
+    const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
+    const double c0d = sizeof(real) == 4 ? *reinterpret_cast<const double *>(sp + 2) : 0.0;  // centre entry's c0
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
@@ -662,9 +722,23 @@ __global__ void __launch_bounds__(256)
         auto finish = [&](const V (&hv)[NT], int jz) {
             const uint32_t zo = (uint32_t)jz * zstep;
             const V u0 = tc.relax(hv[0], jz);
-            V r = u0 - flux_diff<real, VEC>(xa.relax(hv[1], jz), xb.relax(hv[2], jz), u0, xd.relax(hv[3], jz), Cx, kx);
+            V dx = flux_diff<real, VEC>(xa.relax(hv[1], jz), xb.relax(hv[2], jz), u0, xd.relax(hv[3], jz), Cx, kx);
+            V dy = 0;
             if constexpr (DIM == 2)
-                r -= flux_diff<real, VEC>(ya.relax(hv[4], jz), yb.relax(hv[5], jz), u0, yd.relax(hv[6], jz), Cy, ky);
+                dy = flux_diff<real, VEC>(ya.relax(hv[4], jz), yb.relax(hv[5], jz), u0, yd.relax(hv[6], jz), Cy, ky);
+            V r;
+            if constexpr (sizeof(real) == 4) {
+                // the centre relaxation and the flux sum in FP64, one stochastic rounding
+                const double ta = (double)tc.tz[2 * jz], tb = (double)tc.tz[2 * jz + 1];
+                const uint32_t i0 = ecell + (uint32_t)jz * (uint32_t)g.npl + (uint32_t)p0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const double g0 = c0d * (double)hv[0][e] + ((double)tc.l1[e] * ta + (double)tc.l2[e] * tb);
+                    r[e] = round_stochastic(g0 - ((double)dx[e] + (double)dy[e]), hash32((i0 + e) ^ key));
+                }
+            } else {
+                r = u0 - dx - dy;
+            }
             __builtin_nontemporal_store(r, reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo +
                                                                   (uint32_t)(p0 * sizeof(real))));
             double s = 0.0;
@@ -730,13 +804,22 @@ __global__ void __launch_bounds__(256) k_final(Args A, const real *src, real *ds
     const real *E = params + (long long)gc * g.pe;
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     const real c0 = E[0];
+    const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 1) : 0u;
+    const double c0d = sizeof(real) == 4 ? *reinterpret_cast<const double *>(E + 2) : 0.0;
+    const uint32_t ecell = (uint32_t)(gc - I.cell0) * (uint32_t)g.nv;
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
         const real l1 = E[g.tx1 + jx] * E[g.ty1 + jy];
         const real l2 = E[g.tx2 + jx] * E[g.ty2 + jy];
         for (int jz = z0; jz < z1; ++jz) {
             const long long i = off + (long long)jz * g.npl + p;
-            dst[i] = c0 * src[i] + (l1 * E[g.tz + 2 * jz] + l2 * E[g.tz + 2 * jz + 1]);
+            if constexpr (sizeof(real) == 4) {
+                const double v = c0d * (double)src[i] +
+                                 ((double)l1 * (double)E[g.tz + 2 * jz] + (double)l2 * (double)E[g.tz + 2 * jz + 1]);
+                dst[i] = round_stochastic(v, hash32((ecell + (uint32_t)(jz * g.npl + p)) ^ key));
+            } else {
+                dst[i] = c0 * src[i] + (l1 * E[g.tz + 2 * jz] + l2 * E[g.tz + 2 * jz + 1]);
+            }
         }
     }
 }

@@ -1,10 +1,11 @@
 """Autotune the streaming kernel for the standard workloads on this GPU and
 record the shapes in tuned.json (read by binding.Context(tune="table")).
 
-    python -m paper_0903_4044_amd.tune
+    python -m paper_0903_4044_amd.tune [--out PATH]
 """
 from __future__ import annotations
 
+import argparse
 import json
 import sys
 
@@ -23,6 +24,9 @@ def workloads():
 
 
 def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=binding.TUNED_PATH, help="where to write the table")
+    args = ap.parse_args()
     torch.cuda.set_device(0)
     table = binding.load_tuned()
     for name, probs, prec in workloads():
@@ -36,7 +40,7 @@ def main() -> int:
         del f
         ctx.close()
         torch.cuda.empty_cache()
-    with open(binding.TUNED_PATH, "w") as fh:
+    with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return 0
 

@@ -277,13 +277,17 @@ def test_graph_replay_matches_eager(B):
     C = B.Context(cfg, "fp32")
     x = C.initial_state()
     torch.cuda.synchronize()
-    ref = {n: C.step(x, n=n).clone() for n in (5, 6, 9)}
+    ref = {}
+    for n in (5, 6, 9):
+        C.set_seed(100 + n)
+        ref[n] = C.step(x, n=n).clone()
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         C.set_graph(True)
         out = torch.empty_like(x)
         for rep in range(3):
             for n in (5, 6, 9):
+                C.set_seed(100 + n)
                 C.step(x, out, n=n)
                 side.synchronize()
                 assert torch.equal(out, ref[n]), (rep, n)
