@@ -293,10 +293,12 @@ __global__ void __launch_bounds__(256)
     __shared__ AdjSlots S;
     __shared__ double cf[NSL][NCOEF];
     const Geo &g = A.g;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int gc = L / A.vsplit, split = L % A.vsplit;
-    const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gc)];
-    const int c = gc - I.cell0, ix = c % I.nx, iy = c / I.nx;
+    const int Lq = xcd_remap(blockIdx.x, gridDim.x);
+    const int gq = Lq / A.vsplit, split = Lq % A.vsplit;
+    const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gq)];
+    const int c = strip_cell(I, gq - I.cell0), ix = c % I.nx, iy = c / I.nx;
+    const int gc = I.cell0 + c;
+    const int L = gc * A.vsplit + split;  // (cell, chunk) index of the wall sums
     const bool per = I.kind == KIND_PER1 || I.kind == KIND_PER2;
     if (threadIdx.x < NSL) {
         const int sl = threadIdx.x;

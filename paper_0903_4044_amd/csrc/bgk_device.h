@@ -96,6 +96,31 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + (x < r ? x : r) + k;
 }
 
+// Visiting order of the cells of one instance for the stencil kernels.  The
+// columns of a 2D instance are cut into strips STRIP cells wide and each
+// strip is walked row by row, so the cells in flight on one XCD and their
+// y-neighbours (two rows either side) span a few strip widths of the visiting
+// order and stay in that XCD's L2; row-major order would put the y-neighbours
+// nx cells away and fetch every row from HBM several times.  1D instances
+// (ny = 1) map to themselves.  Returns the instance-local cell of position q.
+constexpr int STRIP = 16;
+
+__device__ __forceinline__ int strip_cell(const Inst &I, int q)
+{
+    const int W = I.nx < STRIP ? I.nx : STRIP;
+    const int span = W * I.ny;
+    const int nfull = I.nx / W;
+    if (q < nfull * span) {
+        const int k = q / span, r = q - k * span;
+        const int iy = r / W;
+        return iy * I.nx + k * W + (r - iy * W);
+    }
+    const int rem = I.nx - nfull * W;
+    const int r = q - nfull * span;
+    const int iy = r / rem;
+    return iy * I.nx + nfull * W + (r - iy * rem);
+}
+
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
 
 __device__ __forceinline__ float minmod3(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
@@ -128,6 +153,17 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x)
 __device__ __forceinline__ uint32_t pass_key(const uint32_t *pass, uint32_t stream)
 {
     return hash32(*pass * 2u + stream + 0x9e3779b9u);
+}
+
+// Stochastic rounding of x to float with 16 random bits r16, placed at the
+// top of the 29 bits below the float's last mantissa bit (the lower 13 bits
+// truncate: a bias under 2^-16 ulp).  One 32-bit hash serves two elements.
+__device__ __forceinline__ float round_stochastic16(double x, uint32_t r16)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    b += (unsigned long long)r16 << 13;
+    b &= ~((1ull << 29) - 1ull);
+    return (float)__longlong_as_double((long long)b);
 }
 
 // Stochastic rounding of x to float: add 29 uniform bits below the float's
@@ -646,11 +682,13 @@ __global__ void __launch_bounds__(256)
     // multiple of 8 keeps every workgroup on one XCD's contiguous range).
     const int nitems = A.ncells * A.vsplit;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int L = xcd_remap(item, nitems);
-    const int gc = L / A.vsplit, split = L % A.vsplit;
-    const int ii = find_inst(A.cell_prefix, A.ninst, gc);
+    const int Lq = xcd_remap(item, nitems);
+    const int gq = Lq / A.vsplit, split = Lq % A.vsplit;
+    const int ii = find_inst(A.cell_prefix, A.ninst, gq);
     const Inst &I = A.inst[ii];
-    const int c = gc - I.cell0;
+    const int c = strip_cell(I, gq - I.cell0);
+    const int gc = I.cell0 + c;
+    const int L = gc * A.vsplit + split;  // (cell, chunk) index of the partial sums
     const int ix = c % I.nx, iy = c / I.nx;
 
     if (threadIdx.x < NSLOT) {
@@ -682,7 +720,9 @@ __global__ void __launch_bounds__(256)
     const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
     const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;  // element index of (cell, 0) in the instance
     const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
-    const double c0d = sizeof(real) == 4 ? *reinterpret_cast<const double *>(sp + 2) : 0.0;  // centre entry's c0
+    // the centre entry's c0 - 1 as a two-float sum (float path)
+    const double c0m1 = sizeof(real) == 4 ? *reinterpret_cast<const double *>(sp + 2) - 1.0 : 0.0;
+    const float c0m1_hi = (float)c0m1, c0m1_lo = (float)(c0m1 - (double)c0m1_hi);
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
@@ -719,8 +759,9 @@ __global__ void __launch_bounds__(256)
         constexpr int NT = DIM == 1 ? 4 : 7;
         const Tap<real, VEC> *taps[7] = {&tc, &xa, &xb, &xd, &ya, &yb, &yd};
         // One jz: relax the loaded taps, stream, store, accumulate moments.
-        auto finish = [&](const V (&hv)[NT], int jz) {
-            const uint32_t zo = (uint32_t)jz * zstep;
+        // One jz: relax the loaded taps, stream, store, accumulate moments.
+        // zo is the byte offset of plane jz (jz * Nvx * Nvy elements).
+        auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo) {
             const V u0 = tc.relax(hv[0], jz);
             V dx = flux_diff<real, VEC>(xa.relax(hv[1], jz), xb.relax(hv[2], jz), u0, xd.relax(hv[3], jz), Cx, kx);
             V dy = 0;
@@ -728,13 +769,21 @@ __global__ void __launch_bounds__(256)
                 dy = flux_diff<real, VEC>(ya.relax(hv[4], jz), yb.relax(hv[5], jz), u0, yd.relax(hv[6], jz), Cy, ky);
             V r;
             if constexpr (sizeof(real) == 4) {
-                // the centre relaxation and the flux sum in FP64, one stochastic rounding
-                const double ta = (double)tc.tz[2 * jz], tb = (double)tc.tz[2 * jz + 1];
-                const uint32_t i0 = ecell + (uint32_t)jz * (uint32_t)g.npl + (uint32_t)p0;
+                // New value h + d with the increment d = (c0 - 1) h + M - fluxes
+                // formed in float (c0 - 1 as a two-float sum, so the relaxation
+                // keeps its mass to ~2^-48), then h + d in double and one
+                // stochastic rounding.  The increment's own rounding is
+                // relative to d, far below an ulp of h wherever d is small.
+                const real a = tc.tz[2 * jz], b = tc.tz[2 * jz + 1];
+                const uint32_t i0 = ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real);
+                uint32_t hb = 0;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const double g0 = c0d * (double)hv[0][e] + ((double)tc.l1[e] * ta + (double)tc.l2[e] * tb);
-                    r[e] = round_stochastic(g0 - ((double)dx[e] + (double)dy[e]), hash32((i0 + e) ^ key));
+                    const real M = tc.l1[e] * a + tc.l2[e] * b;
+                    const real d = __builtin_fmaf(c0m1_hi, hv[0][e], __builtin_fmaf(c0m1_lo, hv[0][e], M)) - (dx[e] + dy[e]);
+                    const uint32_t ie = i0 + (uint32_t)e;
+                    if (e == 0 || (ie & 1u) == 0) hb = hash32((ie >> 1) ^ key);
+                    r[e] = round_stochastic16((double)hv[0][e] + (double)d, (ie & 1u) ? (hb >> 16) : (hb & 0xffffu));
                 }
             } else {
                 r = u0 - dx - dy;
@@ -752,33 +801,60 @@ __global__ void __launch_bounds__(256)
             Az += vz * s;
             Azz += vz * vz * s;
         };
-        // Software pipeline: the loads of the next UNR jz values are issued
+        // Software pipeline: the loads of the next UNR jz planes are issued
         // before the current ones are relaxed and streamed, so every wave keeps
-        // one group of loads in flight while it computes.
+        // one group of loads in flight while it computes.  Plane offsets
+        // advance by additions; prefetches past the lane's last plane re-read
+        // it.  With two planes per stage the loop body is written twice over
+        // alternating register sets, so a prefetched value is consumed one
+        // stage later and never copied; with one plane per stage the plain
+        // rotation needs fewer registers (more waves per SIMD).
         const int zs = UNR * A.zr;
         int jz = z0 + zr;
         if (jz < z1) {
             const int zlast = z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);  // last jz of this lane's residue
-            V hv[UNR][NT];
+            const uint32_t zlast_off = (uint32_t)zlast * zstep, zr_off = (uint32_t)A.zr * zstep;
+            const uint32_t zs_off = (uint32_t)zs * zstep;
+            uint32_t zoff = (uint32_t)jz * zstep;
+            auto load_stage = [&](V (&h)[UNR][NT], uint32_t off) {
 #pragma unroll
-            for (int u = 0; u < UNR; ++u)
+                for (int u = 0; u < UNR; ++u) {
+                    const uint32_t o = min(off + (uint32_t)u * zr_off, zlast_off);
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    hv[u][t] = taps[t]->load(base, (uint32_t)min(jz + u * A.zr, zlast) * zstep);
-            for (; jz < z1; jz += zs) {
-                V hn[UNR][NT];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u)
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        hn[u][t] = taps[t]->load(base, (uint32_t)min(jz + zs + u * A.zr, zlast) * zstep);
-#pragma unroll
-                for (int u = 0; u < UNR; ++u)
-                    if (jz + u * A.zr < z1) finish(hv[u], jz + u * A.zr);
+                    for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(base, o);
+                }
+            };
+            auto compute_stage = [&](const V (&h)[UNR][NT], int j, uint32_t off) {
 #pragma unroll
                 for (int u = 0; u < UNR; ++u)
+                    if (j + u * A.zr < z1) finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off);
+            };
+            V ha[UNR][NT];
+            load_stage(ha, zoff);
+            if constexpr (UNR == 2) {
+                V hb[UNR][NT];
+                for (;;) {
+                    load_stage(hb, zoff + zs_off);
+                    compute_stage(ha, jz, zoff);
+                    jz += zs;
+                    zoff += zs_off;
+                    if (jz >= z1) break;
+                    load_stage(ha, zoff + zs_off);
+                    compute_stage(hb, jz, zoff);
+                    jz += zs;
+                    zoff += zs_off;
+                    if (jz >= z1) break;
+                }
+            } else {
+                for (; jz < z1; jz += zs, zoff += zs_off) {
+                    V hn[UNR][NT];
+                    load_stage(hn, zoff + zs_off);
+                    compute_stage(ha, jz, zoff);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) hv[u][t] = hn[u][t];
+                    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) ha[u][t] = hn[u][t];
+                }
             }
         }
 #pragma unroll
