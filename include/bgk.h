@@ -175,8 +175,11 @@ int bgk_timing(bgk_ctx *ctx, double *ms, int *launches);
  * (unbiased stochastic rounding), because round-to-nearest loses the
  * sub-ulp change per step of a nearly uniform, nearly Maxwellian region and
  * so freezes its slow drift.  The random bits are a hash of (element index
- * within its instance, rounding counter), so results do not depend on the
- * launch shape or on batching.  A call bgk_step(..., n, ...) uses counters
+ * within its instance, rounding counter): they do not depend on the launch
+ * shape or on batching (results still differ at rounding level between
+ * shapes that split a cell's moment sums differently).  The 16 random bits
+ * of an element sit at the top of the 29 bits a float drops from a double,
+ * so the rounding is unbiased to within 2^-16 ulp.  A call bgk_step(..., n, ...) uses counters
  * seed .. seed + n - 1 for its streaming passes and seed + n for its closing
  * relaxation, then advances the context's seed by n; bgk_set_rounding_seed
  * sets it (0 after bgk_init) so that a run can be repeated bit for bit.

@@ -132,8 +132,8 @@ __device__ __forceinline__ float minmod3(float a, float b) { return __builtin_am
 // per step there is far below half an ulp, so every step rounds back to the
 // same float and the slow drift of the FP64 dynamics is lost.  The random
 // bits come from a counter-based hash of (element index within its
-// instance, streaming pass), so results do not depend on launch shape or
-// batching and repeat exactly for the same rounding seed.
+// instance, streaming pass), so they do not depend on launch shape or
+// batching, and a run repeats exactly for the same rounding seed.
 
 // 32-bit integer hash ("lowbias32", C. Wellons, Prospecting for Hash
 // Functions, 2018): xorshift-multiply rounds with constants 0x7feb352d and
