@@ -97,8 +97,10 @@ typedef struct bgk_ctx bgk_ctx;
  * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
  * instance's dt, and allocates the context's device work space on the current
  * device.  precision: BGK_FP64 or BGK_FP32.
- * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3), BGK_E_UNSUPPORTED,
- * BGK_E_HIP.  On failure *out is NULL. */
+ * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3), BGK_E_UNSUPPORTED
+ * (also when one workgroup's table entries, 2 (Nvx + Nvy + Nvz) values per
+ * stencil slot, exceed the device's LDS per workgroup), BGK_E_HIP.  On
+ * failure *out is NULL. */
 int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out);
 
 /* Release the context and its device memory (synchronises the device). */
@@ -202,11 +204,13 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * moment, table and reduction in double); lam_n must not alias either input
  * (BGK_E_ALIAS).  grad_params is a device array of 2 * n_probs doubles that
  * the call ACCUMULATES into (zero it before the first step of a sweep).
- * Minmod branch decisions are those of the forward map at f_n; at a kink
- * (equal slopes or a zero product) the branch taken by the forward
- * limiter's own tie rule is differentiated.  The first call allocates the
- * context's reverse-sweep work space (three extra f buffers); BGK_E_HIP if
- * that fails.  Asynchronous on `stream`. */
+ * Minmod branch decisions are those of the forward map at f_n: a limited
+ * slope is differentiated as 0 unless both differences have the same strict
+ * sign, else as the smaller-magnitude difference (the backward one on a tie
+ * of magnitudes).  The first call allocates the context's reverse-sweep work
+ * space (two extra f buffers and per-cell coefficients); BGK_E_HIP if that
+ * fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9 (1D) table entries per
+ * workgroup exceed the device's LDS.  Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *stream);
 

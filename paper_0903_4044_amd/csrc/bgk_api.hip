@@ -62,6 +62,7 @@ struct bgk_ctx {
     double *mom = nullptr;     // ncells * 5 (bgk_check)
     // reverse sweep (allocated at the first bgk_step_adjoint / bgk_lid_shear call)
     bool adj_ready = false;
+    bool adjoint_fits = true;  // reverse-sweep tables fit the device's LDS
     void *adj_h = nullptr, *adj_hb = nullptr;                     // f-sized: h = S(R_a f), abar
     double *info_f = nullptr, *info_h = nullptr;                  // ncells * NINFO
     double *adj_sums = nullptr, *adj_wsum = nullptr;              // ncells * vsplit_max * (NSUM, NWALL)
@@ -309,6 +310,25 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     g.ty2 = g.tx2 + g.nvx;
     g.tz = (g.ty2 + g.nvy + 1) & ~1;
     g.pe = (g.tz + 2 * g.nvz + 3) & ~3;
+    {
+        // LDS per workgroup: the table entries of every stencil slot (13 in
+        // 2D, 7 in 1D for the step; 17 and 9 for the reverse sweep) plus a
+        // few KB of static buffers
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
+            lds_max <= 0)
+            lds_max = 65536;
+        const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
+        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack, adj = (c->dim == 2 ? 17 : 9) * entry + slack;
+        if (fwd > (size_t)lds_max) {
+            char b[160];
+            snprintf(b, sizeof b, "velocity grid needs %zu bytes of LDS per workgroup; the device allows %d", fwd,
+                     lds_max);
+            delete c;
+            return fail(nullptr, BGK_E_UNSUPPORTED, b);
+        }
+        c->adjoint_fits = adj <= (size_t)lds_max;
+    }
 
     c->h_cell_prefix.push_back(0);
     c->h_pseudo_prefix.push_back(0);
@@ -706,6 +726,8 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (!ctx) return BGK_E_INVALID;
     if (!f_n || !lam_next || !lam_n || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_step_adjoint: NULL buffer");
     if (lam_n == f_n || lam_n == lam_next) return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: lam_n must not alias inputs");
+    if (!ctx->adjoint_fits)
+        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
                                       : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);

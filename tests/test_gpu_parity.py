@@ -231,6 +231,35 @@ def test_fp32_tracks_slow_relaxation_drift(B, oracle_mod):
     assert max(e) <= 5e-7, (e, drift)
 
 
+@pytest.mark.parametrize("kind,nv,prec", [("periodic2d", (128, 128, 2), "fp64"), ("cavity", (128, 2, 128), "fp64"),
+                                          ("shock", (128, 128, 4), "fp32"), ("cavity", (2, 128, 128), "fp32")])
+def test_largest_velocity_axis(B, oracle_mod, kind, nv, prec):
+    """128 points on a velocity axis (the largest the library takes): the
+    table entries of a workgroup are largest, and the step still matches."""
+    cfg = small(kind, nx=3, ny=2, nv=nv, vlo=(-6.0,) * 3, vhi=(6.0,) * 3)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed_initial(O, seed=70)
+    ref = O.step(f0, 2)
+    C = B.Context(cfg, prec, tune="off")
+    y = C.step(to_dev(f0, C.dtype), n=2)
+    if prec == "fp64":
+        check_fp64(y, ref, O, cfg)
+        lam = inputs.uniform(O.shape, seed=71, lo=-1, hi=1)
+        lref, gref = O.step_adjoint(f0, lam)
+        got, _ = C.step_adjoint(to_dev(f0, torch.float64), to_dev(lam, torch.float64))
+        got = got.cpu().numpy().reshape(O.shape)
+        assert np.max(np.abs(got - lref)) <= 1e-12 * np.max(np.abs(lref))
+    else:
+        e = moment_errors(C.moments(y).cpu().numpy(), O.moments(ref), cfg)
+        assert max(e) <= 1e-5, e
+
+
+def test_velocity_axis_above_limit_rejected(B):
+    with pytest.raises(B.BGKError) as ei:
+        B.Context(small("shock", nv=(130, 8, 8)), "fp64")
+    assert ei.value.code == B.E_UNSUPPORTED
+
+
 # --------------------------------------------------------------- errors
 
 
