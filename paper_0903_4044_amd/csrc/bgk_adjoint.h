@@ -251,14 +251,14 @@ __device__ __forceinline__ MuTap<real, VEC> mu_tap(const Geo &g, const double *c
 
 // Branch of minmod(a, b): 0 unless a and b have the same strict sign, then
 // 1 if |a| < |b| (slope = a, the forward difference), else 2 (slope = b).
-// Signs are compared directly: the product a b of two Maxwellian-tail slopes
-// underflows in float, while the forward limiter (a median) does not.
+// It is read off the forward limiter's own value m = median(a, b, 0): m is
+// 0, or equal to b (taken on a tie |a| = |b|), or else equal to a.  (The
+// product a b of two Maxwellian-tail slopes would underflow in float.)
 template <typename real>
 __device__ __forceinline__ int mm_branch(real a, real b)
 {
-    const bool same = (a > (real)0 && b > (real)0) || (a < (real)0 && b < (real)0);
-    if (!same) return 0;
-    return fabs(a) < fabs(b) ? 1 : 2;
+    const real m = minmod3(a, b);
+    return m == (real)0 ? 0 : (m == b ? 2 : 1);
 }
 
 // One direction's contribution (values in upwind order, see above).

@@ -221,6 +221,24 @@ static void drop_graphs(bgk_ctx *c)
     c->chunks.clear();
 }
 
+// Smallest jz residue count zr that makes the lane tasks (Nvx/vec) * Nvy * zr
+// fill whole waves, and the largest block (a multiple of 64 up to 256)
+// dividing the task count.
+static void task_shape(const Geo &g, int vec, int zchunk, int *zr_out, int *block_out)
+{
+    const int groups = g.npl / vec;
+    *zr_out = 1;
+    *block_out = 256;
+    for (int zr = 1; zr <= std::max(1, zchunk / 2); ++zr) {
+        const int t = groups * zr;
+        if (t % 64) continue;
+        *zr_out = zr;
+        for (int b = 256; b >= 64; b -= 64)
+            if (t % b == 0) { *block_out = b; break; }
+        break;
+    }
+}
+
 static void set_shape(bgk_ctx *c, int vec, int unroll, int vsplit, int persist = 0)
 {
     drop_graphs(c);
@@ -229,18 +247,7 @@ static void set_shape(bgk_ctx *c, int vec, int unroll, int vsplit, int persist =
     c->unroll = unroll;
     c->persist = persist;
     c->vsplit = std::max(1, std::min(c->vsplit_max, vsplit));
-    const int zchunk = g.nvz / c->vsplit;
-    const int groups = g.npl / c->vec;
-    c->zr = 1;
-    c->sblock = 256;
-    for (int zr = 1; zr <= std::max(1, zchunk / 2); ++zr) {
-        const int t = groups * zr;
-        if (t % 64) continue;
-        c->zr = zr;
-        for (int b = 256; b >= 64; b -= 64)
-            if (t % b == 0) { c->sblock = b; break; }
-        break;
-    }
+    task_shape(g, c->vec, g.nvz / c->vsplit, &c->zr, &c->sblock);
 }
 
 static int vsplit_for(const bgk_ctx *c, int target_wg)
@@ -666,15 +673,21 @@ static void adj_stream_dispatch(bgk_ctx *c, const void *f, const void *lam, hipS
     const real *p0 = params_buf<real>(c, 0);
     const real *fr = (const real *)f, *lr = (const real *)lam;
     real *o = (real *)c->adj_hb;
-    if (c->vec == 4 && sizeof(real) == 4)
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 4>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
-                           c->adj_coef, o, c->adj_wsum);
-    else if (c->vec == 2)
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 2>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
-                           c->adj_coef, o, c->adj_wsum);
+    // its own lane-task shape (measured on the 64^2 cavity: one jx per lane
+    // task for float, two for double where the grid allows)
+    const int vec = (sizeof(real) == 8 && vec_valid(c, 2)) ? 2 : 1;
+    Args a = make_args(c);
+    int block = 256;
+    task_shape(c->geo, vec, c->geo.nvz / c->vsplit, &a.zr, &block);
+    if (vec == 4)
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 4>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
+                           c->adj_wsum);
+    else if (vec == 2)
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 2>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
+                           c->adj_wsum);
     else
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 1>), dim3(nb), dim3(256), lds, s, make_args(c), fr, p0, lr,
-                           c->adj_coef, o, c->adj_wsum);
+        hipLaunchKernelGGL((k_adj_stream<real, DIM, 1>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
+                           c->adj_wsum);
 }
 
 // One reverse step.  The first streaming pass of the step is recomputed
