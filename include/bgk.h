@@ -145,8 +145,11 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
  * walk the items of all instances (one persistent launch for a batch).
  * bgk_init picks a default.  bgk_autotune times every valid shape on the
  * state f (device, f_elems elements, read only; synchronises the stream) and
- * keeps the fastest; bgk_get_launch reports the shape in use and, after
- * autotuning, the streaming kernel's time in microseconds; bgk_set_launch
+ * keeps the fastest by the steady time of a real step (streaming pass and
+ * table preparation, (10 steps - 2 steps) / 8); it borrows a temporary
+ * f-sized device buffer for the steps' output during the call (if that
+ * allocation fails it times bare streaming passes over f instead); bgk_get_launch reports the shape in use and, after
+ * autotuning, the measured time per step in microseconds; bgk_set_launch
  * applies a shape (BGK_E_INVALID if not valid for the context). */
 int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream);
 int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us);

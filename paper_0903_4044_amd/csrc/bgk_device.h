@@ -666,7 +666,9 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // jz modulo ZR); it loops over jz = z0 + zr, z0 + zr + ZR, ... < z1.  The host
 // picks VEC so that all v_x of a group share a sign, and ZR so that the task
 // count fills whole waves.
-template <typename real, int DIM, int VEC, int UNR>
+// NTSTORE: store the output non-temporally (chosen by the host when the working
+// set exceeds the last-level cache; a plain store otherwise).
+template <typename real, int DIM, int VEC, int UNR, bool NTSTORE>
 __global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
@@ -788,8 +790,9 @@ __global__ void __launch_bounds__(256)
             } else {
                 r = u0 - dx - dy;
             }
-            __builtin_nontemporal_store(r, reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo +
-                                                                  (uint32_t)(p0 * sizeof(real))));
+            V *op = reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo + (uint32_t)(p0 * sizeof(real)));
+            if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
+            else *op = r;
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
