@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="",
+                    help="comma-separated subset of the extra workloads to run (default: all)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no HIP events around the streaming launches (roofline not reported)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
@@ -234,7 +236,10 @@ def main():
                 ("cavity_128_fp32", [inputs.config("cavity_128_fp32")], "fp32", 200, 10, False),
                 ("batch_64_cavities_fp32", inputs.batch_cavities(), "fp32", 20, 2, False),
                 ("batch_64_cavities_fp32_graph", inputs.batch_cavities(), "fp32", 20, 2, True)]
+        wanted = set(x for x in args.extras.split(",") if x)
         for name, probs, p, steps, warm, graph in runs:
+            if wanted and name not in wanted:
+                continue
             s, k, pts, shp = run_workload(binding, torch, probs, p, steps, warm, True, True, graph)
             e = {"updates_per_s": pts * steps / s, "steps": steps, "points": pts, "launch": shp,
                  "precision": p, "graph": graph}
@@ -245,6 +250,8 @@ def main():
             print(f"# {name}: {e['updates_per_s']:.4g} updates/s" +
                   (f", {e['achieved_GBs']:.0f} GB/s" if "achieved_GBs" in e else ""), file=sys.stderr, flush=True)
         for p in ("fp32", "fp64"):
+            if wanted and f"adjoint_cavity_64_{p}" not in wanted:
+                continue
             fwd, bwd, pts, n = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
             e = {"updates_per_s": pts * n / (fwd + bwd), "steps": n, "points": pts, "precision": p,
                  "forward_s": fwd, "reverse_s": bwd, "reverse_updates_per_s": pts * n / bwd,
@@ -253,10 +260,11 @@ def main():
             extras[f"adjoint_cavity_64_{p}"] = e
             print(f"# adjoint_cavity_64_{p}: {e['updates_per_s']:.4g} updates/s (forward {fwd * 1e3:.1f} ms, "
                   f"reverse {bwd * 1e3:.1f} ms)", file=sys.stderr, flush=True)
-        plain = extras["shock_m1.5_fp64"]["updates_per_s"]
-        extras["plain_fp64_updates_per_s"] = plain
-        extras["ratio_vs_plain_fp64"] = {k: v["updates_per_s"] / plain for k, v in extras.items()
-                                         if isinstance(v, dict) and "updates_per_s" in v}
+        if "shock_m1.5_fp64" in extras:
+            plain = extras["shock_m1.5_fp64"]["updates_per_s"]
+            extras["plain_fp64_updates_per_s"] = plain
+            extras["ratio_vs_plain_fp64"] = {k: v["updates_per_s"] / plain for k, v in extras.items()
+                                             if isinstance(v, dict) and "updates_per_s" in v}
         out["extras"] = extras
 
     if not args.no_cpu_baseline:
