@@ -326,7 +326,9 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
             lds_max <= 0)
             lds_max = 65536;
         const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
-        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack, adj = (c->dim == 2 ? 17 : 9) * entry + slack;
+        const size_t roles = (size_t)(c->dim == 2 ? 4 * 7 : 2 * 4) * g.nvz * 2 * c->esize;
+        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + roles + slack;
+        const size_t adj = (c->dim == 2 ? 17 : 9) * entry + slack;
         if (fwd > (size_t)lds_max) {
             char b[160];
             snprintf(b, sizeof b, "velocity grid needs %zu bytes of LDS per workgroup; the device allows %d", fwd,
@@ -485,21 +487,36 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
 // 256 MB last-level cache (MALL) plain stores leave the output there (the
 // 256 x 32^3 FP64 shock runs 30 us instead of 43 us per pass); larger working
 // sets use non-temporal stores, measured faster for them.
+// LDS of the streaming kernel's role-ordered z-tables (one-residue shapes):
+// [sign combination][jz][tap role][2] values.
+static size_t role_table_bytes(const bgk_ctx *c)
+{
+    const int combos = c->dim == 2 ? 4 : 2, roles = c->dim == 2 ? 7 : 4;
+    return (size_t)combos * c->geo.nvz * roles * 2 * c->esize;
+}
+
 static bool stream_nt(const bgk_ctx *c)
 {
     return 2.0 * (double)c->f_elems * (double)c->esize > 192.0 * (1 << 20);
 }
 
+template <typename real, int DIM, int VEC, int UNR, bool NTS>
+static void stream_kernel_z(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
+{
+    const real *p = (const real *)params_buf<real>(c, c->pass_parity);
+    if (c->zr == 1)  // every lane of a wave on the same plane: role-ordered z-tables after the slots
+        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, NTS, true>), dim3(nb), dim3(c->sblock),
+                           lds + role_table_bytes(c), s, make_args(c), (const real *)src, (real *)dst, p, c->partial);
+    else
+        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, NTS, false>), dim3(nb), dim3(c->sblock), lds, s,
+                           make_args(c), (const real *)src, (real *)dst, p, c->partial);
+}
+
 template <typename real, int DIM, int VEC, int UNR>
 static void stream_kernel_u(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
-    const real *p = (const real *)params_buf<real>(c, c->pass_parity);
-    if (stream_nt(c))
-        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, true>), dim3(nb), dim3(c->sblock), lds, s, make_args(c),
-                           (const real *)src, (real *)dst, p, c->partial);
-    else
-        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, false>), dim3(nb), dim3(c->sblock), lds, s, make_args(c),
-                           (const real *)src, (real *)dst, p, c->partial);
+    if (stream_nt(c)) stream_kernel_z<real, DIM, VEC, UNR, true>(c, nb, lds, src, dst, s);
+    else stream_kernel_z<real, DIM, VEC, UNR, false>(c, nb, lds, src, dst, s);
 }
 
 template <typename real, int DIM, int VEC>

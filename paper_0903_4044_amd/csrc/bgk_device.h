@@ -626,6 +626,8 @@ struct Tap {
         const real a = tz[2 * jz], b = tz[2 * jz + 1];
         return c0 * h + (l1 * a + l2 * b);
     }
+    // same arithmetic with the plane's table values given
+    __device__ __forceinline__ V relax_ab(V h, real a, real b) const { return c0 * h + (l1 * a + l2 * b); }
 };
 
 template <typename real, int VEC>
@@ -668,7 +670,13 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // count fills whole waves.
 // NTSTORE: store the output non-temporally (chosen by the host when the working
 // set exceeds the last-level cache; a plain store otherwise).
-template <typename real, int DIM, int VEC, int UNR, bool NTSTORE>
+// ZU: one jz residue (ZR = 1), so all lanes of a wave walk the same plane.
+// The plane's byte offset is then wave-uniform: it goes into the scalar base
+// of the loads (no per-tap vector address arithmetic), and the z-tables of
+// the taps are re-laid out in LDS as [sign combination][jz][tap role][2] so
+// that one vector address per plane reaches every tap's pair through
+// immediate offsets.
+template <typename real, int DIM, int VEC, int UNR, bool NTSTORE, bool ZU>
 __global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
@@ -712,6 +720,21 @@ __global__ void __launch_bounds__(256)
         sp[t] = params[(long long)SI.par[s] * g.pe + o];
     }
     __syncthreads();
+    constexpr int NROLE = DIM == 1 ? 4 : 7;   // centre, x (-2, -1, +1), y (-2, -1, +1)
+    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
+    real *tzr = sp + NSLOT * g.pe;           // [combo][jz][role][2]
+    if constexpr (ZU) {
+        const int n = NCOMBO * g.nvz * NROLE;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const int role = t % NROLE, jz = (t / NROLE) % g.nvz, combo = t / (NROLE * g.nvz);
+            const int sx = combo & 1, sy = combo >> 1;
+            const int slot = role == 0 ? 0 : role <= 3 ? 1 + 3 * sx + (role - 1) : 7 + 3 * sy + (role - 4);
+            const real *E = sp + slot * g.pe + g.tz + 2 * jz;
+            tzr[2 * t] = E[0];
+            tzr[2 * t + 1] = E[1];
+        }
+        __syncthreads();
+    }
 
     const real *base = src + I.f0;
     real *outb = dst + I.f0;
@@ -728,7 +751,7 @@ __global__ void __launch_bounds__(256)
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
-        const int pg = task % ngroups, zr = task / ngroups;
+        const int pg = task % ngroups, zr = ZU ? 0 : task / ngroups;
         const int jy = pg / ngx, jx0 = (pg - jy * ngx) * VEC;
         const int p0 = jy * g.nvx + jx0;
         V Cx, kx;
@@ -760,15 +783,35 @@ __global__ void __launch_bounds__(256)
         double Az = 0.0, Azz = 0.0;
         constexpr int NT = DIM == 1 ? 4 : 7;
         const Tap<real, VEC> *taps[7] = {&tc, &xa, &xb, &xd, &ya, &yb, &yd};
+        // this lane's z-table rows (ZU): combination of the signs of v_x, v_y
+        const int combo = DIM == 1 ? sx : sx + 2 * (vy > 0.0 ? 0 : 1);
+        const real *tzl = tzr + combo * g.nvz * NROLE * 2;
         // One jz: relax the loaded taps, stream, store, accumulate moments.
         // One jz: relax the loaded taps, stream, store, accumulate moments.
         // zo is the byte offset of plane jz (jz * Nvx * Nvy elements).
         auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo) {
-            const V u0 = tc.relax(hv[0], jz);
-            V dx = flux_diff<real, VEC>(xa.relax(hv[1], jz), xb.relax(hv[2], jz), u0, xd.relax(hv[3], jz), Cx, kx);
+            real ta[NT], tb[NT];  // the taps' z-table values at plane jz
+            if constexpr (ZU) {
+                const real *row = tzl + jz * (NROLE * 2);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    ta[t] = row[2 * t];
+                    tb[t] = row[2 * t + 1];
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    ta[t] = taps[t]->tz[2 * jz];
+                    tb[t] = taps[t]->tz[2 * jz + 1];
+                }
+            }
+            const V u0 = tc.relax_ab(hv[0], ta[0], tb[0]);
+            V dx = flux_diff<real, VEC>(xa.relax_ab(hv[1], ta[1], tb[1]), xb.relax_ab(hv[2], ta[2], tb[2]), u0,
+                                        xd.relax_ab(hv[3], ta[3], tb[3]), Cx, kx);
             V dy = 0;
             if constexpr (DIM == 2)
-                dy = flux_diff<real, VEC>(ya.relax(hv[4], jz), yb.relax(hv[5], jz), u0, yd.relax(hv[6], jz), Cy, ky);
+                dy = flux_diff<real, VEC>(ya.relax_ab(hv[4], ta[4], tb[4]), yb.relax_ab(hv[5], ta[5], tb[5]), u0,
+                                          yd.relax_ab(hv[6], ta[6], tb[6]), Cy, ky);
             V r;
             if constexpr (sizeof(real) == 4) {
                 // New value h + d with the increment d = (c0 - 1) h + M - fluxes
@@ -776,7 +819,7 @@ __global__ void __launch_bounds__(256)
                 // keeps its mass to ~2^-48), then h + d in double and one
                 // stochastic rounding.  The increment's own rounding is
                 // relative to d, far below an ulp of h wherever d is small.
-                const real a = tc.tz[2 * jz], b = tc.tz[2 * jz + 1];
+                const real a = ta[0], b = tb[0];
                 const uint32_t i0 = ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real);
                 uint32_t hb = 0;
 #pragma unroll
@@ -823,8 +866,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const uint32_t o = min(off + (uint32_t)u * zr_off, zlast_off);
+                    if constexpr (ZU) {
+                        // wave-uniform plane offset folded into the scalar base
+                        const real *bz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) +
+                                                                        __builtin_amdgcn_readfirstlane(o));
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(base, o);
+                        for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(bz, 0u);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(base, o);
+                    }
                 }
             };
             auto compute_stage = [&](const V (&h)[UNR][NT], int j, uint32_t off) {
