@@ -145,9 +145,22 @@ def run_adjoint(binding, torch, cfg, precision, every=20):
     return fwd, bwd, points, nsteps
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, budget_s: float):
-    """The FP64 oracle on the same grid: one step, then as many as fit in the
-    budget; returns updates/s and the sample description."""
+    """The FP64 oracle on the same grid: one untimed step, then as many steps
+    as fit in the budget on all host threads, then (a third of the budget)
+    on one thread, the paper's CPU comparison; returns updates/s and the
+    sample description."""
+    import ctypes
     import oracle
     O = oracle.Oracle(cfg)
     f = O.initial_state()
@@ -159,9 +172,21 @@ def cpu_baseline(cfg, budget_s: float):
     O.step(f, n)
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-    return {"value": O.ncell * O.nvel * n / t, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} time steps of the full {O.ncell} x {O.nvel} grid in FP64 after one untimed step "
-                      f"({t:.1f} s)"}
+    out = {"value": O.ncell * O.nvel * n / t, "unit": "updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} time steps of the full {O.ncell} x {O.nvel} grid in FP64 after one untimed step "
+                     f"({t:.1f} s)", "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    try:  # the oracle's OpenMP runtime: same library in this process
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        O.step(f, 1)
+        t1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": O.ncell * O.nvel / t1, "unit": "updates/s",
+                                "sample": f"1 time step of the full grid on 1 thread ({t1:.1f} s)"}
+    except OSError:
+        pass
+    return out
 
 
 def main():
