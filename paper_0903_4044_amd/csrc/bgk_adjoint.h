@@ -41,7 +41,7 @@ __global__ void k_relax_info(Args A, const double *__restrict__ partial, double 
     Relax r;
     moments_from_raw(raw, &r);
     const double tau = which == 0 ? (I.strang ? 0.5 * I.dt : 0.0) : (I.strang ? 0.5 * I.dt : I.dt);
-    const double nu = r.n * pow(r.T, 1.0 - I.omega) / I.kn;
+    const double nu = r.n * (I.omega == 0.5 ? sqrt(r.T) : pow(r.T, 1.0 - I.omega)) / I.kn;
     double *o = info + (long long)c * NINFO;
     o[0] = r.n;
     o[1] = r.V[0];
@@ -70,7 +70,7 @@ __device__ __forceinline__ void build_phi(const Geo &g, const double *in, PhiTab
         const double d = vnode(g, a, k) - in[1 + a];
         T.e[a][k] = exp(-d * d / in[4]);
     }
-    if (threadIdx.x == 0) T.P = in[0] * pow(M_PI * in[4], -1.5);
+    if (threadIdx.x == 0) T.P = in[0] * pi_t_m32(in[4]);
     __syncthreads();
 }
 
@@ -620,7 +620,7 @@ __device__ __forceinline__ void lid_constants(const Geo &g, const Inst &I, doubl
                                               double *Dp)
 {
     double k = 0, d = 0, kp = 0, dp = 0;
-    const double pw = pow(M_PI * I.tw, -1.5);
+    const double pw = pi_t_m32(I.tw);
     for (long long j = threadIdx.x & 63; j < g.nv; j += 64) {
         const int jx = (int)(j % g.nvx), jy = (int)((j / g.nvx) % g.nvy), jz = (int)(j / g.npl);
         const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy), vz = vnode(g, 2, jz);

@@ -314,11 +314,20 @@ __device__ __forceinline__ void moments_from_raw(const double *raw, Relax *r)
     r->T = 2.0 / 3.0 * (raw[4] / raw[0] - (r->V[0] * r->V[0] + r->V[1] * r->V[1] + r->V[2] * r->V[2]));
 }
 
+// (pi T)^(-3/2) as a square root and a division (no pow).
+__device__ __forceinline__ double pi_t_m32(double T)
+{
+    const double pt = M_PI * T;
+    return 1.0 / (pt * sqrt(pt));
+}
+
 __device__ __forceinline__ void finish_relax(const Inst &I, double tau, Relax *r)
 {
-    const double nu = r->n * pow(r->T, 1.0 - I.omega) / I.kn;
+    // T^(1 - omega): a square root for omega = 1/2 (every workload), pow otherwise
+    const double tp = I.omega == 0.5 ? sqrt(r->T) : pow(r->T, 1.0 - I.omega);
+    const double nu = r->n * tp / I.kn;
     r->a = -expm1(-nu * tau);
-    r->P = r->n * pow(M_PI * r->T, -1.5);
+    r->P = r->n * pi_t_m32(r->T);
 }
 
 __device__ __forceinline__ double wave_sum(double x)
@@ -342,8 +351,10 @@ __device__ __forceinline__ void lane_tables(const Geo &g, const double V[3], dou
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int k = lane + 64 * s;
+            t.e[a][s] = 0.0;
+            if (64 * s >= nv_of(g, a)) continue;  // wave-uniform: no second slot below 65 points
             const double d = vnode(g, a, k) - V[a];
-            t.e[a][s] = k < nv_of(g, a) ? exp(-d * d / T) : 0.0;
+            if (k < nv_of(g, a)) t.e[a][s] = exp(-d * d / T);
         }
 }
 
@@ -512,7 +523,7 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
         const double V[3] = {st[1], 0.0, 0.0};
         Tables t;
         lane_tables(g, V, st[2], t);
-        write_entry<real>(g, E, 0.0, st[0] * pow(M_PI * st[2], -1.5), t, 0.0, z);
+        write_entry<real>(g, E, 0.0, st[0] * pi_t_m32(st[2]), t, 0.0, z);
         return;
     }
     // Diffuse wall face, Eq. (bc_cavity): ghost = n_W Phi_W for velocities
@@ -541,7 +552,7 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     double flux = C.c0 * hraw;
     if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * C.s1[b2][0];
     if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * C.s2[b2][0];
-    const double pw = pow(M_PI * I.tw, -1.5);
+    const double pw = pi_t_m32(I.tw);
     const double den = pw * g.dV * out_w * ow * sw[b2][0];
     (void)b1;
     write_entry<real>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
@@ -971,7 +982,7 @@ __global__ void __launch_bounds__(256) k_init(Args A, real *__restrict__ f)
         const double *st = x < 0.0 ? I.up : I.dn;
         n = st[0]; V = st[1]; T = st[2];
     }
-    const double P = n * pow(M_PI * T, -1.5);
+    const double P = n * pi_t_m32(T);
     const long long off = I.f0 + (long long)c * g.nv;
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
