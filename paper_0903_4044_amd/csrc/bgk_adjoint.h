@@ -281,7 +281,10 @@ __device__ __forceinline__ real direction_adjoint(real um2, real um1, real u0, r
 // S_gamma' = sum gamma dPhi_W/dT_w over the emitted velocities, where
 // gamma = C mu(0) + C k [b0 = b] (mu(0) - mu(1)) is the adjoint of that
 // velocity's emitted ghost value per unit n_W.
-template <typename real, int DIM, int VEC>
+// ZU (one jz residue, all lanes of a wave on one plane): as in the forward
+// kernel, the plane offset goes into the scalar base of the loads and the f
+// taps' z-tables are read from a role-ordered LDS copy.
+template <typename real, int DIM, int VEC, bool ZU>
 __global__ void __launch_bounds__(256)
     k_adj_stream(Args A, const real *__restrict__ f, const real *__restrict__ params, const real *__restrict__ lam,
                  const double *__restrict__ coef, real *__restrict__ out, double *__restrict__ wsum)
@@ -325,6 +328,21 @@ __global__ void __launch_bounds__(256)
         cf[sl][q] = S.mucell[sl] >= 0 ? coef[(long long)(I.cell0 + S.mucell[sl]) * NCOEF + q] : 0.0;
     }
     __syncthreads();
+    constexpr int NROLE = DIM == 1 ? 5 : 9;   // centre, x (-2, -1, +1, +2), y (-2, -1, +1, +2)
+    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
+    real *tzr = sp + NSL * g.pe;             // [combo][jz][role][2]
+    if constexpr (ZU) {
+        const int n = NCOMBO * g.nvz * NROLE;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const int role = t % NROLE, jz = (t / NROLE) % g.nvz, combo = t / (NROLE * g.nvz);
+            const int sx = combo & 1, sy = combo >> 1;
+            const int slot = role == 0 ? 0 : role <= 4 ? 1 + 4 * sx + (role - 1) : 9 + 4 * sy + (role - 5);
+            const real *E = sp + slot * g.pe + g.tz + 2 * jz;
+            tzr[2 * t] = E[0];
+            tzr[2 * t + 1] = E[1];
+        }
+        __syncthreads();
+    }
 
     const real *fb = f + I.f0;
     const real *lb = lam + I.f0;
@@ -341,7 +359,7 @@ __global__ void __launch_bounds__(256)
     double ws[NWALL] = {0, 0, 0, 0, 0, 0, 0, 0};
 
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
-        const int pg = task % ngroups, zr = task / ngroups;
+        const int pg = task % ngroups, zr = ZU ? 0 : task / ngroups;
         const int jy = pg / ngx, jx0 = (pg - jy * ngx) * VEC;
         const int p0 = jy * g.nvx + jx0;
         V Cx, kx;
@@ -352,6 +370,7 @@ __global__ void __launch_bounds__(256)
         }
         const double vy = vnode(g, 1, jy);
         const int sx = vnode(g, 0, jx0) > 0.0 ? 0 : 1;
+        const real *tzl = tzr + (DIM == 1 ? sx : sx + 2 * (vy > 0.0 ? 0 : 1)) * g.nvz * NROLE * 2;
         const int bx = 1 + 4 * sx;
         const Tap<real, VEC> tc = input_tap<real, VEC>(g, sp, S.cell[0], p0, jx0, jy);
         const Tap<real, VEC> xa = input_tap<real, VEC>(g, sp + (bx + 0) * g.pe, S.cell[bx + 0], p0, jx0, jy);
@@ -391,14 +410,24 @@ __global__ void __launch_bounds__(256)
             const uint32_t zo = (uint32_t)jz * zstep;
             const double vzd = vnode(g, 2, jz);
             const real vz = (real)vzd;
-            const V u0 = tc.relax(tc.load(fb, zo), jz);
-            const V m0 = mc.value(mc.load(lb, zo), vz);
+            // plane bases: wave-uniform under ZU (folded into the scalar base)
+            const uint32_t zb = ZU ? __builtin_amdgcn_readfirstlane(zo) : 0u, zv = ZU ? 0u : zo;
+            const real *fz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(fb) + zb);
+            const real *lz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(lb) + zb);
+            // relaxed f at a tap: z-table pair from the role rows (ZU) or the tap's entry
+            const real *row = tzl + jz * (NROLE * 2);
+            auto rl = [&](const Tap<real, VEC> &t, int role, V h) -> V {
+                if constexpr (ZU) return t.relax_ab(h, row[2 * role], row[2 * role + 1]);
+                else return t.relax(h, jz);
+            };
+            const V u0 = rl(tc, 0, tc.load(fz, zv));
+            const V m0 = mc.value(mc.load(lz, zv), vz);
             V r = m0;
             {
-                const V um2 = xa.relax(xa.load(fb, zo), jz), um1 = xb.relax(xb.load(fb, zo), jz);
-                const V u1 = xd.relax(xd.load(fb, zo), jz), u2 = xe.relax(xe.load(fb, zo), jz);
-                const V mm1 = mxb.value(mxb.load(lb, zo), vz), m1 = mxd.value(mxd.load(lb, zo), vz);
-                const V m2 = mxe.value(mxe.load(lb, zo), vz);
+                const V um2 = rl(xa, 1, xa.load(fz, zv)), um1 = rl(xb, 2, xb.load(fz, zv));
+                const V u1 = rl(xd, 3, xd.load(fz, zv)), u2 = rl(xe, 4, xe.load(fz, zv));
+                const V mm1 = mxb.value(mxb.load(lz, zv), vz), m1 = mxd.value(mxd.load(lz, zv), vz);
+                const V m2 = mxe.value(mxe.load(lz, zv), vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],
@@ -421,10 +450,10 @@ __global__ void __launch_bounds__(256)
                 }
             }
             if constexpr (DIM == 2) {
-                const V um2 = ya.relax(ya.load(fb, zo), jz), um1 = yb.relax(yb.load(fb, zo), jz);
-                const V u1 = yd.relax(yd.load(fb, zo), jz), u2 = ye.relax(ye.load(fb, zo), jz);
-                const V mm1 = myb.value(myb.load(lb, zo), vz), m1 = myd.value(myd.load(lb, zo), vz);
-                const V m2 = mye.value(mye.load(lb, zo), vz);
+                const V um2 = rl(ya, 5, ya.load(fz, zv)), um1 = rl(yb, 6, yb.load(fz, zv));
+                const V u1 = rl(yd, 7, yd.load(fz, zv)), u2 = rl(ye, 8, ye.load(fz, zv));
+                const V mm1 = myb.value(myb.load(lz, zv), vz), m1 = myd.value(myd.load(lz, zv), vz);
+                const V m2 = mye.value(mye.load(lz, zv), vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],

@@ -63,6 +63,7 @@ struct bgk_ctx {
     // reverse sweep (allocated at the first bgk_step_adjoint / bgk_lid_shear call)
     bool adj_ready = false;
     bool adjoint_fits = true;  // reverse-sweep tables fit the device's LDS
+    int lds_max = 65536;       // device LDS per workgroup (bytes)
     void *adj_h = nullptr, *adj_hb = nullptr;                     // f-sized: h = S(R_a f), abar
     double *info_f = nullptr, *info_h = nullptr;                  // ncells * NINFO
     double *adj_sums = nullptr, *adj_wsum = nullptr;              // ncells * vsplit_max * (NSUM, NWALL)
@@ -326,9 +327,9 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
             lds_max <= 0)
             lds_max = 65536;
         const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
-        const size_t roles = (size_t)(c->dim == 2 ? 4 * 7 : 2 * 4) * g.nvz * 2 * c->esize;
-        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + roles + slack;
+        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack;
         const size_t adj = (c->dim == 2 ? 17 : 9) * entry + slack;
+        c->lds_max = lds_max;
         if (fwd > (size_t)lds_max) {
             char b[160];
             snprintf(b, sizeof b, "velocity grid needs %zu bytes of LDS per workgroup; the device allows %d", fwd,
@@ -487,12 +488,21 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
 // 256 MB last-level cache (MALL) plain stores leave the output there (the
 // 256 x 32^3 FP64 shock runs 30 us instead of 43 us per pass); larger working
 // sets use non-temporal stores, measured faster for them.
-// LDS of the streaming kernel's role-ordered z-tables (one-residue shapes):
-// [sign combination][jz][tap role][2] values.
-static size_t role_table_bytes(const bgk_ctx *c)
+// LDS of the role-ordered z-tables of the one-residue kernels:
+// [sign combination][jz][tap role][2] values; roles: 7 (2D) or 4 for the
+// streaming kernel, 9 or 5 for the reverse sweep's gather kernel.
+static size_t role_table_bytes(const bgk_ctx *c, bool adjoint)
 {
-    const int combos = c->dim == 2 ? 4 : 2, roles = c->dim == 2 ? 7 : 4;
+    const int combos = c->dim == 2 ? 4 : 2;
+    const int roles = adjoint ? (c->dim == 2 ? 9 : 5) : (c->dim == 2 ? 7 : 4);
     return (size_t)combos * c->geo.nvz * roles * 2 * c->esize;
+}
+
+// The one-residue form needs every lane of a wave on one plane (zr = 1) and
+// its role tables to fit in LDS next to the slot entries.
+static bool use_roles(const bgk_ctx *c, int zr, size_t lds, bool adjoint)
+{
+    return zr == 1 && lds + role_table_bytes(c, adjoint) + 4096 <= (size_t)c->lds_max;
 }
 
 static bool stream_nt(const bgk_ctx *c)
@@ -504,9 +514,10 @@ template <typename real, int DIM, int VEC, int UNR, bool NTS>
 static void stream_kernel_z(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
     const real *p = (const real *)params_buf<real>(c, c->pass_parity);
-    if (c->zr == 1)  // every lane of a wave on the same plane: role-ordered z-tables after the slots
+    if (use_roles(c, c->zr, lds, false))  // one plane per wave: role-ordered z-tables after the slots
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, NTS, true>), dim3(nb), dim3(c->sblock),
-                           lds + role_table_bytes(c), s, make_args(c), (const real *)src, (real *)dst, p, c->partial);
+                           lds + role_table_bytes(c, false), s, make_args(c), (const real *)src, (real *)dst, p,
+                           c->partial);
     else
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, NTS, false>), dim3(nb), dim3(c->sblock), lds, s,
                            make_args(c), (const real *)src, (real *)dst, p, c->partial);
@@ -710,15 +721,23 @@ static void adj_stream_dispatch(bgk_ctx *c, const void *f, const void *lam, hipS
     Args a = make_args(c);
     int block = 256;
     task_shape(c->geo, vec, c->geo.nvz / c->vsplit, &a.zr, &block);
-    if (vec == 4)
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 4>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
-                           c->adj_wsum);
-    else if (vec == 2)
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 2>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
-                           c->adj_wsum);
-    else
-        hipLaunchKernelGGL((k_adj_stream<real, DIM, 1>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr, c->adj_coef, o,
-                           c->adj_wsum);
+    // (measured on the 64^2 cavity: the role form helps float, not double)
+    if (sizeof(real) == 4 && use_roles(c, a.zr, lds, true)) {
+        const size_t l = lds + role_table_bytes(c, true);
+        if (vec == 2)
+            hipLaunchKernelGGL((k_adj_stream<real, DIM, 2, true>), dim3(nb), dim3(block), l, s, a, fr, p0, lr,
+                               c->adj_coef, o, c->adj_wsum);
+        else
+            hipLaunchKernelGGL((k_adj_stream<real, DIM, 1, true>), dim3(nb), dim3(block), l, s, a, fr, p0, lr,
+                               c->adj_coef, o, c->adj_wsum);
+    } else {
+        if (vec == 2)
+            hipLaunchKernelGGL((k_adj_stream<real, DIM, 2, false>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr,
+                               c->adj_coef, o, c->adj_wsum);
+        else
+            hipLaunchKernelGGL((k_adj_stream<real, DIM, 1, false>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr,
+                               c->adj_coef, o, c->adj_wsum);
+    }
 }
 
 // One reverse step.  The first streaming pass of the step is recomputed
