@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
         double A0 = 0, Az = 0, Azz = 0;
+#pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const double h = (double)fc[(long long)jz * g.npl + p];
             const double vz = vnode(g, 2, jz);
@@ -952,6 +953,7 @@ __global__ void __launch_bounds__(256) k_final(Args A, const real *src, real *ds
         const int jx = p % g.nvx, jy = p / g.nvx;
         const real l1 = E[g.tx1 + jx] * E[g.ty1 + jy];
         const real l2 = E[g.tx2 + jx] * E[g.ty2 + jy];
+#pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const long long i = off + (long long)jz * g.npl + p;
             if constexpr (sizeof(real) == 4) {
