@@ -406,28 +406,60 @@ __global__ void __launch_bounds__(256)
             emy = (sy == 0 && wb) || (sy == 1 && wt);
             wy = sy == 0 ? 2 : 3;
         }
-        for (int jz = z0 + zr; jz < z1; jz += A.zr) {
-            const uint32_t zo = (uint32_t)jz * zstep;
-            const double vzd = vnode(g, 2, jz);
-            const real vz = (real)vzd;
+        // The 9 (1D: 5) f taps and 7 (1D: 4) lambda taps of one plane, loaded
+        // one plane ahead of their use (software pipeline; the prefetch after
+        // the lane's last plane re-reads it).
+        constexpr int NF = DIM == 1 ? 5 : 9, NL = DIM == 1 ? 4 : 7;
+        auto load_plane = [&](int j, V (&F)[NF], V (&Lm)[NL]) {
+            const uint32_t zo = (uint32_t)j * zstep;
             // plane bases: wave-uniform under ZU (folded into the scalar base)
             const uint32_t zb = ZU ? __builtin_amdgcn_readfirstlane(zo) : 0u, zv = ZU ? 0u : zo;
             const real *fz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(fb) + zb);
             const real *lz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(lb) + zb);
+            F[0] = tc.load(fz, zv);
+            F[1] = xa.load(fz, zv);
+            F[2] = xb.load(fz, zv);
+            F[3] = xd.load(fz, zv);
+            F[4] = xe.load(fz, zv);
+            Lm[0] = mc.load(lz, zv);
+            Lm[1] = mxb.load(lz, zv);
+            Lm[2] = mxd.load(lz, zv);
+            Lm[3] = mxe.load(lz, zv);
+            if constexpr (DIM == 2) {
+                F[5] = ya.load(fz, zv);
+                F[6] = yb.load(fz, zv);
+                F[7] = yd.load(fz, zv);
+                F[8] = ye.load(fz, zv);
+                Lm[4] = myb.load(lz, zv);
+                Lm[5] = myd.load(lz, zv);
+                Lm[6] = mye.load(lz, zv);
+            }
+        };
+        int jz = z0 + zr;
+        if (jz >= z1) continue;
+        const int zlast = z1 - 1 - ((z1 - 1 - jz) % A.zr);  // last plane of this lane's residue
+        V F[NF], Lm[NL];
+        load_plane(jz, F, Lm);
+        for (; jz < z1; jz += A.zr) {
+            V Fn[NF], Ln[NL];
+            load_plane(min(jz + A.zr, zlast), Fn, Ln);
+            const uint32_t zo = (uint32_t)jz * zstep;
+            const double vzd = vnode(g, 2, jz);
+            const real vz = (real)vzd;
             // relaxed f at a tap: z-table pair from the role rows (ZU) or the tap's entry
             const real *row = tzl + jz * (NROLE * 2);
             auto rl = [&](const Tap<real, VEC> &t, int role, V h) -> V {
                 if constexpr (ZU) return t.relax_ab(h, row[2 * role], row[2 * role + 1]);
                 else return t.relax(h, jz);
             };
-            const V u0 = rl(tc, 0, tc.load(fz, zv));
-            const V m0 = mc.value(mc.load(lz, zv), vz);
+            const V u0 = rl(tc, 0, F[0]);
+            const V m0 = mc.value(Lm[0], vz);
             V r = m0;
             {
-                const V um2 = rl(xa, 1, xa.load(fz, zv)), um1 = rl(xb, 2, xb.load(fz, zv));
-                const V u1 = rl(xd, 3, xd.load(fz, zv)), u2 = rl(xe, 4, xe.load(fz, zv));
-                const V mm1 = mxb.value(mxb.load(lz, zv), vz), m1 = mxd.value(mxd.load(lz, zv), vz);
-                const V m2 = mxe.value(mxe.load(lz, zv), vz);
+                const V um2 = rl(xa, 1, F[1]), um1 = rl(xb, 2, F[2]);
+                const V u1 = rl(xd, 3, F[3]), u2 = rl(xe, 4, F[4]);
+                const V mm1 = mxb.value(Lm[1], vz), m1 = mxd.value(Lm[2], vz);
+                const V m2 = mxe.value(Lm[3], vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],
@@ -450,10 +482,10 @@ __global__ void __launch_bounds__(256)
                 }
             }
             if constexpr (DIM == 2) {
-                const V um2 = rl(ya, 5, ya.load(fz, zv)), um1 = rl(yb, 6, yb.load(fz, zv));
-                const V u1 = rl(yd, 7, yd.load(fz, zv)), u2 = rl(ye, 8, ye.load(fz, zv));
-                const V mm1 = myb.value(myb.load(lz, zv), vz), m1 = myd.value(myd.load(lz, zv), vz);
-                const V m2 = mye.value(mye.load(lz, zv), vz);
+                const V um2 = rl(ya, 5, F[5]), um1 = rl(yb, 6, F[6]);
+                const V u1 = rl(yd, 7, F[7]), u2 = rl(ye, 8, F[8]);
+                const V mm1 = myb.value(Lm[4], vz), m1 = myd.value(Lm[5], vz);
+                const V m2 = mye.value(Lm[6], vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],
@@ -477,6 +509,10 @@ __global__ void __launch_bounds__(256)
                 }
             }
             *reinterpret_cast<V *>(reinterpret_cast<char *>(ob) + out0 + zo + (uint32_t)(p0 * sizeof(real))) = r;
+#pragma unroll
+            for (int t = 0; t < NF; ++t) F[t] = Fn[t];
+#pragma unroll
+            for (int t = 0; t < NL; ++t) Lm[t] = Ln[t];
         }
     }
     if (wl || wr || wb || wt) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);

@@ -35,7 +35,7 @@ namespace bgk {
 
 constexpr int NVMAX = 128;        // per velocity component
 constexpr int KIND_SHOCK = 0, KIND_CAVITY = 1, KIND_PER1 = 2, KIND_PER2 = 3;
-constexpr int MODE_FIRST = 0, MODE_MID = 1, MODE_FINAL = 2, MODE_IDENT = 3;
+constexpr int MODE_FIRST = 0, MODE_MID = 1, MODE_FINAL = 2;
 constexpr int NQ = 9;             // moment sums per cell: 1, vx, vy, vz, |v|^2, 4 half fluxes
 
 struct Inst {
@@ -283,15 +283,10 @@ __global__ void k_check(int ncells, const double *__restrict__ mom, int *__restr
 //   FIRST: g = R1(f0)        (Strang: R_{dt/2}; Lie: identity)
 //   MID:   g = R1(R2(h))     (Strang: R_{dt/2} R_{dt/2}; Lie: R_dt)
 //   FINAL: f = R2(h)         (Strang: R_{dt/2}; Lie: R_dt)
-//   IDENT: g = h             (no relaxation; the reverse sweep streams R_a(f) itself)
 // Returned in application order: ta is applied first, tb second; nr relaxations.
 __device__ __forceinline__ int relax_times(const Inst &I, int mode, double *ta, double *tb)
 {
     const double h = 0.5 * I.dt;
-    if (mode == MODE_IDENT) {
-        *ta = *tb = 0.0;
-        return 0;
-    }
     if (I.strang) {
         *ta = h;
         *tb = h;
