@@ -94,6 +94,7 @@ __global__ void __launch_bounds__(256) k_adj_sums(Args A, const real *__restrict
         const int jx = p % g.nvx, jy = p / g.nvx;
         const double cx = vnode(g, 0, jx) - in[1], cy = vnode(g, 1, jy) - in[2];
         const double pxy = T.P * T.e[0][jx] * T.e[1][jy];
+#pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const long long i = off + (long long)jz * g.npl + p;
             const double m = (double)mu[i], xv = (double)x[i];
@@ -170,6 +171,7 @@ __global__ void __launch_bounds__(256) k_adj_apply(Args A, const real *__restric
         const int jx = p % g.nvx, jy = p / g.nvx;
         const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
         const double base = G0 + G1 * vx + G2 * vy + G4 * (vx * vx + vy * vy);
+#pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const int i = jz * g.npl + p;
             const double vz = vnode(g, 2, jz);
