@@ -462,11 +462,28 @@ static real *params_buf(bgk_ctx *c, int parity)
     return (real *)c->params + (size_t)parity * (c->ncells + c->npseudo) * c->geo.pe;
 }
 
+// Jx values per lane of the pointwise kernels (16-byte loads where Nvx allows).
+static int pointwise_vec(const bgk_ctx *c)
+{
+    const int want = c->precision == BGK_FP32 ? 4 : 2;
+    for (int v = want; v > 1; v /= 2)
+        if (c->geo.nvx % v == 0) return v;
+    return 1;
+}
+
 template <typename real>
 static int launch_moments(bgk_ctx *c, const void *f, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
-    hipLaunchKernelGGL(k_moments<real>, dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f, c->partial);
+    if (pointwise_vec(c) == 4)
+        hipLaunchKernelGGL((k_moments<real, 4>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
+                           c->partial);
+    else if (pointwise_vec(c) == 2)
+        hipLaunchKernelGGL((k_moments<real, 2>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
+                           c->partial);
+    else
+        hipLaunchKernelGGL((k_moments<real, 1>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
+                           c->partial);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -576,8 +593,16 @@ template <typename real>
 static int launch_final(bgk_ctx *c, const void *src, void *dst, int parity, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
-    hipLaunchKernelGGL(k_final<real>, dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src, (real *)dst,
-                       (const real *)params_buf<real>(c, parity));
+    const real *p = (const real *)params_buf<real>(c, parity);
+    if (pointwise_vec(c) == 4)
+        hipLaunchKernelGGL((k_final<real, 4>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
+                           (real *)dst, p);
+    else if (pointwise_vec(c) == 2)
+        hipLaunchKernelGGL((k_final<real, 2>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
+                           (real *)dst, p);
+    else
+        hipLaunchKernelGGL((k_final<real, 1>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
+                           (real *)dst, p);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }

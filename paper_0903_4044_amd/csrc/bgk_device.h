@@ -213,12 +213,25 @@ __device__ __forceinline__ void fold_column(double (&acc)[NQ], double vx, double
     acc[8] += vy > 0.0 ? vy * A0 : 0.0;
 }
 
+template <typename T, int N>
+using vec_t = T __attribute__((ext_vector_type(N)));
+
+// Byte-offset load/store from a uniform base (SGPR base + 32-bit VGPR offset).
+template <typename V>
+__device__ __forceinline__ V ld(const void *base, uint32_t off)
+{
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // ---------------------------------------------------------------- moments
 // Partial moment sums of f over one jz chunk of one cell:
-// partial[(cell * vsplit + split) * NQ + q] (without the dV factor).
-template <typename real>
+// partial[(cell * vsplit + split) * NQ + q] (without the dV factor).  Each
+// lane reads VEC consecutive jx at one jy (16-byte loads where the grid
+// allows) down its jz chunk.
+template <typename real, int VEC>
 __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict__ f, double *__restrict__ partial)
 {
+    using V = vec_t<real, VEC>;
     const Geo &g = A.g;
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int gc = L / A.vsplit, split = L % A.vsplit;
@@ -226,19 +239,31 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
     const Inst &I = A.inst[ii];
     const real *fc = f + I.f0 + (long long)(gc - I.cell0) * g.nv;
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    const int ngrp = g.npl / VEC;
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
-        const int jx = p % g.nvx, jy = p / g.nvx;
-        double A0 = 0, Az = 0, Azz = 0;
+    for (int q = threadIdx.x; q < ngrp; q += blockDim.x) {
+        const int p0 = q * VEC, jx0 = p0 % g.nvx, jy = p0 / g.nvx;
+        double A0[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) A0[e] = 0.0;
+        double Az = 0, Azz = 0;
 #pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
-            const double h = (double)fc[(long long)jz * g.npl + p];
+            const V h = ld<V>(fc, (uint32_t)((jz * g.npl + p0) * (int)sizeof(real)));
+            double sh = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const double he = (double)h[e];
+                A0[e] += he;
+                sh += he;
+            }
             const double vz = vnode(g, 2, jz);
-            A0 += h;
-            Az += vz * h;
-            Azz += vz * vz * h;
+            Az += vz * sh;
+            Azz += vz * vz * sh;
         }
-        fold_column(acc, vnode(g, 0, jx), vnode(g, 1, jy), A0, Az, Azz);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            fold_column(acc, vnode(g, 0, jx0 + e), vnode(g, 1, jy), A0[e], e == 0 ? Az : 0.0, e == 0 ? Azz : 0.0);
     }
     block_sum_store<NQ>(acc, partial + (long long)L * NQ);
 }
@@ -609,15 +634,6 @@ __device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int pos, i
     }
 }
 
-template <typename T, int N>
-using vec_t = T __attribute__((ext_vector_type(N)));
-
-// Byte-offset load/store from a uniform base (SGPR base + 32-bit VGPR offset).
-template <typename V>
-__device__ __forceinline__ V ld(const void *base, uint32_t off)
-{
-    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + off);
-}
 
 // One stencil input for the current lane: VEC consecutive jx at one jy.
 template <typename real, int VEC>
@@ -928,36 +944,51 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- final
-// Pointwise f = R2(h) from the cell's own entry (MODE_FINAL tables).
-template <typename real>
+// Pointwise f = R2(h) from the cell's own entry (MODE_FINAL tables); VEC
+// consecutive jx per lane.  src may be dst (each lane rewrites what it read).
+template <typename real, int VEC>
 __global__ void __launch_bounds__(256) k_final(Args A, const real *src, real *dst, const real *__restrict__ params)
 {
+    using V = vec_t<real, VEC>;
     const Geo &g = A.g;
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int gc = L / A.vsplit, split = L % A.vsplit;
     const int ii = find_inst(A.cell_prefix, A.ninst, gc);
     const Inst &I = A.inst[ii];
     const long long off = I.f0 + (long long)(gc - I.cell0) * g.nv;
+    const real *sc = src + off;
+    real *dc = dst + off;
     const real *E = params + (long long)gc * g.pe;
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     const real c0 = E[0];
     const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 1) : 0u;
     const double c0d = sizeof(real) == 4 ? *reinterpret_cast<const double *>(E + 2) : 0.0;
     const uint32_t ecell = (uint32_t)(gc - I.cell0) * (uint32_t)g.nv;
-    for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
-        const int jx = p % g.nvx, jy = p / g.nvx;
-        const real l1 = E[g.tx1 + jx] * E[g.ty1 + jy];
-        const real l2 = E[g.tx2 + jx] * E[g.ty2 + jy];
+    const int ngrp = g.npl / VEC;
+    for (int q = threadIdx.x; q < ngrp; q += blockDim.x) {
+        const int p0 = q * VEC, jx0 = p0 % g.nvx, jy = p0 / g.nvx;
+        V l1, l2;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            l1[e] = E[g.tx1 + jx0 + e] * E[g.ty1 + jy];
+            l2[e] = E[g.tx2 + jx0 + e] * E[g.ty2 + jy];
+        }
 #pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
-            const long long i = off + (long long)jz * g.npl + p;
-            if constexpr (sizeof(real) == 4) {
-                const double v = c0d * (double)src[i] +
-                                 ((double)l1 * (double)E[g.tz + 2 * jz] + (double)l2 * (double)E[g.tz + 2 * jz + 1]);
-                dst[i] = round_stochastic(v, hash32((ecell + (uint32_t)(jz * g.npl + p)) ^ key));
-            } else {
-                dst[i] = c0 * src[i] + (l1 * E[g.tz + 2 * jz] + l2 * E[g.tz + 2 * jz + 1]);
+            const uint32_t o = (uint32_t)((jz * g.npl + p0) * (int)sizeof(real));
+            const V h = ld<V>(sc, o);
+            const real a = E[g.tz + 2 * jz], b = E[g.tz + 2 * jz + 1];
+            V r;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (sizeof(real) == 4) {
+                    const double v = c0d * (double)h[e] + ((double)l1[e] * (double)a + (double)l2[e] * (double)b);
+                    r[e] = round_stochastic(v, hash32((ecell + (uint32_t)(jz * g.npl + p0 + e)) ^ key));
+                } else {
+                    r[e] = c0 * h[e] + (l1[e] * a + l2[e] * b);
+                }
             }
+            *reinterpret_cast<V *>(reinterpret_cast<char *>(dc) + o) = r;
         }
     }
 }
