@@ -812,7 +812,10 @@ __global__ void __launch_bounds__(256)
         // One jz: relax the loaded taps, stream, store, accumulate moments.
         // One jz: relax the loaded taps, stream, store, accumulate moments.
         // zo is the byte offset of plane jz (jz * Nvx * Nvy elements).
-        auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo) {
+        // hp: the hashes of this plane pair when the caller computed them
+        // (have), for two consecutive planes of one stage.
+        using U = vec_t<uint32_t, VEC>;
+        auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo, U hp, bool have) {
             real ta[NT], tb[NT];  // the taps' z-table values at plane jz
             if constexpr (ZU) {
                 const real *row = tzl + jz * (NROLE * 2);
@@ -843,15 +846,17 @@ __global__ void __launch_bounds__(256)
                 // stochastic rounding.  The increment's own rounding is
                 // relative to d, far below an ulp of h wherever d is small.
                 const real a = ta[0], b = tb[0];
-                const uint32_t i0 = ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real);
-                uint32_t hb = 0;
+                // random bits: one hash per element pair (planes 2k and 2k + 1 of
+                // one velocity column, keyed by the even member's index), low
+                // half for the even plane
+                const bool odd = (jz & 1) != 0;
+                const uint32_t ieven = ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real) - (odd ? (uint32_t)g.npl : 0u);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const real M = tc.l1[e] * a + tc.l2[e] * b;
                     const real d = __builtin_fmaf(c0m1_hi, hv[0][e], __builtin_fmaf(c0m1_lo, hv[0][e], M)) - (dx[e] + dy[e]);
-                    const uint32_t ie = i0 + (uint32_t)e;
-                    if (e == 0 || (ie & 1u) == 0) hb = hash32((ie >> 1) ^ key);
-                    r[e] = round_stochastic16((double)hv[0][e] + (double)d, (ie & 1u) ? (hb >> 16) : (hb & 0xffffu));
+                    const uint32_t hb = have ? hp[e] : hash32((ieven + (uint32_t)e) ^ key);
+                    r[e] = round_stochastic16((double)hv[0][e] + (double)d, odd ? (hb >> 16) : (hb & 0xffffu));
                 }
             } else {
                 r = u0 - dx - dy;
@@ -902,9 +907,17 @@ __global__ void __launch_bounds__(256)
                 }
             };
             auto compute_stage = [&](const V (&h)[UNR][NT], int j, uint32_t off) {
+                // two consecutive planes (one residue, even j): one hash per pair
+                U hp = 0;
+                const bool have = sizeof(real) == 4 && UNR == 2 && ZU && (j & 1) == 0 && j + 1 < z1;
+                if (have) {
+                    const uint32_t ieven = ecell + (uint32_t)p0 + off / (uint32_t)sizeof(real);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) hp[e] = hash32((ieven + (uint32_t)e) ^ key);
+                }
 #pragma unroll
                 for (int u = 0; u < UNR; ++u)
-                    if (j + u * A.zr < z1) finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off);
+                    if (j + u * A.zr < z1) finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off, hp, have);
             };
             V ha[UNR][NT];
             load_stage(ha, zoff);
