@@ -138,17 +138,21 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
 /* Launch shape of the streaming kernel (engineering interface; results do
  * not depend on it beyond rounding of the moment sums).  A shape is
  * (vec, unroll, vsplit, persist): jx values per lane task (1, 2 or 4; 4 only
- * for BGK_FP32, and only if it divides Nvx with one v_x sign per group), jz
- * values per software-pipeline stage (1 or 2), jz chunks per cell (one work
- * item each, 1 .. a context-dependent maximum), and persist: 0 launches one
- * workgroup per work item, k > 0 launches k workgroups per compute unit that
- * walk the items of all instances (one persistent launch for a batch).
+ * for BGK_FP32, and only if it divides Nvx with one v_x sign per group),
+ * unroll: the software pipeline of the jz loop (1: one plane per stage, one
+ * in flight ahead; 2: two planes per stage, one stage ahead; 3, 4: one plane
+ * per stage, 2 or 3 planes ahead), jz chunks per cell (one work item each,
+ * 1 .. a context-dependent maximum), and persist: 0 launches one workgroup
+ * per work item, k > 0 launches k workgroups per compute unit that walk the
+ * items of all instances (one persistent launch for a batch).
  * bgk_init picks a default.  bgk_autotune times every valid shape on the
  * state f (device, f_elems elements, read only; synchronises the stream) and
  * keeps the fastest by the steady time of a real step (streaming pass and
- * table preparation, (10 steps - 2 steps) / 8); it borrows a temporary
- * f-sized device buffer for the steps' output during the call (if that
- * allocation fails it times bare streaming passes over f instead); bgk_get_launch reports the shape in use and, after
+ * table preparation, (10 steps - 2 steps) / 8; the four fastest of the
+ * sweep are timed twice more and ranked by their best time); it borrows a
+ * temporary f-sized device buffer for the steps' output during the call (if
+ * that allocation fails it times bare streaming passes over f instead); on
+ * an error the previous shape stays in use; bgk_get_launch reports the shape in use and, after
  * autotuning, the measured time per step in microseconds; bgk_set_launch
  * applies a shape (BGK_E_INVALID if not valid for the context). */
 int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream);

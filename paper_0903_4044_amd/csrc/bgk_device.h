@@ -653,13 +653,12 @@ struct Tap {
     __device__ __forceinline__ V relax_ab(V h, real a, real b) const { return c0 * h + (l1 * a + l2 * b); }
 };
 
+// Tap reading h of instance-local cell `cell` with the tables of entry E.
 template <typename real, int VEC>
-__device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp, const SlotInfo &SI, int slot, int p0,
-                                                   int jx0, int jy)
+__device__ __forceinline__ Tap<real, VEC> make_tap_at(const Geo &g, const real *E, int cell, int p0, int jx0, int jy)
 {
     Tap<real, VEC> t;
-    const real *E = sp + slot * g.pe;
-    t.off = (uint32_t)(((long long)SI.cell[slot] * g.nv + p0) * sizeof(real));
+    t.off = (uint32_t)(((long long)cell * g.nv + p0) * sizeof(real));
     t.tz = E + g.tz;
     t.c0 = E[0];
     const real y1 = E[g.ty1 + jy], y2 = E[g.ty2 + jy];
@@ -671,6 +670,21 @@ __device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp,
     return t;
 }
 
+template <typename real, int VEC>
+__device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp, const SlotInfo &SI, int slot, int p0,
+                                                   int jx0, int jy)
+{
+    return make_tap_at<real, VEC>(g, sp + slot * g.pe, SI.cell[slot], p0, jx0, jy);
+}
+
+// Second-order upwind value at the downwind face of cell u0 (upwind
+// neighbour um1, downwind neighbour u1) with slope factor k = (1 - C)/2.
+template <typename real>
+__device__ __forceinline__ real face_value(real um1, real u0, real u1, real k)
+{
+    return u0 + k * minmod3(u1 - u0, u0 - um1);
+}
+
 // Upwind flux difference along one direction, values in upwind order
 // (u_{-2}, u_{-1}, u_0, u_1), Courant magnitudes C and slope factors k = (1 - C)/2.
 template <typename real, int VEC>
@@ -680,8 +694,8 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
     vec_t<real, VEC> r;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-        const real fp = u0[e] + k[e] * minmod3(u1[e] - u0[e], u0[e] - um1[e]);
-        const real fm = um1[e] + k[e] * minmod3(u0[e] - um1[e], um1[e] - um2[e]);
+        const real fp = face_value(um1[e], u0[e], u1[e], k[e]);
+        const real fm = face_value(um2[e], um1[e], u0[e], k[e]);
         r[e] = C[e] * (fp - fm);
     }
     return r;
@@ -699,7 +713,7 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // the taps are re-laid out in LDS as [sign combination][jz][tap role][2] so
 // that one vector address per plane reaches every tap's pair through
 // immediate offsets.
-template <typename real, int DIM, int VEC, int UNR, bool NTSTORE, bool ZU>
+template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU>
 __global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
@@ -881,8 +895,10 @@ __global__ void __launch_bounds__(256)
         // advance by additions; prefetches past the lane's last plane re-read
         // it.  With two planes per stage the loop body is written twice over
         // alternating register sets, so a prefetched value is consumed one
-        // stage later and never copied; with one plane per stage the plain
-        // rotation needs fewer registers (more waves per SIMD).
+        // stage later and never copied; with one plane per stage a ring of
+        // PD + 1 single-plane buffers keeps PD planes in flight (more loads in
+        // flight per register than two-plane stages, where half the buffers
+        // are being computed on).
         const int zs = UNR * A.zr;
         int jz = z0 + zr;
         if (jz < z1) {
@@ -919,10 +935,9 @@ __global__ void __launch_bounds__(256)
                 for (int u = 0; u < UNR; ++u)
                     if (j + u * A.zr < z1) finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off, hp, have);
             };
-            V ha[UNR][NT];
-            load_stage(ha, zoff);
             if constexpr (UNR == 2) {
-                V hb[UNR][NT];
+                V ha[UNR][NT], hb[UNR][NT];
+                load_stage(ha, zoff);
                 for (;;) {
                     load_stage(hb, zoff + zs_off);
                     compute_stage(ha, jz, zoff);
@@ -936,14 +951,54 @@ __global__ void __launch_bounds__(256)
                     if (jz >= z1) break;
                 }
             } else {
-                for (; jz < z1; jz += zs, zoff += zs_off) {
-                    V hn[UNR][NT];
-                    load_stage(hn, zoff + zs_off);
-                    compute_stage(ha, jz, zoff);
+                // One plane per stage.  With one residue a lane's planes are
+                // consecutive, and the random bits of an even plane are kept
+                // for its odd partner.
+                U hcar = 0;
+                const int jfirst = jz;
+                auto stage1 = [&](const V (&h)[1][NT], int j, uint32_t off) {
+                    if constexpr (sizeof(real) == 4 && ZU) {
+                        if ((j & 1) == 0) {
+                            const uint32_t ieven = ecell + (uint32_t)p0 + off / (uint32_t)sizeof(real);
 #pragma unroll
-                    for (int u = 0; u < UNR; ++u)
+                            for (int e = 0; e < VEC; ++e) hcar[e] = hash32((ieven + (uint32_t)e) ^ key);
+                            finish(h[0], j, off, hcar, true);
+                        } else {
+                            finish(h[0], j, off, hcar, j > jfirst);
+                        }
+                    } else {
+                        finish(h[0], j, off, hcar, false);
+                    }
+                };
+                if constexpr (PD == 1) {
+                    // one plane in flight: plain rotation (the compiler
+                    // renames the copies)
+                    V ha[1][NT];
+                    load_stage(ha, zoff);
+                    for (; jz < z1; jz += zs, zoff += zs_off) {
+                        V hn[1][NT];
+                        load_stage(hn, zoff + zs_off);
+                        stage1(ha, jz, zoff);
 #pragma unroll
-                        for (int t = 0; t < NT; ++t) ha[u][t] = hn[u][t];
+                        for (int t = 0; t < NT; ++t) ha[0][t] = hn[0][t];
+                    }
+                } else {
+                    // PD planes in flight: a ring of PD + 1 buffers (buffer
+                    // r % (PD + 1) holds the lane's plane jz + r * zr)
+                    V hr[PD + 1][1][NT];
+#pragma unroll
+                    for (int d = 0; d < PD; ++d) load_stage(hr[d], zoff + (uint32_t)d * zs_off);
+                    for (;;) {
+#pragma unroll
+                        for (int r = 0; r <= PD; ++r) {
+                            load_stage(hr[(r + PD) % (PD + 1)], zoff + (uint32_t)PD * zs_off);
+                            stage1(hr[r], jz, zoff);
+                            jz += zs;
+                            zoff += zs_off;
+                            if (jz >= z1) goto ring_done;
+                        }
+                    }
+                ring_done:;
                 }
             }
         }

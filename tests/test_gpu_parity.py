@@ -319,7 +319,7 @@ def test_autotune_keeps_parity(B, oracle_mod):
 
 @pytest.mark.parametrize("kind", ["shock", "cavity"])
 def test_every_shape_matches_oracle(B, oracle_mod, kind):
-    """Each launch shape (vector width, pipeline depth, jz chunks, persistent
+    """Each launch shape (vector width, pipeline mode, jz chunks, persistent
     grid) computes the same step to rounding."""
     cfg = small(kind, nv=(16, 16, 8), nx=7, ny=6)
     O = oracle_mod.Oracle(cfg)
@@ -329,7 +329,7 @@ def test_every_shape_matches_oracle(B, oracle_mod, kind):
         C = B.Context(cfg, prec, tune="off")
         x = to_dev(f0, C.dtype)
         for vec in (1, 2, 4):
-            for unroll in (1, 2):
+            for unroll in (1, 2, 3, 4):
                 for vsplit in (1, 3):
                     for persist in (0, 1):
                         try:
@@ -342,6 +342,36 @@ def test_every_shape_matches_oracle(B, oracle_mod, kind):
                         else:
                             e = moment_errors(C.moments(y).cpu().numpy(), O.moments(ref), cfg)
                             assert max(e) <= 1e-5, (vec, unroll, vsplit, persist, e)
+
+
+@pytest.mark.parametrize("kind,nx", [("shock", 9), ("periodic1d", 7), ("cavity", 5)])
+def test_pipeline_modes_match_bitwise(B, oracle_mod, kind, nx):
+    """The jz-loop pipeline modes (two planes per stage; one plane with 1, 2
+    or 3 planes in flight) compute the same step bit for bit, FP32 rounding
+    bits included."""
+    cfg = small(kind, nv=(16, 16, 8), nx=nx, ny=4)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed_initial(O, seed=63)
+    ran = 0
+    for prec in ("fp64", "fp32"):
+        C = B.Context(cfg, prec, tune="off")
+        x = to_dev(f0, C.dtype)
+        for vec in (1, 2, 4):
+            for vsplit in (1, 3):
+                ref = None
+                for unroll in (2, 1, 3, 4):
+                    try:
+                        C.set_launch(vec, unroll, vsplit, 0)
+                    except B.BGKError:
+                        break
+                    C.set_seed(7)
+                    y = C.step(x, n=3)
+                    if ref is None:
+                        ref = y.clone()
+                    else:
+                        assert torch.equal(y, ref), (prec, vec, vsplit, unroll)
+                        ran += 1
+    assert ran >= 12
 
 
 def test_graph_replay_matches_eager(B):
