@@ -349,6 +349,8 @@ __global__ void __launch_bounds__(256)
     const real *fb = f + I.f0;
     const real *lb = lam + I.f0;
     real *ob = out + I.f0;
+    const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));  // below 2^32 (init)
+    const __amdgpu_buffer_rsrc_t frs = make_rsrc(fb, ibytes), lrs = make_rsrc(lb, ibytes);
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     const bool lim = I.minmod != 0;
@@ -414,27 +416,34 @@ __global__ void __launch_bounds__(256)
         constexpr int NF = DIM == 1 ? 5 : 9, NL = DIM == 1 ? 4 : 7;
         auto load_plane = [&](int j, V (&F)[NF], V (&Lm)[NL]) {
             const uint32_t zo = (uint32_t)j * zstep;
-            // plane bases: wave-uniform under ZU (folded into the scalar base)
-            const uint32_t zb = ZU ? __builtin_amdgcn_readfirstlane(zo) : 0u, zv = ZU ? 0u : zo;
-            const real *fz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(fb) + zb);
-            const real *lz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(lb) + zb);
-            F[0] = tc.load(fz, zv);
-            F[1] = xa.load(fz, zv);
-            F[2] = xb.load(fz, zv);
-            F[3] = xd.load(fz, zv);
-            F[4] = xe.load(fz, zv);
-            Lm[0] = mc.load(lz, zv);
-            Lm[1] = mxb.load(lz, zv);
-            Lm[2] = mxd.load(lz, zv);
-            Lm[3] = mxe.load(lz, zv);
+            // under ZU the plane offset is wave-uniform: buffer loads take it as
+            // their scalar offset next to the tap's per-lane offset
+            const uint32_t zb = ZU ? __builtin_amdgcn_readfirstlane(zo) : 0u;
+            auto lf = [&](const auto &tp) -> V {
+                if constexpr (ZU) return buf_ld<V>(frs, tp.off, zb);
+                else return tp.load(fb, zo);
+            };
+            auto ll = [&](const auto &tp) -> V {
+                if constexpr (ZU) return buf_ld<V>(lrs, tp.off, zb);
+                else return tp.load(lb, zo);
+            };
+            F[0] = lf(tc);
+            F[1] = lf(xa);
+            F[2] = lf(xb);
+            F[3] = lf(xd);
+            F[4] = lf(xe);
+            Lm[0] = ll(mc);
+            Lm[1] = ll(mxb);
+            Lm[2] = ll(mxd);
+            Lm[3] = ll(mxe);
             if constexpr (DIM == 2) {
-                F[5] = ya.load(fz, zv);
-                F[6] = yb.load(fz, zv);
-                F[7] = yd.load(fz, zv);
-                F[8] = ye.load(fz, zv);
-                Lm[4] = myb.load(lz, zv);
-                Lm[5] = myd.load(lz, zv);
-                Lm[6] = mye.load(lz, zv);
+                F[5] = lf(ya);
+                F[6] = lf(yb);
+                F[7] = lf(yd);
+                F[8] = lf(ye);
+                Lm[4] = ll(myb);
+                Lm[5] = ll(myd);
+                Lm[6] = ll(mye);
             }
         };
         int jz = z0 + zr;

@@ -223,6 +223,29 @@ __device__ __forceinline__ V ld(const void *base, uint32_t off)
     return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// Buffer loads: a descriptor (base, byte size) in scalar registers, a 32-bit
+// per-lane byte offset and a wave-uniform byte offset added by the load
+// itself, so no vector instruction forms a 64-bit address.  Reads past the
+// size return zero instead of faulting.  Third descriptor word of this ISA
+// family for raw (unformatted, stride 0) buffers.
+constexpr int BUF_WORD3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_WORD3);
+}
+
+template <typename V>
+__device__ __forceinline__ V buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(V) == 4)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else if constexpr (sizeof(V) == 8)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
 // ---------------------------------------------------------------- moments
 // Partial moment sums of f over one jz chunk of one cell:
 // partial[(cell * vsplit + split) * NQ + q] (without the dV factor).  Each
@@ -775,6 +798,8 @@ __global__ void __launch_bounds__(256)
 
     const real *base = src + I.f0;
     real *outb = dst + I.f0;
+    // the instance's f as a buffer (its byte size is below 2^32, checked at init)
+    const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, (uint32_t)((long long)I.ncell * g.nv * sizeof(real)));
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
     const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
     const bool lim = I.minmod != 0;
@@ -911,11 +936,10 @@ __global__ void __launch_bounds__(256)
                 for (int u = 0; u < UNR; ++u) {
                     const uint32_t o = min(off + (uint32_t)u * zr_off, zlast_off);
                     if constexpr (ZU) {
-                        // wave-uniform plane offset folded into the scalar base
-                        const real *bz = reinterpret_cast<const real *>(reinterpret_cast<const char *>(base) +
-                                                                        __builtin_amdgcn_readfirstlane(o));
+                        // buffer loads: tap offset per lane, wave-uniform plane offset
+                        const uint32_t so = __builtin_amdgcn_readfirstlane(o);
 #pragma unroll
-                        for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(bz, 0u);
+                        for (int t = 0; t < NT; ++t) h[u][t] = buf_ld<V>(frs, taps[t]->off, so);
                     } else {
 #pragma unroll
                         for (int t = 0; t < NT; ++t) h[u][t] = taps[t]->load(base, o);
