@@ -495,8 +495,20 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
     Args a = make_args(c);
     a.nparts = nparts;
     real *copy = mode == MODE_FIRST ? params_buf<real>(c, 1 - parity) : nullptr;
-    hipLaunchKernelGGL(k_prep<real>, dim3((ne + 3) / 4), dim3(256), 0, s, a, c->partial, params_buf<real>(c, parity),
-                       mode, ne, copy);
+    // lanes per entry: the smallest of 16, 32, 64 that holds the largest velocity axis
+    const int nvmax = std::max(c->geo.nvx, std::max(c->geo.nvy, c->geo.nvz));
+    const int w = nvmax <= 16 ? 16 : nvmax <= 32 ? 32 : 64;
+    const int per_block = 4 * (64 / w);
+    real *pb = params_buf<real>(c, parity);
+    if (w == 16)
+        hipLaunchKernelGGL((k_prep<real, 16>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
+                           pb, mode, ne, copy);
+    else if (w == 32)
+        hipLaunchKernelGGL((k_prep<real, 32>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
+                           pb, mode, ne, copy);
+    else
+        hipLaunchKernelGGL((k_prep<real, 64>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
+                           pb, mode, ne, copy);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }

@@ -374,9 +374,11 @@ __device__ __forceinline__ void finish_relax(const Inst &I, double tau, Relax *r
     r->P = r->n * pi_t_m32(r->T);
 }
 
+// Sum over the W-lane segment of the wave that holds this lane (butterfly).
+template <int W = 64>
 __device__ __forceinline__ double wave_sum(double x)
 {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
     return x;
 }
 
@@ -387,16 +389,17 @@ struct Tables {
     double e[3][2];
 };
 
+template <int W = 64>
 __device__ __forceinline__ void lane_tables(const Geo &g, const double V[3], double T, Tables &t)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (W - 1);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const int k = lane + 64 * s;
+            const int k = lane + W * s;
             t.e[a][s] = 0.0;
-            if (64 * s >= nv_of(g, a)) continue;  // wave-uniform: no second slot below 65 points
+            if (W * s >= nv_of(g, a)) continue;  // uniform: no second slot up to W points
             const double d = vnode(g, a, k) - V[a];
             if (k < nv_of(g, a)) t.e[a][s] = exp(-d * d / T);
         }
@@ -410,27 +413,28 @@ __device__ __forceinline__ void zero_tables(Tables &t)
 
 // Wave-reduced 1D sums of a table: s[a][0] = sum e, s[a][1] = sum v e,
 // s[a][2] = sum v^2 e, s[a][3] = sum_{v<0} |v| e, s[a][4] = sum_{v>0} v e.
+template <int W = 64>
 __device__ __forceinline__ void wave_table_sums(const Geo &g, const Tables &t, double (*s)[5], bool half)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (W - 1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double s0 = 0, s1 = 0, s2 = 0, sm = 0, sp = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const double v = vnode(g, a, lane + 64 * q), x = t.e[a][q];
+            const double v = vnode(g, a, lane + W * q), x = t.e[a][q];
             s0 += x;
             s1 += v * x;
             s2 += v * v * x;
             if (v < 0.0) sm += -v * x;
             else sp += v * x;
         }
-        s[a][0] = wave_sum(s0);
-        s[a][1] = wave_sum(s1);
-        s[a][2] = wave_sum(s2);
+        s[a][0] = wave_sum<W>(s0);
+        s[a][1] = wave_sum<W>(s1);
+        s[a][2] = wave_sum<W>(s2);
         if (half) {
-            s[a][3] = wave_sum(sm);
-            s[a][4] = wave_sum(sp);
+            s[a][3] = wave_sum<W>(sm);
+            s[a][4] = wave_sum<W>(sp);
         }
     }
 }
@@ -458,16 +462,17 @@ struct Coef {
 
 // Coefficients of the relaxations folded into one cell's entry, from that
 // cell's partial moment sums (A.nparts per cell).  Wave-uniform control flow.
+template <int W = 64>
 __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, int gc, int mode,
                                                   const double *partial, Coef &C, bool want_sums)
 {
     const Geo &g = A.g;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (W - 1);
     double mine = 0.0;
     if (lane < NQ)
         for (int k = 0; k < A.nparts; ++k) mine += partial[((long long)gc * A.nparts + k) * NQ + lane];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) C.raw[q] = __shfl(mine, q, 64) * g.dV;
+    for (int q = 0; q < NQ; ++q) C.raw[q] = __shfl(mine, q, W) * g.dV;
     double ta, tb;
     C.nr = relax_times(I, mode, &ta, &tb);
     C.c0 = 1.0;
@@ -477,16 +482,16 @@ __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, 
     if (C.nr == 0) return;
     moments_from_raw(C.raw, &C.r1);
     finish_relax(I, ta, &C.r1);
-    lane_tables(g, C.r1.V, C.r1.T, C.t1);
-    if (C.nr == 2 || want_sums) wave_table_sums(g, C.t1, C.s1, want_sums);
+    lane_tables<W>(g, C.r1.V, C.r1.T, C.t1);
+    if (C.nr == 2 || want_sums) wave_table_sums<W>(g, C.t1, C.s1, want_sums);
     if (C.nr == 2) {
         double mp[5], m2[5];
         maxwell_raw(C.r1.P, g.dV, C.s1, mp);
         for (int q = 0; q < 5; ++q) m2[q] = C.r1.a * mp[q] + (1.0 - C.r1.a) * C.raw[q];
         moments_from_raw(m2, &C.r2);
         finish_relax(I, tb, &C.r2);
-        lane_tables(g, C.r2.V, C.r2.T, C.t2);
-        if (want_sums) wave_table_sums(g, C.t2, C.s2, true);
+        lane_tables<W>(g, C.r2.V, C.r2.T, C.t2);
+        if (want_sums) wave_table_sums<W>(g, C.t2, C.s2, true);
         C.c0 = (1.0 - C.r1.a) * (1.0 - C.r2.a);
         C.cA = C.r1.a * (1.0 - C.r2.a) * C.r1.P;
         C.cB = C.r2.a * C.r2.P;
@@ -498,11 +503,11 @@ __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, 
 
 // Write one entry: c0, TX1 = cA eA_x, TY1 = eA_y, TX2 = cB eB_x, TY2 = eB_y,
 // TZ = (eA_z, eB_z) interleaved.
-template <typename real>
+template <typename real, int W = 64>
 __device__ __forceinline__ void write_entry(const Geo &g, real *E, double c0, double cA, const Tables &tA, double cB,
                                             const Tables &tB)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (W - 1);
     if (lane == 0) {
         E[0] = (real)c0;
         // float entries also keep c0 in double (slots 2-3, 8-byte aligned): the
@@ -512,7 +517,7 @@ __device__ __forceinline__ void write_entry(const Geo &g, real *E, double c0, do
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int k = lane + 64 * q;
+        const int k = lane + W * q;
         if (k < g.nvx) {
             E[g.tx1 + k] = (real)(cA * tA.e[0][q]);
             E[g.tx2 + k] = (real)(cB * tB.e[0][q]);
@@ -541,8 +546,8 @@ __device__ __forceinline__ int wall_of_entry(const Inst &I, int k, int *pos)
 }
 
 // Table entry e (a cell, or a ghost source after the ncells cells), computed by
-// the calling wave from the partial moment sums of the streaming input.
-template <typename real>
+// the calling W-lane segment from the partial moment sums of the streaming input.
+template <typename real, int W>
 __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const double *partial, real *params)
 {
     const Geo &g = A.g;
@@ -550,8 +555,8 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     Coef C;
     if (e < A.ncells) {
         const int ii = find_inst(A.cell_prefix, A.ninst, e);
-        cell_coefficients(A, A.inst[ii], e, mode, partial, C, false);
-        write_entry<real>(g, E, C.c0, C.cA, C.t1, C.cB, C.t2);
+        cell_coefficients<W>(A, A.inst[ii], e, mode, partial, C, false);
+        write_entry<real, W>(g, E, C.c0, C.cA, C.t1, C.cB, C.t2);
         return;
     }
     // ghost sources
@@ -566,8 +571,8 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
         const double *st = k == 0 ? I.up : I.dn;
         const double V[3] = {st[1], 0.0, 0.0};
         Tables t;
-        lane_tables(g, V, st[2], t);
-        write_entry<real>(g, E, 0.0, st[0] * pi_t_m32(st[2]), t, 0.0, z);
+        lane_tables<W>(g, V, st[2], t);
+        write_entry<real, W>(g, E, 0.0, st[0] * pi_t_m32(st[2]), t, 0.0, z);
         return;
     }
     // Diffuse wall face, Eq. (bc_cavity): ghost = n_W Phi_W for velocities
@@ -578,12 +583,12 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     const int w = wall_of_entry(I, k, &pos);
     const int axis = w < 2 ? 0 : 1;
     const int adj = w == 0 ? pos * I.nx : w == 1 ? pos * I.nx + I.nx - 1 : w == 2 ? pos : (I.ny - 1) * I.nx + pos;
-    cell_coefficients(A, I, I.cell0 + adj, mode, partial, C, true);
+    cell_coefficients<W>(A, I, I.cell0 + adj, mode, partial, C, true);
     const double VW[3] = {w == 3 ? I.uw : 0.0, 0.0, 0.0};
     Tables tw;
-    lane_tables(g, VW, I.tw, tw);
+    lane_tables<W>(g, VW, I.tw, tw);
     double sw[3][5];
-    wave_table_sums(g, tw, sw, true);
+    wave_table_sums<W>(g, tw, sw, true);
     const int b1 = axis == 0 ? 1 : 0, b2 = 2;  // the two other components
     // incident: v_axis < 0 for walls 0, 2 (sum index 3), v_axis > 0 for walls 1, 3 (index 4)
     const bool lowwall = (w == 0 || w == 2);
@@ -599,25 +604,29 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     const double pw = pi_t_m32(I.tw);
     const double den = pw * g.dV * out_w * ow * sw[b2][0];
     (void)b1;
-    write_entry<real>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
-    if ((threadIdx.x & 63) == 1) E[1] = (real)(flux / den);  // n_W, read by the reverse sweep
+    write_entry<real, W>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
+    if ((threadIdx.x & (W - 1)) == 1) E[1] = (real)(flux / den);  // n_W, read by the reverse sweep
 }
 
-// Table preparation between streaming passes: one wave per entry.
-template <typename real>
+// Table preparation between streaming passes: one W-lane segment per entry,
+// 64 / W entries per wave (W = the smallest of 16, 32, 64 that holds the
+// largest velocity axis, so few lanes idle on small grids; every sum is a
+// butterfly inside the segment, and a segment's results equal those of a
+// whole wave with the extra lanes holding zeros).
+template <typename real, int W>
 __global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__ partial, real *__restrict__ params,
                                               int mode, int nentries, real *__restrict__ params_shock_copy)
 {
     // Tables of these modes follow a streaming pass: advance the rounding
     // counter once (stream order puts this after that pass's reads).
     if (blockIdx.x == 0 && threadIdx.x == 0 && (mode == MODE_MID || mode == MODE_FINAL)) A.pass[0] = A.pass[0] + 1u;
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= nentries) return;  // the whole wave leaves; no block barrier follows
-    prep_entry<real>(A, e, mode, partial, params);
+    const int e = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / W) + (int)((threadIdx.x & 63) / W);
+    if (e >= nentries) return;  // the whole segment leaves; sums never leave a segment
+    prep_entry<real, W>(A, e, mode, partial, params);
     // Far-field entries never change: give the other parity buffer a copy.
     if (params_shock_copy && e >= A.ncells) {
         const int ii = find_inst(A.pseudo_prefix, A.ninst, e - A.ncells);
-        if (A.inst[ii].kind == KIND_SHOCK) prep_entry<real>(A, e, mode, partial, params_shock_copy);
+        if (A.inst[ii].kind == KIND_SHOCK) prep_entry<real, W>(A, e, mode, partial, params_shock_copy);
     }
 }
 
@@ -728,14 +737,16 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // jz modulo ZR); it loops over jz = z0 + zr, z0 + zr + ZR, ... < z1.  The host
 // picks VEC so that all v_x of a group share a sign, and ZR so that the task
 // count fills whole waves.
+// UNR, PD: the jz pipeline -- UNR planes per stage (1 or 2); with one plane
+// per stage, PD planes in flight ahead of the one computed (1 to 3).
 // NTSTORE: store the output non-temporally (chosen by the host when the working
 // set exceeds the last-level cache; a plain store otherwise).
 // ZU: one jz residue (ZR = 1), so all lanes of a wave walk the same plane.
-// The plane's byte offset is then wave-uniform: it goes into the scalar base
-// of the loads (no per-tap vector address arithmetic), and the z-tables of
-// the taps are re-laid out in LDS as [sign combination][jz][tap role][2] so
-// that one vector address per plane reaches every tap's pair through
-// immediate offsets.
+// The plane's byte offset is then wave-uniform: the taps are buffer loads
+// with it as their scalar offset (no per-tap vector address arithmetic), and
+// the z-tables of the taps are re-laid out in LDS as [sign combination][jz]
+// [tap role][2] so that one vector address per plane reaches every tap's
+// pair through immediate offsets.
 template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU>
 __global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
