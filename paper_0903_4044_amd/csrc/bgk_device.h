@@ -232,7 +232,14 @@ constexpr int BUF_WORD3 = 0x00020000;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_WORD3);
+    // The descriptor must sit in scalar registers (a descriptor the compiler
+    // takes for divergent costs a loop per load); its inputs are wave-uniform,
+    // and readfirstlane says so.
+    const uint64_t a = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void *p = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), BUF_WORD3);
 }
 
 template <typename V>
@@ -757,7 +764,16 @@ __global__ void __launch_bounds__(256)
     constexpr int NSLOT = DIM == 1 ? 7 : 13;
     real *sp = reinterpret_cast<real *>(smem);
     __shared__ SlotInfo SI;
+    // v_z and v_z^2 of every plane (wave-uniform per plane: one LDS broadcast
+    // instead of recomputing them per lane)
+    __shared__ double vzt[NVMAX][2];
     const Geo &g = A.g;
+    for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
+        const double vz = vnode(g, 2, k);
+        vzt[k][0] = vz;
+        vzt[k][1] = vz * vz;
+    }
+    // (the first barrier of the item loop orders these writes before any read)
     // Work items (cell, jz chunk).  A grid smaller than the item count makes
     // the kernel persistent: each workgroup walks items gridDim.x apart (a
     // multiple of 8 keeps every workgroup on one XCD's contiguous range).
@@ -906,7 +922,9 @@ __global__ void __launch_bounds__(256)
                     const real M = tc.l1[e] * a + tc.l2[e] * b;
                     const real d = __builtin_fmaf(c0m1_hi, hv[0][e], __builtin_fmaf(c0m1_lo, hv[0][e], M)) - (dx[e] + dy[e]);
                     const uint32_t hb = have ? hp[e] : hash32((ieven + (uint32_t)e) ^ key);
-                    r[e] = round_stochastic16((double)hv[0][e] + (double)d, odd ? (hb >> 16) : (hb & 0xffffu));
+                    // bits 0-15 for the even plane, 16-31 for the odd one
+                    r[e] = round_stochastic16((double)hv[0][e] + (double)d,
+                                              __builtin_amdgcn_ubfe(hb, odd ? 16u : 0u, 16u));
                 }
             } else {
                 r = u0 - dx - dy;
@@ -921,9 +939,8 @@ __global__ void __launch_bounds__(256)
                 A0[k] += hk;
                 s += hk;
             }
-            const double vz = vnode(g, 2, jz);
-            Az += vz * s;
-            Azz += vz * vz * s;
+            Az += vzt[jz][0] * s;
+            Azz += vzt[jz][1] * s;
         };
         // Software pipeline: the loads of the next UNR jz planes are issued
         // before the current ones are relaxed and streamed, so every wave keeps
