@@ -148,7 +148,8 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
  * bgk_init picks a default.  bgk_autotune times every valid shape on the
  * state f (device, f_elems elements, read only; synchronises the stream) and
  * keeps the fastest by the steady time of a real step (streaming pass and
- * table preparation, (10 steps - 2 steps) / 8; the four fastest of the
+ * table preparation, (10 steps - 2 steps) / 8, after an untimed warm-up
+ * of a few steps; the four fastest of the
  * sweep are timed twice more and ranked by their best time); it borrows a
  * temporary f-sized device buffer for the steps' output during the call (if
  * that allocation fails it times bare streaming passes over f instead); on

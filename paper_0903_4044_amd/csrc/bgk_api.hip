@@ -967,6 +967,11 @@ static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
         return tmp ? time_steps<real>(c, f, tmp, s, us) : time_stream<real>(c, f, s, 4, us);
     };
     int rc = BGK_OK;
+    if (tmp) {
+        // untimed warm-up: the first shapes of a cold device otherwise time slow
+        double us = 0.0;
+        for (int r = 0; r < 3 && !rc; ++r) rc = time_steps<real>(c, f, tmp, s, &us);
+    }
     for (int vec : {4, 2, 1}) {
         if (!vec_valid(c, vec)) continue;
         for (int unroll : {1, 2, 3, 4})
