@@ -263,17 +263,34 @@ __device__ __forceinline__ int mm_branch(real a, real b)
     return m == (real)0 ? 0 : (m == b ? 2 : 1);
 }
 
-// One direction's contribution (values in upwind order, see above).
+// Branch indicators of one limiter evaluation as numbers: p1 = [branch 1],
+// p2 = [branch 2] (mm_branch's cases), formed from the same median value.
+template <typename real>
+struct MmInd {
+    real p1, p2;
+};
+
+template <typename real>
+__device__ __forceinline__ MmInd<real> mm_ind(real a, real b)
+{
+    const real m = minmod3(a, b);
+    const bool nz = m != (real)0, eb = m == b;
+    return {nz && !eb ? (real)1 : (real)0, nz && eb ? (real)1 : (real)0};
+}
+
+// One direction's contribution (values in upwind order, see above).  The
+// branch codes enter only through 0/1 indicators, so the adjoint is a short
+// sum of exact integer multiples of the mu values.
 template <typename real>
 __device__ __forceinline__ real direction_adjoint(real um2, real um1, real u0, real u1, real u2, real mm1, real m0,
                                                   real m1, real m2, real C, real k)
 {
-    const int bm1 = mm_branch<real>(u0 - um1, um1 - um2);
-    const int b0 = mm_branch<real>(u1 - u0, u0 - um1);
-    const int b1 = mm_branch<real>(u2 - u1, u1 - u0);
-    const real A0 = (real)((b0 == 1) - (b0 == 2) + (bm1 == 1));
-    const real A1 = (real)((b1 == 2) - (b0 == 1) + (b0 == 2));
-    const real lim = m0 * A0 + m1 * A1 - (b1 == 2 ? m2 : (real)0) - (bm1 == 1 ? mm1 : (real)0);
+    const MmInd<real> bm1 = mm_ind<real>(u0 - um1, um1 - um2);
+    const MmInd<real> b0 = mm_ind<real>(u1 - u0, u0 - um1);
+    const MmInd<real> b1 = mm_ind<real>(u2 - u1, u1 - u0);
+    const real A0 = b0.p1 - b0.p2 + bm1.p1;
+    const real A1 = b1.p2 - b0.p1 + b0.p2;
+    const real lim = m0 * A0 + m1 * A1 - b1.p2 * m2 - bm1.p1 * mm1;
     return C * (m1 - m0) + C * k * lim;
 }
 
