@@ -110,7 +110,7 @@ def make_problem(cfg: dict) -> Problem:
     p.lid_mach = float(cfg.get("lid_mach", 0.0))
     p.t_wall = float(cfg.get("t_wall", 1.0))
     p.strang = 1 if cfg.get("splitting", "strang") == "strang" else 0
-    p.minmod = 1 if cfg.get("limiter", "minmod") == "minmod" else 0
+    p.minmod = {"minmod": 1, "none": 0, "shift": 2}[cfg.get("limiter", "minmod")]
     return p
 
 

@@ -25,7 +25,10 @@
  *
  * Readings of points the paper leaves open (all restated where used):
  *   - streaming is the one-step minmod-limited upwind scheme in flux form;
- *     with the limiter off it is Eq. (upwind) exactly;
+ *     with the limiter off it is Eq. (upwind) exactly; the paper's own
+ *     large-time-step form (Sec. 2.1, below Eq. (exact)) translates each
+ *     v_x by the integer part of its Courant number and applies Eq. (upwind)
+ *     to the fraction left ("shift" streaming, one-dimensional problems);
  *   - a time step is R_{dt/2} S_dt R_{dt/2} (Strang) or R_dt S_dt (Lie,
  *     the paper's order), every R using the moments of its own input;
  *   - two ghost layers per side: the far-field Maxwellians for the shock,
@@ -57,7 +60,7 @@ typedef struct {
     double lid_mach;
     double t_wall;
     int strang; /* 1: R_{dt/2} S R_{dt/2}; 0: R_dt S (Lie) */
-    int minmod; /* 1: minmod slopes; 0: first-order upwind */
+    int minmod; /* 1: minmod slopes; 0: first-order upwind; 2: shift + first-order upwind */
 } orc_problem;
 
 static const double GAMMA = 5.0 / 3.0;
@@ -317,12 +320,64 @@ static double face_value(double um1, double u0, double u1, double u2, double C, 
     return 0.0;
 }
 
+/* Free streaming over dt along x by translation (Sec. 2.1, Eq. (exact) and
+ * the text below it): the exact solution moves f by v_x dt.  With the
+ * Courant number C = v_x dt / dx, |C| = m + th (m its integer part), the
+ * value is first taken m cells upwind and Eq. (upwind) is then applied over
+ * the fraction th:
+ *     out_i = (1 - th) g_{i - s m} + th g_{i - s (m + 1)},   s = sign(v_x).
+ * Positions outside [0, nx) hold the far-field Maxwellians of Eq. (bc_shock)
+ * (upstream for x < 0) or the periodic images.  One-dimensional problems. */
+static void stream_shift(const orc_problem *p, const double *gs, double *out, double dt)
+{
+    velgrid g = make_velgrid(p);
+    const int nx = p->nx;
+    const long nv = nvel(p);
+    const double dx = dxs(p);
+    double *up = 0, *dn = 0;
+    if (p->kind == ORC_SHOCK) {
+        double su[3], sd[3];
+        orc_rankine_hugoniot(p->mach, su, sd);
+        double Vu[3] = {su[1], 0, 0}, Vd[3] = {sd[1], 0, 0};
+        up = malloc(sizeof(double) * nv);
+        dn = malloc(sizeof(double) * nv);
+        maxwellian_on(&g, su[0], Vu, su[2], up);
+        maxwellian_on(&g, sd[0], Vd, sd[2], dn);
+    }
+#pragma omp parallel for schedule(static)
+    for (int ix = 0; ix < nx; ++ix) {
+        double *o = out + (long)ix * nv;
+        for (long j = 0; j < nv; ++j) {
+            const double C = g.vx[j] * dt / dx;
+            const long s = C > 0.0 ? 1 : -1;
+            const double a = fabs(C);
+            const long m = (long)floor(a);
+            const double th = a - (double)m;
+            double val[2];
+            for (int k = 0; k < 2; ++k) {
+                long pos = ix - s * (m + k);
+                if (pos >= 0 && pos < nx) val[k] = gs[pos * nv + j];
+                else if (p->kind == ORC_SHOCK) val[k] = pos < 0 ? up[j] : dn[j];
+                else val[k] = gs[(((pos % nx) + nx) % nx) * nv + j];
+            }
+            o[j] = (1.0 - th) * val[0] + th * val[1];
+        }
+    }
+    free(up);
+    free(dn);
+    free_velgrid(&g);
+}
+
 /* Free streaming over dt, Eq. (freestreaming), in flux form:
  *   out_i = g_i - sum_d C_d (face_{i+1/2} - face_{i-1/2}),  C_d = v_d dt / dx_d,
  * every face built from the same input g.  g is first copied into an array
  * with two ghost layers on each side of each streaming direction. */
 void orc_stream(const orc_problem *p, const double *gs, double *out, double dt)
 {
+    if (p->minmod == 2) {
+        stream_shift(p, gs, out, dt);
+        return;
+    }
     velgrid g = make_velgrid(p);
     const int two = is2d(p);
     const int nx = p->nx, ny = two ? p->ny : 1;

@@ -319,6 +319,71 @@ def test_lid_shear_no_slip_and_limit(oracle_mod):
     assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
 
 
+# ------------------------------------------------------- shift streaming
+
+
+def test_shift_streaming_integer_courant_is_translation(oracle_mod):
+    """Sec. 2.1, Eq. (exact) and the text below it: with integer Courant
+    numbers the shift form moves each v_x column by exactly C cells."""
+    cfg = prob(kind="periodic1d", nx=11, x0=0.0, x1=11.0, nv=(4, 2, 2), vlo=(-2,) * 3, vhi=(2,) * 3,
+               dt=2.0, limiter="shift")
+    O = oracle_mod.Oracle(cfg)  # v_x = -1.5, -0.5, 0.5, 1.5; dx = 1 -> C = -3, -1, 1, 3
+    g = inputs.uniform(O.shape, seed=71, lo=0.0, hi=1.0)
+    out = O.stream(g, 2.0)
+    vx, _, _ = O.velocity_nodes()
+    want = np.empty_like(g)
+    for j in range(O.nvel):
+        want[:, j] = np.roll(g[:, j], int(round(vx[j] * 2.0)))
+    np.testing.assert_array_equal(out, want)
+
+
+def test_shift_streaming_below_unit_courant_is_eq_upwind(oracle_mod):
+    """With |C| < 1 the integer part is zero and the shift form is Eq. (upwind)."""
+    cfg = prob(kind="periodic1d", nx=9, nv=(6, 2, 2), vlo=(-3,) * 3, vhi=(3,) * 3, limiter="shift")
+    O = oracle_mod.Oracle(cfg)
+    Ou = oracle_mod.Oracle(dict(cfg, limiter="none"))
+    g = inputs.uniform(O.shape, seed=72, lo=0.1, hi=1.0)
+    np.testing.assert_allclose(O.stream(g, O.dt), Ou.stream(g, O.dt), rtol=1e-14, atol=1e-16)
+
+
+def test_shift_streaming_large_courant(oracle_mod):
+    """Large fractional Courant numbers on a periodic box: each column is a
+    convex combination of two translated copies, so its sum is kept and the
+    result matches interpolation of the exact translation of linear data."""
+    cfg = prob(kind="periodic1d", nx=13, x0=0.0, x1=13.0, nv=(6, 2, 2), vlo=(-3,) * 3, vhi=(3,) * 3,
+               dt=3.3, limiter="shift")
+    O = oracle_mod.Oracle(cfg)  # C = v_x * 3.3: -8.25, -4.95, -1.65, 1.65, 4.95, 8.25
+    g = inputs.uniform(O.shape, seed=73, lo=0.1, hi=1.0)
+    out = O.stream(g, 3.3)
+    np.testing.assert_allclose(out.sum(axis=0), g.sum(axis=0), rtol=1e-14)
+    vx, _, _ = O.velocity_nodes()
+    # exact translation of a periodic sampled profile, evaluated by linear
+    # interpolation between the two neighbouring grid points
+    for j in range(O.nvel):
+        C = vx[j] * 3.3
+        xs = (np.arange(13) - C) % 13
+        lo = np.floor(xs).astype(int)
+        w = xs - lo
+        want = (1 - w) * g[lo % 13, j] + w * g[(lo + 1) % 13, j]
+        np.testing.assert_allclose(out[:, j], want, rtol=1e-13)
+
+
+def test_shift_streaming_far_field_inflow(oracle_mod):
+    """Shock box, Courant numbers above the box width from the upstream side:
+    every cell reached from outside takes the far-field Maxwellian (Eq. bc_shock)."""
+    cfg = prob(kind="shock", nx=6, x0=-3.0, x1=3.0, nv=(4, 2, 2), vlo=(-2,) * 3, vhi=(10,) * 3,
+               mach=1.5, dt=2.5, limiter="shift")
+    O = oracle_mod.Oracle(cfg)  # v_x = -0.5, 2.5, 5.5, 8.5, dx = 1 -> C = -1.25, 6.25, 13.75, 21.25
+    g = inputs.uniform(O.shape, seed=74, lo=0.1, hi=1.0)
+    out = O.stream(g, 2.5)
+    vx, _, _ = O.velocity_nodes()
+    up = O.initial_state()[0]  # the upstream Maxwellian (cell 0 lies at x < 0)
+    for j in range(O.nvel):
+        C = vx[j] * 2.5
+        if C >= 7.0:  # both sources of every cell lie left of the box
+            np.testing.assert_allclose(out[:, j], up[j], rtol=1e-14)
+
+
 # ------------------------------------------------------------------ twin
 
 
@@ -334,6 +399,20 @@ def test_twin_agrees(oracle_mod, kind, splitting, limiter):
     O, W = oracle_mod.Oracle(cfg), Twin(cfg)
     f = O.initial_state() * (1 + 0.3 * inputs.uniform(O.shape, seed=29, lo=-1, hi=1))
     assert W.dt == pytest.approx(O.dt, rel=1e-15)
+    np.testing.assert_allclose(O.step(f, 3), W.step(f, 3), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["shock", "periodic1d"])
+@pytest.mark.parametrize("cfl", [0.7, 3.6])
+def test_twin_agrees_shift(oracle_mod, kind, cfl):
+    """The C oracle's shift streaming and the twin's separately written one
+    (index gathers) agree to rounding after three Lie steps, below and above
+    unit Courant number."""
+    from oracle.twin import Twin
+    cfg = prob(kind=kind, nx=7, nv=(6, 3, 2), vlo=(-3, -3, -2), vhi=(4, 3, 2), kn=0.4, mach=1.5,
+               x0=-1.0 if kind == "shock" else 0.0, cfl=cfl, splitting="lie", limiter="shift")
+    O, W = oracle_mod.Oracle(cfg), Twin(cfg)
+    f = O.initial_state() * (1 + 0.3 * inputs.uniform(O.shape, seed=75, lo=-1, hi=1))
     np.testing.assert_allclose(O.step(f, 3), W.step(f, 3), rtol=1e-12, atol=1e-15)
 
 
