@@ -65,6 +65,9 @@ extern "C" {
 #define BGK_LIE 1           /* R_dt S_dt (Sec. 2.1) */
 #define BGK_MINMOD 0        /* second-order minmod-limited upwind */
 #define BGK_NOLIMIT 1       /* first-order upwind, Eq. (upwind) */
+#define BGK_SHIFT 2         /* translation form of Sec. 2.1: shift by the integer part of the
+                               Courant number, Eq. (upwind) over the fraction; one-dimensional
+                               kinds, any Courant number (no Courant limit) */
 
 #define BGK_FP64 0          /* f stored and streamed in double */
 #define BGK_FP32 1          /* f stored and streamed in float; moments, Maxwellian
@@ -87,7 +90,8 @@ typedef struct bgk_problem {
     double lid_mach;        /* cavity: lid speed as a Mach number at T_r, U_W = Ma sqrt(5/6) */
     double t_wall;          /* cavity: wall temperature, > 0 */
     int splitting;          /* BGK_STRANG or BGK_LIE */
-    int limiter;            /* BGK_MINMOD or BGK_NOLIMIT */
+    int limiter;            /* BGK_MINMOD, BGK_NOLIMIT or BGK_SHIFT (all instances of a context
+                               use BGK_SHIFT or none does) */
 } bgk_problem;
 
 typedef struct bgk_ctx bgk_ctx;
@@ -97,8 +101,10 @@ typedef struct bgk_ctx bgk_ctx;
  * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
  * instance's dt, and allocates the context's device work space on the current
  * device.  precision: BGK_FP64 or BGK_FP32.
- * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3), BGK_E_UNSUPPORTED
- * (also when one workgroup's table entries, 2 (Nvx + Nvy + Nvz) values per
+ * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3; not checked for
+ * BGK_SHIFT), BGK_E_UNSUPPORTED (also for BGK_SHIFT on a two-dimensional
+ * kind or mixed with other limiters in one context, and when one workgroup's
+ * table entries, 2 (Nvx + Nvy + Nvz) values per
  * stencil slot, exceed the device's LDS per workgroup), BGK_E_HIP.  On
  * failure *out is NULL. */
 int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out);
@@ -144,7 +150,8 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
  * per stage, 2 or 3 planes ahead), jz chunks per cell (one work item each,
  * 1 .. a context-dependent maximum), and persist: 0 launches one workgroup
  * per work item, k > 0 launches k workgroups per compute unit that walk the
- * items of all instances (one persistent launch for a batch).
+ * items of all instances (one persistent launch for a batch).  Contexts
+ * with BGK_SHIFT streaming take vec 1 and unroll 1 only.
  * bgk_init picks a default.  bgk_autotune times every valid shape on the
  * state f (device, f_elems elements, read only; synchronises the stream) and
  * keeps the fastest by the steady time of a real step (streaming pass and
@@ -218,7 +225,8 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * of magnitudes).  The first call allocates the context's reverse-sweep work
  * space (two extra f buffers and per-cell coefficients); BGK_E_HIP if that
  * fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9 (1D) table entries per
- * workgroup exceed the device's LDS.  Asynchronous on `stream`. */
+ * workgroup exceed the device's LDS, or for BGK_SHIFT contexts (no reverse
+ * sweep of the translation form).  Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *stream);
 

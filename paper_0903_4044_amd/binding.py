@@ -110,7 +110,7 @@ def to_struct(cfg: dict) -> Problem:
     p.lid_mach = float(cfg.get("lid_mach", 0.0))
     p.t_wall = float(cfg.get("t_wall", 1.0))
     p.splitting = 0 if cfg.get("splitting", "strang") == "strang" else 1
-    p.limiter = 0 if cfg.get("limiter", "minmod") == "minmod" else 1
+    p.limiter = {"minmod": 0, "none": 1, "shift": 2}[cfg.get("limiter", "minmod")]
     return p
 
 

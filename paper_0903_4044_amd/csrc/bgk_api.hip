@@ -43,6 +43,7 @@ struct bgk_ctx {
     int sblock = 256;          // streaming kernel: threads per workgroup
     int unroll = 1;            // streaming kernel: jz values whose loads are issued together
     int persist = 0;           // streaming kernel: 0 one workgroup per item, else resident workgroups per CU
+    bool shift = false;        // every instance streams in the translation form (k_shift)
     // hipGraph replay of two-step chunks (stream, prep, stream, prep); key:
     // (f_out, which buffer the chunk starts from, table parity)
     bool use_graph = false;
@@ -181,13 +182,18 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (!(p.kn > 0.0) || !std::isfinite(p.kn)) return bad("Kn must be > 0");
     if (!std::isfinite(p.omega)) return bad("omega must be finite");
     if (p.splitting != BGK_STRANG && p.splitting != BGK_LIE) return bad("unknown splitting");
-    if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT) return bad("unknown limiter");
+    if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT && p.limiter != BGK_SHIFT) return bad("unknown limiter");
+    if (p.limiter == BGK_SHIFT && two) {
+        snprintf(b, sizeof b, "problem %d: shift streaming is one-dimensional", idx);
+        msg = b;
+        return BGK_E_UNSUPPORTED;
+    }
     if (p.kind == BGK_SHOCK_1D && !(p.mach > 1.0)) return bad("shock needs Mach > 1");
     if (p.kind == BGK_CAVITY_2D && !(p.t_wall > 0.0)) return bad("wall temperature must be > 0");
     if (!(p.dt > 0.0) && !(p.cfl > 0.0)) return bad("need dt > 0 or cfl > 0");
     const double rate = courant_rate(p, two);
     const double dt = p.dt > 0.0 ? p.dt : p.cfl / rate;
-    if (dt * rate > 2.0 / 3.0 * (1.0 + 1e-12)) {
+    if (p.limiter != BGK_SHIFT && dt * rate > 2.0 / 3.0 * (1.0 + 1e-12)) {
         snprintf(b, sizeof b, "problem %d: Courant sum %.6g exceeds 2/3", idx, dt * rate);
         msg = b;
         return BGK_E_CFL;
@@ -207,6 +213,7 @@ static bool vec_valid(const bgk_ctx *c, int v)
 {
     const Geo &g = c->geo;
     if (v == 1) return true;
+    if (c->shift) return false;  // the translation-form kernel takes one jx per lane task
     if (v == 4 && c->precision == BGK_FP64) return false;
     if (g.nvx % v) return false;
     for (int k = 0; k < g.nvx; k += v) {
@@ -264,7 +271,7 @@ static void choose_launch(bgk_ctx *c)
     for (int v : {4, 2})
         if (vec_valid(c, v)) { vec = v; break; }
     if (c->dim == 2) vec = 1;
-    const int unroll = (c->dim == 1 && c->precision == BGK_FP32) ? 2 : 1;
+    const int unroll = (c->dim == 1 && c->precision == BGK_FP32 && !c->shift) ? 2 : 1;
     const int target = c->dim == 1 ? (c->precision == BGK_FP32 ? 1024 : 512) : 2048;
     set_shape(c, vec, unroll, vsplit_for(c, target));
     c->block = 256;
@@ -283,6 +290,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
         const bgk_problem &p = probs[i], &q = probs[0];
         if (is2d_kind(p.kind) != is2d_kind(q.kind))
             return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must have the same dimension");
+        if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
+            return fail(nullptr, BGK_E_UNSUPPORTED, "shift streaming cannot share a context with other limiters");
         for (int a = 0; a < 3; ++a)
             if (p.nv[a] != q.nv[a] || p.vlo[a] != q.vlo[a] || p.vhi[a] != q.vhi[a])
                 return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must share the velocity grid");
@@ -292,6 +301,7 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     c->esize = precision == BGK_FP64 ? 8 : 4;
     c->ninst = n_probs;
     c->dim = is2d_kind(probs[0].kind) ? 2 : 1;
+    c->shift = probs[0].limiter == BGK_SHIFT;
     c->probs.assign(probs, probs + n_probs);
     (void)hipGetDevice(&c->device);
     {
@@ -354,6 +364,7 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
         I.cell0 = c->h_cell_prefix.back();
         I.strang = p.splitting == BGK_STRANG;
         I.minmod = p.limiter == BGK_MINMOD;
+        I.shift = p.limiter == BGK_SHIFT;
         I.f0 = f_off;
         const double dx = (p.x1 - p.x0) / p.nx, dy = two ? (p.y1 - p.y0) / p.ny : 1.0;
         I.dt = p.dt > 0.0 ? p.dt : p.cfl / courant_rate(p, two);
@@ -607,7 +618,15 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         c->ev_used++;
         HIP_TRY(c, hipEventRecord(e0, s));
     }
-    if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
+    if (c->shift) {
+        const real *p = (const real *)params_buf<real>(c, c->pass_parity);
+        if (stream_nt(c))
+            hipLaunchKernelGGL((k_shift<real, true>), dim3(nb), dim3(c->sblock), 0, s, make_args(c),
+                               (const real *)src, (real *)dst, p, c->partial);
+        else
+            hipLaunchKernelGGL((k_shift<real, false>), dim3(nb), dim3(c->sblock), 0, s, make_args(c),
+                               (const real *)src, (real *)dst, p, c->partial);
+    } else if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
     else stream_dispatch<real, 1>(c, nb, lds, src, dst, s);
     HIP_TRY(c, hipGetLastError());
     if (c->timing) HIP_TRY(c, hipEventRecord(e1, s));
@@ -841,6 +860,7 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (lam_n == f_n || lam_n == lam_next) return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: lam_n must not alias inputs");
     if (!ctx->adjoint_fits)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
+    if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
                                       : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
@@ -978,6 +998,7 @@ static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
             for (int vs : splits)
                 for (int ps : {0, 2, 4}) {
                     if (rc) break;
+                    if (c->shift && unroll != 1) continue;  // k_shift has one pipeline form
                     if (ps && c->ncells * vs <= ps * c->ncu) continue;  // grid already resident
                     Cand k{0.0, vec, unroll, vs, ps};
                     rc = measure(k, &k.us);
@@ -1030,8 +1051,8 @@ extern "C" int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vs
 extern "C" int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int persist)
 {
     if (!ctx) return BGK_E_INVALID;
-    if (!(vec == 1 || vec == 2 || vec == 4) || !vec_valid(ctx, vec) || unroll < 1 || unroll > 4 || vsplit < 1 ||
-        vsplit > ctx->vsplit_max || persist < 0 || persist > 64)
+    if (!(vec == 1 || vec == 2 || vec == 4) || !vec_valid(ctx, vec) || unroll < 1 || unroll > 4 ||
+        (ctx->shift && unroll != 1) || vsplit < 1 || vsplit > ctx->vsplit_max || persist < 0 || persist > 64)
         return fail(ctx, BGK_E_INVALID, "bgk_set_launch: shape not valid for this context");
     set_shape(ctx, vec, unroll, vsplit, persist);
     return BGK_OK;

@@ -43,6 +43,7 @@ struct Inst {
     int cell0;      // first global cell index of the instance
     int pseudo0;    // first global params entry of its ghost sources
     int strang, minmod;
+    int shift;      // translation form of the streaming step (k_shift)
     long long f0;   // element offset of the instance in f
     double cx, cy;  // dt / dx, dt / dy
     double dt, kn, omega;
@@ -1060,6 +1061,127 @@ __global__ void __launch_bounds__(256)
     }
     block_sum_store<NQ>(acc, partial + (long long)L * NQ);
     __syncthreads();  // LDS (slots, tables, reduction) is reused by the next item
+    }
+}
+
+// ---------------------------------------------------------------- shift
+// Streaming pass in the translation form of Sec. 2.1 (the text below Eq.
+// (exact)), for one-dimensional instances and any Courant number: with
+// C = v_x dt / dx, |C| = m + th, the value of cell i is taken from cells
+// a = i - s m and b = i - s (m + 1) (s = sign v_x) and blended over the
+// fraction th as in Eq. (upwind):
+//     out = u_a - th (u_a - u_b),   u = the relaxed input (table entries of a, b).
+// A lane task is one (jx, jy) at one jz residue, as in the per-cell kernel
+// with VEC = 1; the two sources and their entries depend on v_x, so each
+// lane resolves them itself (entries from global memory instead of the
+// workgroup's slot table).  With |C| < 1 (m = 0) every operation, the
+// rounding bits and the moment epilogue are those of the per-cell kernel
+// with the limiter off, so the two agree bit for bit there.
+template <typename real, bool NTSTORE>
+__global__ void __launch_bounds__(256)
+    k_shift(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
+            double *__restrict__ partial)
+{
+    using V = vec_t<real, 1>;
+    __shared__ double vzt[NVMAX][2];
+    const Geo &g = A.g;
+    for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
+        const double vz = vnode(g, 2, k);
+        vzt[k][0] = vz;
+        vzt[k][1] = vz * vz;
+    }
+    __syncthreads();
+    const int nitems = A.ncells * A.vsplit;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int Lq = xcd_remap(item, nitems);
+        const int gq = Lq / A.vsplit, split = Lq % A.vsplit;
+        const int ii = find_inst(A.cell_prefix, A.ninst, gq);
+        const Inst &I = A.inst[ii];
+        const int c = gq - I.cell0;
+        const int L = gq * A.vsplit + split;
+        const real *base = src + I.f0;
+        real *outb = dst + I.f0;
+        const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, (uint32_t)((long long)I.ncell * g.nv * sizeof(real)));
+        const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
+        const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+        const int ntask = g.npl * A.zr;
+        const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
+        const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;
+        const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
+        double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+            const int p0 = task % g.npl, zr = task / g.npl;
+            const int jy = p0 / g.nvx, jx = p0 - jy * g.nvx;
+            const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
+            const double ac = fabs(vx) * I.cx;
+            const int m = (int)floor(ac);
+            const real th = (real)(ac - (double)m);
+            const int sgn = vx > 0.0 ? 1 : -1;
+            // the two sources: cell of h and table entry (ghosts read cell c; their entries have c0 = 0)
+            Tap<real, 1> tp[2];
+            const real *Ez[2];
+            for (int k = 0; k < 2; ++k) {
+                const int pos = c - sgn * (m + k);
+                int cell, par;
+                if (pos >= 0 && pos < I.nx) { cell = pos; par = I.cell0 + pos; }
+                else if (I.kind == KIND_PER1) { cell = ((pos % I.nx) + I.nx) % I.nx; par = I.cell0 + cell; }
+                else { cell = c; par = I.pseudo0 + (pos < 0 ? 0 : 1); }
+                const real *E = params + (long long)par * g.pe;
+                tp[k] = make_tap_at<real, 1>(g, E, cell, p0, jx, jy);
+                Ez[k] = E + g.tz;
+            }
+            // c0 - 1 of source a as a two-float sum (float path)
+            float c0m1_hi = 0.0f, c0m1_lo = 0.0f;
+            if constexpr (sizeof(real) == 4) {
+                const double c0m1 = *reinterpret_cast<const double *>(Ez[0] - g.tz + 2) - 1.0;
+                c0m1_hi = (float)c0m1;
+                c0m1_lo = (float)(c0m1 - (double)c0m1_hi);
+            }
+            double A0 = 0.0, Az = 0.0, Azz = 0.0;
+            int jz = z0 + zr;
+            if (jz < z1) {
+                const int zlast = z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);
+                V h[2], hn[2];
+                auto load = [&](V (&hv)[2], int j) {
+                    const uint32_t so = (uint32_t)min(j, zlast) * zstep;
+                    hv[0] = buf_ld<V>(frs, tp[0].off, so);
+                    hv[1] = buf_ld<V>(frs, tp[1].off, so);
+                };
+                load(h, jz);
+                for (; jz < z1; jz += A.zr) {
+                    load(hn, jz + A.zr);
+                    const real a0 = Ez[0][2 * jz], b0 = Ez[0][2 * jz + 1];
+                    const V u0 = tp[0].relax_ab(h[0], a0, b0);
+                    const V u1 = tp[1].relax_ab(h[1], Ez[1][2 * jz], Ez[1][2 * jz + 1]);
+                    const real dx = th * (u0[0] - u1[0]), dy = 0;
+                    real r;
+                    if constexpr (sizeof(real) == 4) {
+                        const bool odd = (jz & 1) != 0;
+                        const uint32_t ieven = ecell + (uint32_t)p0 + (uint32_t)jz * (uint32_t)g.npl -
+                                               (odd ? (uint32_t)g.npl : 0u);
+                        const real M = tp[0].l1[0] * a0 + tp[0].l2[0] * b0;
+                        const real d = __builtin_fmaf(c0m1_hi, h[0][0], __builtin_fmaf(c0m1_lo, h[0][0], M)) - (dx + dy);
+                        const uint32_t hb = hash32(ieven ^ key);
+                        r = round_stochastic16((double)h[0][0] + (double)d, __builtin_amdgcn_ubfe(hb, odd ? 16u : 0u, 16u));
+                    } else {
+                        r = u0[0] - dx - dy;
+                    }
+                    real *op = reinterpret_cast<real *>(reinterpret_cast<char *>(outb) + out0 +
+                                                        (uint32_t)jz * zstep + (uint32_t)(p0 * sizeof(real)));
+                    if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
+                    else *op = r;
+                    const double hk = (double)r;
+                    A0 += hk;
+                    Az += vzt[jz][0] * hk;
+                    Azz += vzt[jz][1] * hk;
+                    h[0] = hn[0];
+                    h[1] = hn[1];
+                }
+            }
+            fold_column(acc, vx, vy, A0, Az, Azz);
+        }
+        block_sum_store<NQ>(acc, partial + (long long)L * NQ);
+        __syncthreads();
     }
 }
 

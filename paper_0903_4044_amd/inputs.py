@@ -22,7 +22,9 @@ density in n_r, length in the domain unit, time in length / sqrt(2 R T_r)):
     lid_mach   cavity: lid speed as a Mach number at the wall temperature
     t_wall     cavity: wall temperature
     splitting  'strang' (R_{dt/2} S_dt R_{dt/2}) or 'lie' (R_dt S_dt, Sec. 2.1)
-    limiter    'minmod' (second order) or 'none' (first-order upwind, Eq. upwind)
+    limiter    'minmod' (second order), 'none' (first-order upwind, Eq. upwind) or
+               'shift' (Sec. 2.1 translation form: integer part of the Courant
+               number as a shift, Eq. upwind over the fraction; 1D kinds)
     steps      number of time steps of the workload
     precision  'fp64' or 'fp32' (storage/streaming precision of f)
 """
@@ -62,6 +64,18 @@ CONFIGS = {
                              vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
                              lid_mach=0.1, t_wall=1.0, steps=5000,
                              precision="fp32"),
+    # The paper's own shock runs (Sec. 4.1): L = 70 mean free paths, Nx up to
+    # 18432, dt = 0.05, Lie splitting, translation-form first-order streaming
+    # (Courant numbers up to ~150 here), viscosity exponent 0.74, the paper's
+    # velocity boxes (16^3 for Mach 1.5, 30^3 for Mach 3), FP32 f.
+    "shock_m1.5_paper": _base(kind="shock", nx=18432, x0=-35.0, x1=35.0,
+                              nv=(16, 16, 16), vlo=(-5.0, -6.0, -6.0), vhi=(7.0, 6.0, 6.0),
+                              kn=1.0, omega=0.74, dt=0.05, mach=1.5, splitting="lie",
+                              limiter="shift", steps=400, precision="fp32"),
+    "shock_m3_paper": _base(kind="shock", nx=18432, x0=-35.0, x1=35.0,
+                            nv=(30, 30, 30), vlo=(-10.0, -11.0, -11.0), vhi=(12.0, 11.0, 11.0),
+                            kn=1.0, omega=0.74, dt=0.05, mach=3.0, splitting="lie",
+                            limiter="shift", steps=200, precision="fp32"),
     # Adjoint workload: 64^2 cavity, 200 steps.
     "cavity_64_adjoint": _base(kind="cavity", nx=64, ny=64, nv=(24, 24, 24),
                                vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,

@@ -80,3 +80,16 @@ def test_init_rejects_bad_precision_and_mixed_grids(B):
 def test_cavity_courant_sum_limit(B):
     cfg = inputs.config("cavity_128_fp32", cfl=0.66)
     assert init_code(B, dict(cfg, cfl=0.7))[0] == B.E_CFL
+
+
+def test_shift_streaming_rules(B):
+    """Translation-form streaming: no Courant limit, one-dimensional kinds
+    only, and not mixed with other limiters in one context."""
+    big = inputs.config("shock_m1.5_fp64", limiter="shift", splitting="lie", dt=0.5)
+    assert init_code(B, dict(big, limiter="none"))[0] == B.E_CFL
+    cav = inputs.config("cavity_64_adjoint", limiter="shift")
+    assert init_code(B, cav)[0] == B.E_UNSUPPORTED
+    h = ctypes.c_void_p()
+    mixed = (B.Problem * 2)(B.to_struct(big), B.to_struct(inputs.config("shock_m1.5_fp64")))
+    assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED
+    assert not h.value
