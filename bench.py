@@ -260,14 +260,17 @@ def main():
         runs = [("shock_m1.5_fp64", [inputs.config("shock_m1.5_fp64")], "fp64", 200, 10, False),
                 ("cavity_128_fp32", [inputs.config("cavity_128_fp32")], "fp32", 200, 10, False),
                 ("batch_64_cavities_fp32", inputs.batch_cavities(), "fp32", 20, 2, False),
-                ("batch_64_cavities_fp32_graph", inputs.batch_cavities(), "fp32", 20, 2, True)]
+                ("batch_64_cavities_fp32_graph", inputs.batch_cavities(), "fp32", 20, 2, True),
+                # the paper's own shock runs: translation streaming, Courant numbers up to ~150
+                ("shock_m1.5_paper_fp32", [inputs.config("shock_m1.5_paper")], "fp32", 100, 10, False),
+                ("shock_m3_paper_fp32", [inputs.config("shock_m3_paper")], "fp32", 50, 5, False)]
         wanted = set(x for x in args.extras.split(",") if x)
         for name, probs, p, steps, warm, graph in runs:
             if wanted and name not in wanted:
                 continue
             s, k, pts, shp = run_workload(binding, torch, probs, p, steps, warm, True, True, graph)
-            e = {"updates_per_s": pts * steps / s, "steps": steps, "points": pts, "launch": shp,
-                 "precision": p, "graph": graph}
+            e = {"updates_per_s": pts * steps / s, "ns_per_update": s / (pts * steps) * 1e9, "steps": steps,
+                 "points": pts, "launch": shp, "precision": p, "graph": graph}
             if k == k:  # timed kernels (not NaN)
                 a = bytes_per_update(p) * pts / (k * 1e-3) / 1e9
                 e.update({"kernel_ms": k, "achieved_GBs": a, "frac": a / PEAK_HBM_GBS})
