@@ -39,6 +39,7 @@ class Problem(ctypes.Structure):
         ("mach", ctypes.c_double), ("lid_mach", ctypes.c_double),
         ("t_wall", ctypes.c_double),
         ("strang", ctypes.c_int), ("minmod", ctypes.c_int),
+        ("conservative", ctypes.c_int),
     ]
 
 
@@ -71,6 +72,8 @@ def lib():
         L.orc_collision_frequency.argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.orc_collision_frequency.restype = ctypes.c_double
         L.orc_relax.argtypes = [P, dp, dp, ctypes.c_double]
+        L.orc_effective_parameters.argtypes = [P, ctypes.c_double, dp, ctypes.c_double, dp]
+        L.orc_effective_parameters.restype = ctypes.c_int
         L.orc_rankine_hugoniot.argtypes = [ctypes.c_double, dp, dp]
         L.orc_wall_density.argtypes = [P, dp, dp]
         L.orc_stream.argtypes = [P, dp, dp, ctypes.c_double]
@@ -111,6 +114,7 @@ def make_problem(cfg: dict) -> Problem:
     p.t_wall = float(cfg.get("t_wall", 1.0))
     p.strang = 1 if cfg.get("splitting", "strang") == "strang" else 0
     p.minmod = {"minmod": 1, "none": 0, "shift": 2}[cfg.get("limiter", "minmod")]
+    p.conservative = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
     return p
 
 
@@ -162,6 +166,14 @@ class Oracle:
     def collision_frequency(self, n, T) -> float:
         return self.L.orc_collision_frequency(ctypes.byref(self.p), float(n), float(T))
 
+    def effective_parameters(self, n, V, T):
+        """(n~, V~, T~) whose discretized Maxwellian has the grid moments
+        (n, V, T), and the number of Newton steps taken."""
+        q = np.empty(5)
+        Va = np.ascontiguousarray(V, dtype=np.float64)
+        it = self.L.orc_effective_parameters(ctypes.byref(self.p), float(n), _ptr(Va), float(T), _ptr(q))
+        return q, it
+
     def relax(self, f, tau) -> np.ndarray:
         f = self._f(f)
         out = np.empty(self.shape)
@@ -201,8 +213,13 @@ class Oracle:
         return self.L.orc_lid_shear(ctypes.byref(self.p), _ptr(f))
 
     # -- reverse sweep (hand-derived adjoint) -----------------------------
+    def _no_conservative(self):
+        if self.p.conservative:
+            raise NotImplementedError("the reverse sweep covers the point-value Maxwellian only")
+
     def relax_adjoint(self, x, mu, tau):
         """(dR_tau/dx)^T mu at x, and dL/dKn."""
+        self._no_conservative()
         x, mu = self._f(x), self._f(mu)
         out, g = np.empty(self.shape), np.zeros(1)
         self.L.orc_relax_adjoint(ctypes.byref(self.p), _ptr(x), _ptr(mu), _ptr(out), float(tau), _ptr(g))
@@ -210,6 +227,7 @@ class Oracle:
 
     def stream_adjoint(self, g_in, mu, dt=None):
         """(dS/dg)^T mu at g_in, and dL/dT_w."""
+        self._no_conservative()
         g_in, mu = self._f(g_in), self._f(mu)
         out, gt = np.empty(self.shape), np.zeros(1)
         self.L.orc_stream_adjoint(ctypes.byref(self.p), _ptr(g_in), _ptr(mu), _ptr(out),
@@ -218,6 +236,7 @@ class Oracle:
 
     def step_adjoint(self, f, lam_next):
         """lam_n = (d step/df)^T lam_next and (dL/dKn, dL/dT_w) of this step."""
+        self._no_conservative()
         f, lam_next = self._f(f), self._f(lam_next)
         out, grad = np.empty(self.shape), np.zeros(2)
         self.L.orc_step_adjoint(ctypes.byref(self.p), _ptr(f), _ptr(lam_next), _ptr(out), _ptr(grad))
@@ -225,6 +244,7 @@ class Oracle:
 
     def lid_shear_grad(self, f):
         """dL/df of the lid shear and its explicit (dL/dKn, dL/dT_w)."""
+        self._no_conservative()
         f = self._f(f)
         lam, grad = np.empty(self.shape), np.zeros(2)
         self.L.orc_lid_shear_grad(ctypes.byref(self.p), _ptr(f), _ptr(lam), _ptr(grad))

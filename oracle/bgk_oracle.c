@@ -33,7 +33,13 @@
  *     the paper's order), every R using the moments of its own input;
  *   - two ghost layers per side: the far-field Maxwellians for the shock,
  *     the diffuse-wall rule of Eq. (bc_cavity) for the cavity;
- *   - dt = CFL / max_j sum_d |v_d(j)| / dx_d over velocity cell centres.
+ *   - dt = CFL / max_j sum_d |v_d(j)| / dx_d over velocity cell centres;
+ *   - the conservative variant (Sec. 2.1, the remark after Eq. (exact)) takes
+ *     the effective (n~, V~, T~) as the exact root of "grid moments of the
+ *     discretized Maxwellian = the cell's n, V, T"; the collision frequency
+ *     keeps the cell's own n and T; far-field and wall Maxwellians stay point
+ *     values (their densities already come from Eq. (RH) and from the
+ *     zero-mass-flux rule).
  *
  * Storage: f[cell][jz][jy][jx] (velocity fastest), cell = iy * nx + ix.
  * Everything is double precision.  Loops are plain; OpenMP only splits the
@@ -61,6 +67,7 @@ typedef struct {
     double t_wall;
     int strang; /* 1: R_{dt/2} S R_{dt/2}; 0: R_dt S (Lie) */
     int minmod; /* 1: minmod slopes; 0: first-order upwind; 2: shift + first-order upwind */
+    int conservative; /* 1: relaxations use the effective Maxwellian parameters */
 } orc_problem;
 
 static const double GAMMA = 5.0 / 3.0;
@@ -192,8 +199,117 @@ double orc_collision_frequency(const orc_problem *p, double n, double T)
     return n * pow(T, 1.0 - p->omega) / p->kn;
 }
 
+/* ------------------------------------------ effective Maxwellian parameters */
+
+/* Solves the 5x5 system A x = b in place (Gaussian elimination with partial
+ * pivoting); returns 0, or -1 for a singular matrix. */
+static int solve5(double A[5][5], double b[5])
+{
+    for (int k = 0; k < 5; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 5; ++r)
+            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (A[piv][k] == 0.0) return -1;
+        if (piv != k) {
+            for (int c = 0; c < 5; ++c) {
+                double t = A[k][c];
+                A[k][c] = A[piv][c];
+                A[piv][c] = t;
+            }
+            double t = b[k];
+            b[k] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = k + 1; r < 5; ++r) {
+            double m = A[r][k] / A[k][k];
+            for (int c = k; c < 5; ++c) A[r][c] -= m * A[k][c];
+            b[r] -= m * b[k];
+        }
+    }
+    for (int k = 4; k >= 0; --k) {
+        double s = b[k];
+        for (int c = k + 1; c < 5; ++c) s -= A[k][c] * b[c];
+        b[k] = s / A[k][k];
+    }
+    return 0;
+}
+
+/* Effective Maxwellian parameters (Sec. 2.1, the remark on conservation
+ * after Eq. (exact)).  The point values of Eq. (Maxw) taken with a cell's
+ * (n, V, T) do not have exactly those moments on the velocity grid.  The
+ * effective values q = (n~, V~, T~) are the ones whose discretized Maxwellian
+ * has them:   M(Phi(q)) = (n, V, T),   M being the grid moments of
+ * Eq. (macroscopic) (cell_moments above).  The root is found by Newton's
+ * method started at (n, V, T), with the Jacobian of M(Phi(q)) from the chain
+ * rule over the grid nodes, at Phi(q)'s own moments (nd, Vd, Td):
+ *   d nd / d Phi_j   = dV,
+ *   d Vd_a / d Phi_j = dV (v_a - Vd_a) / nd,
+ *   d Td / d Phi_j   = (2/3) dV (|v - Vd|^2 - 3 Td / 2) / nd,
+ *   d Phi_j / d n~   = Phi_j / n~,
+ *   d Phi_j / d V~_a = Phi_j 2 (v_a - V~_a) / T~,
+ *   d Phi_j / d T~   = Phi_j (|v - V~|^2 / T~^2 - 3 / (2 T~)).
+ * The iteration stops once a step changes no parameter by more than 1e-14 of
+ * its scale (n~, sqrt(T~), T~), after one more step, or after 60 steps.
+ * phi is scratch of nv doubles.  Returns the number of Newton steps taken. */
+static int effective_parameters(const velgrid *g, double dV, double n, const double V[3], double T, double q[5],
+                                double *phi)
+{
+    q[0] = n;
+    q[1] = V[0];
+    q[2] = V[1];
+    q[3] = V[2];
+    q[4] = T;
+    int it = 0, polish = 0;
+    while (it < 60) {
+        double nd, Vd[3], Td;
+        maxwellian_on(g, q[0], q + 1, q[4], phi);
+        cell_moments(g, dV, phi, &nd, Vd, &Td);
+        double J[5][5] = {{0}}, r[5] = {nd - n, Vd[0] - V[0], Vd[1] - V[1], Vd[2] - V[2], Td - T};
+        for (long j = 0; j < g->nv; ++j) {
+            const double v[3] = {g->vx[j], g->vy[j], g->vz[j]};
+            double dM[5], dP[5], cd2 = 0.0, ct2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                cd2 += (v[a] - Vd[a]) * (v[a] - Vd[a]);
+                ct2 += (v[a] - q[1 + a]) * (v[a] - q[1 + a]);
+            }
+            dM[0] = dV;
+            for (int a = 0; a < 3; ++a) dM[1 + a] = dV * (v[a] - Vd[a]) / nd;
+            dM[4] = 2.0 / 3.0 * dV * (cd2 - 1.5 * Td) / nd;
+            dP[0] = phi[j] / q[0];
+            for (int a = 0; a < 3; ++a) dP[1 + a] = phi[j] * 2.0 * (v[a] - q[1 + a]) / q[4];
+            dP[4] = phi[j] * (ct2 / (q[4] * q[4]) - 1.5 / q[4]);
+            for (int row = 0; row < 5; ++row)
+                for (int col = 0; col < 5; ++col) J[row][col] += dM[row] * dP[col];
+        }
+        if (solve5(J, r) != 0) break;
+        for (int k = 0; k < 5; ++k) q[k] -= r[k];
+        ++it;
+        const double vs = sqrt(q[4]);
+        int small = fabs(r[0]) <= 1e-14 * q[0] && fabs(r[4]) <= 1e-14 * q[4];
+        for (int a = 0; a < 3; ++a) small = small && fabs(r[1 + a]) <= 1e-14 * vs;
+        if (polish) break;
+        if (small) polish = 1;
+    }
+    return it;
+}
+
+/* Effective parameters of the cell moments (n, V, T); q = (n~, V~, T~).
+ * Returns the number of Newton steps. */
+int orc_effective_parameters(const orc_problem *p, double n, const double V[3], double T, double *q)
+{
+    velgrid g = make_velgrid(p);
+    double *phi = malloc(sizeof(double) * g.nv);
+    int it = effective_parameters(&g, dvol(p), n, V, T, q, phi);
+    free(phi);
+    free_velgrid(&g);
+    return it;
+}
+
 /* Homogeneous relaxation over a time tau, solved exactly (Eq. relaxation):
- * out = Phi + (f - Phi) exp(-nu tau), Phi and nu from the moments of f. */
+ * out = Phi + (f - Phi) exp(-nu tau), Phi and nu from the moments of f.  With
+ * p->conservative, Phi is the Maxwellian of the effective parameters (the
+ * collision frequency keeps the cell's own n and T), so that Phi, and with it
+ * out, has exactly the grid moments of f. */
 void orc_relax(const orc_problem *p, const double *f, double *out, double tau)
 {
     velgrid g = make_velgrid(p);
@@ -207,7 +323,13 @@ void orc_relax(const orc_problem *p, const double *f, double *out, double tau)
             const double *fc = f + c * nv;
             double n, V[3], T;
             cell_moments(&g, dV, fc, &n, V, &T);
-            maxwellian_on(&g, n, V, T, phi);
+            if (p->conservative) {
+                double q[5];
+                effective_parameters(&g, dV, n, V, T, q, phi);
+                maxwellian_on(&g, q[0], q + 1, q[4], phi);
+            } else {
+                maxwellian_on(&g, n, V, T, phi);
+            }
             double decay = exp(-orc_collision_frequency(p, n, T) * tau);
             for (long j = 0; j < nv; ++j)
                 out[c * nv + j] = phi[j] + (fc[j] - phi[j]) * decay;

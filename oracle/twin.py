@@ -79,9 +79,32 @@ class Twin:
         T = (c2 * f5).sum(axis=ax) * self.dV / n * (2.0 / 3.0)
         return n, u, T
 
+    def effective(self, n, u, T):
+        """Effective parameters of one cell (Sec. 2.1, the remark on
+        conservation after Eq. (exact)): the (n~, u~, T~) whose Maxwellian on
+        the grid has the grid moments (n, u, T).  Found with SciPy's hybrid
+        Powell root finder on those five equations (residuals scaled by n,
+        sqrt(T), T), started at (n, u, T)."""
+        from scipy.optimize import root
+
+        target = np.array([n, u[0], u[1], u[2], T], dtype=float)
+        scale = np.array([n, math.sqrt(T), math.sqrt(T), math.sqrt(T), T])
+
+        def resid(q):
+            m = self.macro(self.maxwell(q[0], q[1:4], q[4]))
+            return (np.array([m[0], *m[1], m[2]]) - target) / scale
+
+        sol = root(resid, target.copy(), method="hybr", options={"xtol": 1e-15})
+        return sol.x
+
     def relax(self, f5, tau):
         n, u, T = self.macro(f5)
-        M = self.maxwell(n, u, T)
+        if self.cfg.get("maxwellian", "point") == "conservative":
+            q = np.array([self.effective(float(a), b, float(c)) for a, b, c in
+                          zip(n.ravel(), u.reshape(-1, 3), T.ravel())]).reshape(n.shape + (5,))
+            M = self.maxwell(q[..., 0], q[..., 1:4], q[..., 4])
+        else:
+            M = self.maxwell(n, u, T)
         nu = n * T ** (1.0 - self.omega) / self.kn
         k = np.exp(-nu * tau)[..., None, None, None]
         return M + (f5 - M) * k

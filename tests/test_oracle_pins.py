@@ -141,6 +141,107 @@ def test_entropy_decreases_under_relaxation(oracle_mod):
     assert h1 < h0 and h2 < h1
 
 
+# ------------------------------------------------- conservative Maxwellian
+# Sec. 2.1, the remark after Eq. (exact): the relaxation may use effective
+# (n~, V~, T~) chosen so that the discretized Maxwellian has exactly the grid
+# moments of the cell.
+
+
+def coarse(**kw):
+    return prob(nx=3, nv=(8, 8, 8), vlo=(-3,) * 3, vhi=(3,) * 3, maxwellian="conservative", **kw)
+
+
+def test_effective_parameters_invert_the_discretization(oracle_mod):
+    """A Maxwellian sampled with known (n0, V0, T0) on a coarse grid has grid
+    moments off by ~1e-4; the effective parameters of those moments are
+    (n0, V0, T0) again, and that Maxwellian is a fixed point of the
+    conservative relaxation (but not of the point-value one)."""
+    O = oracle_mod.Oracle(coarse())
+    P = oracle_mod.Oracle(dict(coarse(), maxwellian="point"))
+    for n0, V0, T0 in [(1.3, (0.3, -0.2, 0.1), 0.8), (0.6, (-0.5, 0.0, 0.4), 1.1)]:
+        phi = gauss(O, n0, V0, T0)
+        m = O.moments(np.tile(phi, (O.ncell, 1)))[0]
+        assert np.max(np.abs(m - [n0, *V0, T0])) > 1e-5
+        q, it = O.effective_parameters(m[0], m[1:4], m[4])
+        assert it <= 8
+        np.testing.assert_allclose(q, [n0, *V0, T0], rtol=0, atol=2e-14)
+        f = np.tile(phi, (O.ncell, 1))
+        assert np.max(np.abs(O.relax(f, 0.6) - f)) <= 1e-13 * phi.max()
+        assert np.max(np.abs(P.relax(f, 0.6) - f)) > 1e-6 * phi.max()
+
+
+def test_effective_parameters_newton_is_quadratic(oracle_mod):
+    """On a very coarse grid (6^3 nodes on [-2.5, 2.5]^3, moment defects near
+    1e-2) Newton's method with the exact Jacobian reaches the 1e-14 stop in at
+    most 4 steps plus the closing one; a Jacobian with a slipped term
+    converges only linearly and needs 6 or more."""
+    O = oracle_mod.Oracle(prob(nx=3, nv=(6, 6, 6), vlo=(-2.5,) * 3, vhi=(2.5,) * 3, maxwellian="conservative"))
+    for V, T in [((0.5, 0.1, 0.0), 1.0), ((-0.7, 0.3, 0.2), 0.6), ((0.0, 0.0, 0.0), 1.5)]:
+        q, it = O.effective_parameters(1.0, np.array(V, float), T)
+        assert abs(q[4] - T) > 5e-4 and it <= 5
+
+
+def test_effective_parameters_resolved_grid_limit(oracle_mod):
+    """On a grid that resolves the Maxwellian the moment defect vanishes, so
+    the effective parameters are the moments themselves."""
+    O = oracle_mod.Oracle(prob(nv=(40, 40, 40), vlo=(-9,) * 3, vhi=(9,) * 3, maxwellian="conservative"))
+    for n, V, T in [(1.0, (0.0, 0.0, 0.0), 1.0), (2.5, (0.7, -0.3, 0.2), 1.7)]:
+        q, _ = O.effective_parameters(n, np.array(V, float), T)
+        np.testing.assert_allclose(q, [n, *V, T], rtol=0, atol=1e-12)
+
+
+def test_effective_parameters_mirror_symmetry(oracle_mod):
+    """On a grid symmetric about 0 the map (n, V, T) -> (n~, V~, T~) commutes
+    with reflecting a velocity component, and V = 0 gives V~ = 0."""
+    O = oracle_mod.Oracle(coarse())
+    q, _ = O.effective_parameters(1.0, np.array([0.4, -0.25, 0.1]), 0.9)
+    r, _ = O.effective_parameters(1.0, np.array([-0.4, -0.25, -0.1]), 0.9)
+    np.testing.assert_allclose(r, q * [1, -1, 1, -1, 1], rtol=1e-14, atol=1e-15)
+    z, _ = O.effective_parameters(1.0, np.zeros(3), 0.9)
+    assert np.max(np.abs(z[1:4])) < 1e-15 and abs(z[4] - 0.9) > 1e-5
+
+
+def test_conservative_relaxation_conserves_exactly(oracle_mod):
+    """With the effective parameters the relaxation conserves mass, momentum
+    and energy to rounding on a coarse grid, where the point-value
+    Maxwellian's defect is above 1e-7."""
+    O = oracle_mod.Oracle(coarse())
+    P = oracle_mod.Oracle(dict(coarse(), maxwellian="point"))
+    base = gauss(O, 1.0, (0.3, -0.1, 0.2), 1.2)
+    f = base[None, :] * inputs.uniform((O.ncell, O.nvel), seed=11, lo=0.5, hi=1.5)
+    before = O.totals(f)[:5]
+    np.testing.assert_allclose(O.totals(O.relax(f, 0.9))[:5], before, rtol=1e-14, atol=1e-15)
+    assert np.max(np.abs(P.totals(P.relax(f, 0.9))[:5] - before)) > 1e-7
+
+
+@pytest.mark.parametrize("splitting", ["strang", "lie"])
+def test_conservative_periodic_run_conserves(oracle_mod, splitting):
+    """On a periodic box streaming in flux form conserves every velocity sum,
+    so with the conservative relaxation whole steps conserve mass, momentum
+    and energy to rounding; with the point-value Maxwellian energy drifts."""
+    cfg = prob(kind="periodic2d", nx=4, ny=3, nv=(8, 8, 6), vlo=(-3, -3, -3), vhi=(3, 3, 3), kn=0.3,
+               splitting=splitting, maxwellian="conservative")
+    O, P = oracle_mod.Oracle(cfg), oracle_mod.Oracle(dict(cfg, maxwellian="point"))
+    f = np.tile(gauss(O, 1.0, (0.2, 0.0, 0.0), 1.0), (O.ncell, 1))
+    f *= 1 + 0.4 * inputs.uniform(O.shape, seed=41, lo=-1, hi=1)
+    t0 = O.totals(f)[:5]
+    np.testing.assert_allclose(O.totals(O.step(f, 6))[:5], t0, rtol=1e-13, atol=1e-14)
+    assert abs(P.totals(P.step(f, 6))[4] - t0[4]) > 1e-7 * abs(t0[4])
+
+
+@pytest.mark.parametrize("kind", ["shock", "periodic2d", "cavity"])
+def test_twin_agrees_conservative(oracle_mod, kind):
+    """The C oracle's Newton solve and the twin's SciPy root finder on the
+    same defining equations give the same three steps to rounding."""
+    from oracle.twin import Twin
+    cfg = prob(kind=kind, nx=4, ny=3, nv=(6, 4, 4), vlo=(-3, -3, -3), vhi=(3, 3, 3), kn=0.4,
+               mach=1.5, x0=-1.0 if kind == "shock" else 0.0, lid_mach=0.25, t_wall=1.2,
+               maxwellian="conservative")
+    O, W = oracle_mod.Oracle(cfg), Twin(cfg)
+    f = O.initial_state() * (1 + 0.3 * inputs.uniform(O.shape, seed=53, lo=-1, hi=1))
+    np.testing.assert_allclose(O.step(f, 3), W.step(f, 3), rtol=1e-12, atol=1e-15)
+
+
 # --------------------------------------------------------------- streaming
 
 
