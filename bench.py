@@ -35,6 +35,10 @@ DESCRIPTIONS = {
                        "FP64 throughout, Strang + minmod upwind, CFL 0.5",
     "cavity_128_fp32": "2D lid-driven cavity 128x128, lid Mach 0.1, Kn 0.1, T_w 1, 24^3 velocities on [-5,5]^3, "
                        "diffuse walls; f FP32, moments FP64",
+    "shock_m3_fp32_conservative": "the Mach-3 shock above with every relaxation towards the effective "
+                                  "Maxwellian (per-cell Newton solve, exact conservation on the grid)",
+    "cavity_128_fp32_conservative": "the 128^2 cavity above with every relaxation towards the effective "
+                                    "Maxwellian (per-cell Newton solve, exact conservation on the grid)",
 }
 
 
@@ -263,7 +267,12 @@ def main():
                 ("batch_64_cavities_fp32_graph", inputs.batch_cavities(), "fp32", 20, 2, True),
                 # the paper's own shock runs: translation streaming, Courant numbers up to ~150
                 ("shock_m1.5_paper_fp32", [inputs.config("shock_m1.5_paper")], "fp32", 100, 10, False),
-                ("shock_m3_paper_fp32", [inputs.config("shock_m3_paper")], "fp32", 50, 5, False)]
+                ("shock_m3_paper_fp32", [inputs.config("shock_m3_paper")], "fp32", 50, 5, False),
+                # relaxation towards the effective Maxwellian (exact conservation on the grid)
+                ("shock_m3_fp32_conservative", [inputs.config("shock_m3_fp32_conservative")], "fp32", 500, 20,
+                 False),
+                ("cavity_128_fp32_conservative", [inputs.config("cavity_128_fp32_conservative")], "fp32", 200, 10,
+                 False)]
         wanted = set(x for x in args.extras.split(",") if x)
         for name, probs, p, steps, warm, graph in runs:
             if wanted and name not in wanted:

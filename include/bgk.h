@@ -69,6 +69,15 @@ extern "C" {
                                Courant number, Eq. (upwind) over the fraction; one-dimensional
                                kinds, any Courant number (no Courant limit) */
 
+#define BGK_POINT 0         /* relaxation towards the point values of Eq. (Maxw) at the cell's
+                               moments (n, V, T) */
+#define BGK_CONSERVATIVE 1  /* relaxation towards Eq. (Maxw) at the effective (n~, V~, T~) whose
+                               grid moments are exactly the cell's (n, V, T) (Sec. 2.1, the
+                               remark on conservation after Eq. (exact)): mass, momentum and
+                               energy are conserved by every relaxation on the velocity grid;
+                               the collision frequency keeps the cell's own n and T; far-field
+                               and wall Maxwellians stay point values */
+
 #define BGK_FP64 0          /* f stored and streamed in double */
 #define BGK_FP32 1          /* f stored and streamed in float; moments, Maxwellian
                                parameters and all reductions in double; each stored
@@ -92,6 +101,7 @@ typedef struct bgk_problem {
     int splitting;          /* BGK_STRANG or BGK_LIE */
     int limiter;            /* BGK_MINMOD, BGK_NOLIMIT or BGK_SHIFT (all instances of a context
                                use BGK_SHIFT or none does) */
+    int maxwellian;         /* BGK_POINT or BGK_CONSERVATIVE (per instance) */
 } bgk_problem;
 
 typedef struct bgk_ctx bgk_ctx;
@@ -101,7 +111,8 @@ typedef struct bgk_ctx bgk_ctx;
  * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
  * instance's dt, and allocates the context's device work space on the current
  * device.  precision: BGK_FP64 or BGK_FP32.
- * Errors: BGK_E_INVALID, BGK_E_CFL (Courant sum > 2/3; not checked for
+ * Errors: BGK_E_INVALID (also for a maxwellian field other than BGK_POINT and
+ * BGK_CONSERVATIVE), BGK_E_CFL (Courant sum > 2/3; not checked for
  * BGK_SHIFT), BGK_E_UNSUPPORTED (also for BGK_SHIFT on a two-dimensional
  * kind or mixed with other limiters in one context, and when one workgroup's
  * table entries, 2 (Nvx + Nvy + Nvz) values per
@@ -225,8 +236,10 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * of magnitudes).  The first call allocates the context's reverse-sweep work
  * space (two extra f buffers and per-cell coefficients); BGK_E_HIP if that
  * fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9 (1D) table entries per
- * workgroup exceed the device's LDS, or for BGK_SHIFT contexts (no reverse
- * sweep of the translation form).  Asynchronous on `stream`. */
+ * workgroup exceed the device's LDS, for BGK_SHIFT contexts (no reverse
+ * sweep of the translation form) and for contexts with a BGK_CONSERVATIVE
+ * instance (no reverse sweep of the effective parameters' solve).
+ * Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *stream);
 

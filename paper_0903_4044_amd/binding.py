@@ -41,6 +41,7 @@ class Problem(ctypes.Structure):
         ("mach", ctypes.c_double), ("lid_mach", ctypes.c_double),
         ("t_wall", ctypes.c_double),
         ("splitting", ctypes.c_int), ("limiter", ctypes.c_int),
+        ("maxwellian", ctypes.c_int),
     ]
 
 
@@ -111,6 +112,7 @@ def to_struct(cfg: dict) -> Problem:
     p.t_wall = float(cfg.get("t_wall", 1.0))
     p.splitting = 0 if cfg.get("splitting", "strang") == "strang" else 1
     p.limiter = {"minmod": 0, "none": 1, "shift": 2}[cfg.get("limiter", "minmod")]
+    p.maxwellian = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
     return p
 
 

@@ -44,6 +44,7 @@ struct bgk_ctx {
     int unroll = 1;            // streaming kernel: jz values whose loads are issued together
     int persist = 0;           // streaming kernel: 0 one workgroup per item, else resident workgroups per CU
     bool shift = false;        // every instance streams in the translation form (k_shift)
+    bool conservative = false; // some instance relaxes with the effective Maxwellian parameters
     // hipGraph replay of two-step chunks (stream, prep, stream, prep); key:
     // (f_out, which buffer the chunk starts from, table parity)
     bool use_graph = false;
@@ -183,6 +184,7 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (!std::isfinite(p.omega)) return bad("omega must be finite");
     if (p.splitting != BGK_STRANG && p.splitting != BGK_LIE) return bad("unknown splitting");
     if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT && p.limiter != BGK_SHIFT) return bad("unknown limiter");
+    if (p.maxwellian != BGK_POINT && p.maxwellian != BGK_CONSERVATIVE) return bad("unknown Maxwellian form");
     if (p.limiter == BGK_SHIFT && two) {
         snprintf(b, sizeof b, "problem %d: shift streaming is one-dimensional", idx);
         msg = b;
@@ -365,6 +367,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
         I.strang = p.splitting == BGK_STRANG;
         I.minmod = p.limiter == BGK_MINMOD;
         I.shift = p.limiter == BGK_SHIFT;
+        I.conservative = p.maxwellian == BGK_CONSERVATIVE;
+        if (I.conservative) c->conservative = true;
         I.f0 = f_off;
         const double dx = (p.x1 - p.x0) / p.nx, dy = two ? (p.y1 - p.y0) / p.ny : 1.0;
         I.dt = p.dt > 0.0 ? p.dt : p.cfl / courant_rate(p, two);
@@ -861,6 +865,8 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (!ctx->adjoint_fits)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
+    if (ctx->conservative)
+        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of the effective Maxwellian parameters");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
                                       : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);

@@ -44,6 +44,7 @@ struct Inst {
     int pseudo0;    // first global params entry of its ghost sources
     int strang, minmod;
     int shift;      // translation form of the streaming step (k_shift)
+    int conservative;  // relaxations use the effective Maxwellian parameters
     long long f0;   // element offset of the instance in f
     double cx, cy;  // dt / dx, dt / dy
     double dt, kn, omega;
@@ -353,8 +354,9 @@ __device__ __forceinline__ int relax_times(const Inst &I, int mode, double *ta, 
     return mode == MODE_FIRST ? 0 : 1;
 }
 
-struct Relax {          // Maxwellian parameters of one relaxation
-    double n, V[3], T, a, P;
+struct Relax {          // one relaxation: moments (n, V, T) of its input, a, and
+    double n, V[3], T, a;  // the Maxwellian P e_x e_y e_z, e_c = exp(-(v_c - Vm_c)^2 / Tm)
+    double P, Vm[3], Tm;   // (Vm, Tm = V, T unless the effective parameters are used)
 };
 
 __device__ __forceinline__ void moments_from_raw(const double *raw, Relax *r)
@@ -364,6 +366,8 @@ __device__ __forceinline__ void moments_from_raw(const double *raw, Relax *r)
     r->V[1] = raw[2] / raw[0];
     r->V[2] = raw[3] / raw[0];
     r->T = 2.0 / 3.0 * (raw[4] / raw[0] - (r->V[0] * r->V[0] + r->V[1] * r->V[1] + r->V[2] * r->V[2]));
+    for (int c = 0; c < 3; ++c) r->Vm[c] = r->V[c];
+    r->Tm = r->T;
 }
 
 // (pi T)^(-3/2) as a square root and a division (no pow).
@@ -458,6 +462,94 @@ __device__ __forceinline__ void maxwell_raw(double P, double dV, const double (*
     m[4] = w * (s[0][2] * s[1][0] * s[2][0] + s[0][0] * s[1][2] * s[2][0] + s[0][0] * s[1][0] * s[2][2]);
 }
 
+// Effective Maxwellian parameters (Sec. 2.1, the remark on conservation after
+// Eq. (exact)): the (n~, V~, T~) whose discretized Maxwellian has exactly the
+// grid moments (n, V, T) of the cell, so that the relaxation conserves mass,
+// momentum and energy on the velocity grid.  The Maxwellian factorises, so
+// with u = v_c - V~_c and e_c(u) = exp(-u^2 / T~) per component c and the
+// normalised power sums  m_k = sum u^k e_c / sum e_c  (k = 1..4), the grid
+// mean of v_c is V~_c + m_1 and its grid variance c2 = m_2 - m_1^2; the
+// temperature condition couples the components: (2/3) sum_c c2_c = T.
+// Newton's method on (V~, T~), started at (V, T), with the exact Jacobian
+// (derivatives of weighted means by the score 2u/T~ resp. u^2/T~^2):
+//   d mean_c / d V~_c = 2 c2_c / T~,     d mean_c / d T~ = (m_3 - m_1 m_2)_c / T~^2,
+//   d c2_c / d V~_c   = 2 c3_c / T~,     d c2_c / d T~   = (c4 - c2^2 + 2 m_1 c3)_c / T~^2,
+// c3, c4 being the central moments.  The 4x4 system has arrowhead form and is
+// solved in closed form.  It stops after the first step that changes no
+// parameter by more than 1e-14 of its scale (sqrt(T~), T~), or after 30.
+// Then n~ needs no iteration: the grid density is linear in it, and the
+// prefactor  P = n~ (pi T~)^(-3/2) = n / (dV prod_c sum e_c).  The final
+// pass fills this lane's table slots with the e_c of the result.  All sums
+// are butterflies inside the W-lane segment, so every lane holds the same
+// values and the loop is uniform over the segment.
+template <int W = 64>
+__device__ __forceinline__ void effective_tables(const Geo &g, Relax *r, Tables &t)
+{
+    const int lane = threadIdx.x & (W - 1);
+    double Vt[3] = {r->V[0], r->V[1], r->V[2]}, Tt = r->T;
+    bool done = false;
+    for (int it = 0;; ++it) {
+        double res[3], jvv[3], jvt[3], jtv[3], jtt = 0.0, rt = -r->T, s0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int k = lane + W * q;
+                t.e[c][q] = 0.0;
+                if (W * q >= nv_of(g, c)) continue;  // uniform: no second slot up to W points
+                if (k < nv_of(g, c)) {
+                    const double u = vnode(g, c, k) - Vt[c], u2 = u * u;
+                    const double e = exp(-u2 / Tt);
+                    t.e[c][q] = e;
+                    p0 += e;
+                    p1 += u * e;
+                    p2 += u2 * e;
+                    p3 += u2 * u * e;
+                    p4 += u2 * u2 * e;
+                }
+            }
+            s0[c] = wave_sum<W>(p0);
+            if (done) continue;
+            const double i0 = 1.0 / s0[c];
+            const double a1 = wave_sum<W>(p1) * i0, a2 = wave_sum<W>(p2) * i0;
+            const double a3 = wave_sum<W>(p3) * i0, a4 = wave_sum<W>(p4) * i0;
+            const double c2 = a2 - a1 * a1;
+            const double c3 = a3 - 3.0 * a1 * a2 + 2.0 * a1 * a1 * a1;
+            const double c4 = a4 - 4.0 * a1 * a3 + 6.0 * a1 * a1 * a2 - 3.0 * a1 * a1 * a1 * a1;
+            res[c] = Vt[c] + a1 - r->V[c];
+            jvv[c] = 2.0 * c2 / Tt;
+            jvt[c] = (a3 - a1 * a2) / (Tt * Tt);
+            jtv[c] = 4.0 / 3.0 * c3 / Tt;
+            jtt += 2.0 / 3.0 * (c4 - c2 * c2 + 2.0 * a1 * c3) / (Tt * Tt);
+            rt += 2.0 / 3.0 * c2;
+        }
+        if (done) {
+            r->P = r->n / (g.dV * s0[0] * s0[1] * s0[2]);
+            break;
+        }
+        double num = rt, den = jtt;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            num -= jtv[c] * res[c] / jvv[c];
+            den -= jtv[c] * jvt[c] / jvv[c];
+        }
+        const double dT = num / den;
+        bool small = fabs(dT) <= 1e-14 * Tt;
+        const double vs = sqrt(Tt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double dV = (res[c] - jvt[c] * dT) / jvv[c];
+            Vt[c] -= dV;
+            small = small && fabs(dV) <= 1e-14 * vs;
+        }
+        Tt = fmax(Tt - dT, 0.5 * Tt);  // a step may not more than halve T~
+        done = small || it == 29;
+    }
+    for (int c = 0; c < 3; ++c) r->Vm[c] = Vt[c];
+    r->Tm = Tt;
+}
+
 // Everything one wave knows about the relaxations of one cell.
 struct Coef {
     double raw[NQ];     // moment sums (with dV) of the cell's input
@@ -490,9 +582,19 @@ __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, 
     if (C.nr == 0) return;
     moments_from_raw(C.raw, &C.r1);
     finish_relax(I, ta, &C.r1);
-    lane_tables<W>(g, C.r1.V, C.r1.T, C.t1);
-    if (C.nr == 2 || want_sums) wave_table_sums<W>(g, C.t1, C.s1, want_sums);
-    if (C.nr == 2) {
+    if (I.conservative) effective_tables<W>(g, &C.r1, C.t1);
+    else lane_tables<W>(g, C.r1.V, C.r1.T, C.t1);
+    if ((C.nr == 2 && !I.conservative) || want_sums) wave_table_sums<W>(g, C.t1, C.s1, want_sums);
+    if (C.nr == 2 && I.conservative) {
+        // R1 keeps the grid moments, so R2 relaxes towards the same Maxwellian
+        C.r2 = C.r1;
+        finish_relax(I, tb, &C.r2);
+        C.r2.P = C.r1.P;
+        C.t2 = C.t1;
+        if (want_sums)
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 5; ++q) C.s2[c][q] = C.s1[c][q];
+    } else if (C.nr == 2) {
         double mp[5], m2[5];
         maxwell_raw(C.r1.P, g.dV, C.s1, mp);
         for (int q = 0; q < 5; ++q) m2[q] = C.r1.a * mp[q] + (1.0 - C.r1.a) * C.raw[q];
@@ -500,6 +602,8 @@ __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, 
         finish_relax(I, tb, &C.r2);
         lane_tables<W>(g, C.r2.V, C.r2.T, C.t2);
         if (want_sums) wave_table_sums<W>(g, C.t2, C.s2, true);
+    }
+    if (C.nr == 2) {
         C.c0 = (1.0 - C.r1.a) * (1.0 - C.r2.a);
         C.cA = C.r1.a * (1.0 - C.r2.a) * C.r1.P;
         C.cB = C.r2.a * C.r2.P;

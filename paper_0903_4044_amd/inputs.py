@@ -25,6 +25,9 @@ density in n_r, length in the domain unit, time in length / sqrt(2 R T_r)):
     limiter    'minmod' (second order), 'none' (first-order upwind, Eq. upwind) or
                'shift' (Sec. 2.1 translation form: integer part of the Courant
                number as a shift, Eq. upwind over the fraction; 1D kinds)
+    maxwellian 'point' (Eq. Maxw at the cell's moments) or 'conservative'
+               (Eq. Maxw at the effective parameters whose grid moments are the
+               cell's, Sec. 2.1, the remark after Eq. exact)
     steps      number of time steps of the workload
     precision  'fp64' or 'fp32' (storage/streaming precision of f)
 """
@@ -42,8 +45,8 @@ def _base(**kw):
     d = dict(kind="shock", nx=1, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
              nv=(8, 8, 8), vlo=(-4.0, -4.0, -4.0), vhi=(4.0, 4.0, 4.0),
              kn=1.0, omega=0.5, cfl=0.5, dt=0.0, mach=0.0, lid_mach=0.0,
-             t_wall=1.0, splitting="strang", limiter="minmod", steps=1,
-             precision="fp64")
+             t_wall=1.0, splitting="strang", limiter="minmod", maxwellian="point",
+             steps=1, precision="fp64")
     d.update(kw)
     return d
 
@@ -76,6 +79,16 @@ CONFIGS = {
                             nv=(30, 30, 30), vlo=(-10.0, -11.0, -11.0), vhi=(12.0, 11.0, 11.0),
                             kn=1.0, omega=0.74, dt=0.05, mach=3.0, splitting="lie",
                             limiter="shift", steps=200, precision="fp32"),
+    # The Mach-3 shock and the 128^2 cavity relaxing towards the effective
+    # Maxwellian (Sec. 2.1, the remark after Eq. exact).
+    "shock_m3_fp32_conservative": _base(kind="shock", nx=1024, x0=-20.0, x1=20.0,
+                                        nv=(48, 48, 48), vlo=(-8.0,) * 3, vhi=(8.0,) * 3,
+                                        kn=1.0, mach=3.0, steps=2000, precision="fp32",
+                                        maxwellian="conservative"),
+    "cavity_128_fp32_conservative": _base(kind="cavity", nx=128, ny=128, nv=(24, 24, 24),
+                                          vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
+                                          lid_mach=0.1, t_wall=1.0, steps=5000,
+                                          precision="fp32", maxwellian="conservative"),
     # Adjoint workload: 64^2 cavity, 200 steps.
     "cavity_64_adjoint": _base(kind="cavity", nx=64, ny=64, nv=(24, 24, 24),
                                vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,

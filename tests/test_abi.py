@@ -93,3 +93,16 @@ def test_shift_streaming_rules(B):
     mixed = (B.Problem * 2)(B.to_struct(big), B.to_struct(inputs.config("shock_m1.5_fp64")))
     assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED
     assert not h.value
+
+
+def test_maxwellian_form_rules(B):
+    """The Maxwellian form must be BGK_POINT or BGK_CONSERVATIVE."""
+    cfg = inputs.config("shock_m1.5_fp64", maxwellian="conservative")
+    st = B.to_struct(cfg)
+    assert st.maxwellian == 1
+    st.maxwellian = 7
+    arr = (B.Problem * 1)(st)
+    h = ctypes.c_void_p()
+    assert B.load().bgk_init(arr, 1, 0, ctypes.byref(h)) == B.E_INVALID
+    assert not h.value
+    assert "Maxwellian" in B.load().bgk_last_error(None).decode()
