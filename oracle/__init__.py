@@ -83,6 +83,7 @@ def lib():
         L.orc_totals.argtypes = [P, dp, dp]
         L.orc_lid_shear.argtypes = [P, dp]
         L.orc_lid_shear.restype = ctypes.c_double
+        L.orc_cavity_metrics.argtypes = [P, dp, dp]
         L.orc_relax_adjoint.argtypes = [P, dp, dp, dp, ctypes.c_double, dp]
         L.orc_stream_adjoint.argtypes = [P, dp, dp, dp, ctypes.c_double, dp]
         L.orc_step_adjoint.argtypes = [P, dp, dp, dp, dp]
@@ -211,6 +212,14 @@ class Oracle:
     def lid_shear(self, f) -> float:
         f = self._f(f)
         return self.L.orc_lid_shear(ctypes.byref(self.p), _ptr(f))
+
+    def cavity_metrics(self, f) -> np.ndarray:
+        """(D, G) of the Table of Sec. 5.2: mean lid shear stress over
+        p0 U_W and twice the main vortex's centre-line flow rate."""
+        f = self._f(f)
+        out = np.empty(2)
+        self.L.orc_cavity_metrics(ctypes.byref(self.p), _ptr(f), _ptr(out))
+        return out
 
     # -- reverse sweep (hand-derived adjoint) -----------------------------
     def _no_conservative(self):

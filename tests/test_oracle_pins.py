@@ -485,6 +485,68 @@ def test_shift_streaming_far_field_inflow(oracle_mod):
             np.testing.assert_allclose(out[:, j], up[j], rtol=1e-14)
 
 
+# ------------------------------------------------------- cavity metrics
+# D and G of the Table of Sec. 5.2: mean lid shear stress over p0 U_W and
+# twice the main vortex's centre-line flow rate.
+
+
+def metric_cfg(nx, ny, nv=(24, 16, 16)):
+    return prob(kind="cavity", nx=nx, ny=ny, nv=nv, vlo=(-6,) * 3, vhi=(6,) * 3, lid_mach=0.05)
+
+
+def shear_state(O, cfg, u_of_xy):
+    """Cells hold Maxwellians n = T = 1 drifting with V_x = U_W u(x, y)."""
+    uw = cfg["lid_mach"] * math.sqrt(GAMMA / 2)
+    ny, nx = cfg["ny"], cfg["nx"]
+    return np.array([gauss(O, 1.0, (uw * u_of_xy((c % nx + 0.5) / nx, (c // nx + 0.5) / ny), 0.0, 0.0), 1.0)
+                     for c in range(nx * ny)])
+
+
+def test_lid_shear_metric_free_molecular_limit(oracle_mod):
+    """Gas at rest under the lid: the lid emits the incident mass flux
+    1/(2 sqrt(pi)) with mean x-velocity U_W, so D = 1/sqrt(pi).  The
+    half-range sums over v_y converge at second order in dv_y: the error
+    falls fourfold per halving and Richardson's extrapolation hits the
+    closed form."""
+    D = []
+    for nvy in (40, 80, 160):
+        O = oracle_mod.Oracle(metric_cfg(3, 2, nv=(24, nvy, 16)))
+        D.append(O.cavity_metrics(O.initial_state())[0])
+    e = np.array(D) - 1 / math.sqrt(math.pi)
+    assert 3.8 < e[0] / e[1] < 4.2 and 3.8 < e[1] / e[2] < 4.2
+    assert abs((4 * D[2] - D[1]) / 3 - 1 / math.sqrt(math.pi)) < 5e-6
+
+
+@pytest.mark.parametrize("nx", [6, 7])
+def test_vortex_flow_rate_linear_profile(oracle_mod, nx):
+    """u = s (y - a) + k (x - 1/2): on the centre line G = 2 int_a^1 u dy =
+    s (1 - a)^2, exact for the piecewise-linear rule; the x term vanishes
+    only at x = 1/2 (even nx: mean of the middle columns, odd nx: the middle
+    column), so a wrong column changes G."""
+    cfg = metric_cfg(nx, 10)
+    O = oracle_mod.Oracle(cfg)
+    for s, a in [(0.8, 0.37), (1.3, 0.61)]:
+        f = shear_state(O, cfg, lambda x, y: s * (y - a) + 0.4 * (x - 0.5))
+        assert O.cavity_metrics(f)[1] == pytest.approx(s * (1 - a) ** 2, rel=1e-10)
+
+
+def test_vortex_flow_rate_takes_the_top_vortex(oracle_mod):
+    """Two sign changes on the centre line: the integral starts at the upper
+    zero (the main vortex's centre) and converges at second order in dy."""
+    a, b = 0.3, 0.7
+
+    def u(y):
+        return (y - a) * (y - b)
+
+    exact = 2 * ((1 - b) ** 3 / 3 + (b - a) * (1 - b) ** 2 / 2)
+    err = []
+    for ny in (20, 40):
+        cfg = metric_cfg(4, ny)
+        O = oracle_mod.Oracle(cfg)
+        err.append(abs(O.cavity_metrics(shear_state(O, cfg, lambda x, y: u(y)))[1] - exact))
+    assert err[1] < 0.3 * err[0] and err[1] < 2e-4
+
+
 # ------------------------------------------------------------------ twin
 
 
