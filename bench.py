@@ -193,6 +193,55 @@ def cpu_baseline(cfg, budget_s: float):
     return out
 
 
+# The Table of Sec. 5.2: per rarefaction parameter delta, the paper's D and G
+# and the range of the reference values it quotes.
+TABLE1 = {0.1: (0.675, (0.676, 0.678), 0.0975, (0.0973, 0.0976)),
+          1.0: (0.624, (0.625, 0.631), 0.103, (0.104, 0.105)),
+          10.0: (0.393, (0.412, 0.415), 0.143, (0.145, 0.145))}
+
+
+def table1(binding, torch, inputs) -> dict:
+    """Steady driven-cavity runs at the paper's settings, from rest until D
+    and G change by less than 1e-5 over two time units, for this library's
+    scheme (Strang, minmod) and the paper's (Lie, first-order upwind), both
+    with the conservative Maxwellian; and the drift of D with the point-value
+    Maxwellian (whose mass defect on this grid slowly drains the cavity)."""
+    from paper_0903_4044_amd.steady import run_to_steady
+    rows = []
+    for scheme, spl, lim in (("strang-minmod", "strang", "minmod"), ("lie-upwind", "lie", "none")):
+        for delta in inputs.TABLE_DELTAS:
+            cfg = inputs.table_cavity(delta, splitting=spl, limiter=lim)
+            C = binding.Context(cfg, "fp32")
+            C.autotune(C.initial_state())
+            f = C.initial_state()
+            chunk = int(round(2.0 / C.dts[0]))
+            r = run_to_steady(C, f, chunk, rtol=1e-5, max_steps=40 * chunk)
+            D, G = (float(x) for x in r["metrics"][0])
+            Dp, Dr, Gp, Gr = TABLE1[delta]
+            pts = inputs.ncells(cfg) * inputs.nvel(cfg)
+            rows.append({"delta": delta, "scheme": scheme, "D": D, "G": G, "D_paper": Dp, "D_ref": Dr,
+                         "G_paper": Gp, "G_ref": Gr, "steps": r["steps"], "t": r["time"][0],
+                         "converged": r["converged"], "seconds": r["seconds"],
+                         "updates_per_s": pts * r["steps"] / r["seconds"]})
+            print(f"# delta {delta} {scheme}: D {D:.4f} (paper {Dp}, ref {Dr[0]}-{Dr[1]}), "
+                  f"G {G:.4f} (paper {Gp}, ref {Gr[0]}-{Gr[1]}), {r['steps']} steps, {r['seconds']:.1f} s",
+                  file=sys.stderr, flush=True)
+            C.close()
+    # point-value Maxwellian: D after 10 and 20 time units at delta = 10
+    cfg = inputs.table_cavity(10.0, maxwellian="point")
+    C = binding.Context(cfg, "fp32")
+    C.autotune(C.initial_state())
+    chunk = int(round(10.0 / C.dts[0]))
+    r = run_to_steady(C, C.initial_state(), chunk, rtol=0.0, max_steps=2 * chunk)
+    (s1, m1), (s2, m2) = r["history"]
+    drift = {"delta": 10.0, "D_t10": float(m1[0, 0]), "D_t20": float(m2[0, 0]), "G_t10": float(m1[0, 1]),
+             "G_t20": float(m2[0, 1])}
+    print(f"# point Maxwellian, delta 10: D {drift['D_t10']:.5f} at t = 10, {drift['D_t20']:.5f} at t = 20",
+          file=sys.stderr, flush=True)
+    return {"table": "Sec. 5.2 driven cavity, 160^2 cells, 20^3 velocities on [-3,3]^3, lid 0.01, FP32 f",
+            "rows": rows, "point_maxwellian_drift": drift}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +258,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this size 3 times (HBM counter calibration)")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the throughput line: the steady driven-cavity runs of the Sec. 5.2 Table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the stepper has no multi-GPU path.",
@@ -228,6 +279,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.table1:
+        print(json.dumps(table1(binding, torch, inputs)), flush=True)
+        return
     cfg = inputs.config(args.workload)
     prec = cfg["precision"]
     secs, kms, points, shape = run_workload(binding, torch, cfg, prec, args.steps, args.warmup,

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 from . import inputs
@@ -49,7 +50,7 @@ EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_
            "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
            "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph",
            "bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad", "bgk_set_rounding_seed",
-           "bgk_get_rounding_seed")
+           "bgk_get_rounding_seed", "bgk_cavity_metrics")
 
 TUNED_PATH = os.path.join(HERE, "tuned.json")
 
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.bgk_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bgk_lid_shear.argtypes = [vp, vp, vp, vp]
     L.bgk_lid_shear_grad.argtypes = [vp, vp, vp, vp, vp]
+    L.bgk_cavity_metrics.argtypes = [vp, vp, dp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -254,6 +256,14 @@ class Context:
         grad = self.grad_buffer(f.device) if grad is None else grad
         self._check(self.L.bgk_lid_shear_grad(self.h, _ptr(f), _ptr(lam), _ptr(grad), _stream_handle(stream)))
         return lam, grad
+
+    def cavity_metrics(self, f: torch.Tensor, stream=None) -> np.ndarray:
+        """(D, G) of every instance (NaN for non-cavities), shape [ninst, 2];
+        synchronises the stream."""
+        out = np.empty((len(self.problems), 2))
+        self._check(self.L.bgk_cavity_metrics(self.h, _ptr(f), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              _stream_handle(stream)))
+        return out
 
     def check(self, f: torch.Tensor, stream=None) -> int:
         return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))

@@ -74,6 +74,7 @@ struct bgk_ctx {
     int *wall_cells = nullptr;                                    // perimeter cells of the cavities
     int n_wall_cells = 0;
     double *gk = nullptr, *gt = nullptr, *lid = nullptr;          // ncells, ncells, 2 * ncells
+    double *lid_L = nullptr;                                      // ninst (bgk_cavity_metrics)
     int *flags = nullptr;
     // stochastic rounding of FP32 stores: device pass counter and the value
     // the next bgk_step starts it from
@@ -136,6 +137,7 @@ static void release(bgk_ctx *c)
     for (void *q : {c->adj_h, c->adj_hb}) (void)hipFree(q);
     for (double *q : {c->info_f, c->info_h, c->adj_sums, c->adj_wsum, c->adj_coef, c->adj_dw, c->gk, c->gt, c->lid})
         (void)hipFree(q);
+    (void)hipFree(c->lid_L);
     (void)hipFree(c->wall_cells);
     (void)hipFree(c->flags);
     (void)hipFree(c->pass);
@@ -718,6 +720,13 @@ static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t
 
 // ------------------------------------------------------------- reverse sweep
 
+// Per-cell lid sums of bgk_lid_shear (allocated at its first call).
+static int ensure_lid(bgk_ctx *c)
+{
+    if (!c->lid) HIP_TRY(c, hipMalloc((void **)&c->lid, sizeof(double) * 2 * (size_t)c->ncells));
+    return BGK_OK;
+}
+
 static int ensure_adjoint(bgk_ctx *c)
 {
     if (c->adj_ready) return BGK_OK;
@@ -732,7 +741,7 @@ static int ensure_adjoint(bgk_ctx *c)
     HIP_TRY(c, hipMalloc((void **)&c->adj_dw, sizeof(double) * c->ninst * 8));
     HIP_TRY(c, hipMalloc((void **)&c->gk, sizeof(double) * nc));
     HIP_TRY(c, hipMalloc((void **)&c->gt, sizeof(double) * nc));
-    HIP_TRY(c, hipMalloc((void **)&c->lid, sizeof(double) * 2 * nc));
+    TRY(ensure_lid(c));
     std::vector<int> wc;
     for (const Inst &I : c->h_inst) {
         if (I.kind != KIND_CAVITY) continue;
@@ -875,7 +884,7 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
 template <typename real>
 static int lid(bgk_ctx *c, const void *f, double *L, void *lam, double *grad, hipStream_t s)
 {
-    TRY(ensure_adjoint(c));
+    TRY(ensure_lid(c));
     hipLaunchKernelGGL(k_lid_sums<real>, dim3(c->ncells), dim3(256), 0, s, make_args(c), (const real *)f, c->lid);
     HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(k_lid_finish, dim3(c->ninst), dim3(64), 0, s, make_args(c), c->lid, L, grad);
@@ -904,6 +913,66 @@ extern "C" int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, nullptr, lam, grad_params, s)
                                       : lid<float>(ctx, f, nullptr, lam, grad_params, s);
+}
+
+// Steady-cavity metrics (Table of Sec. 5.2), computed on the host from the
+// lid shear and the moments of the centre line.
+//   D = -L / (p0 U_W W): mean lid shear stress in units of p0 U_W, with
+//       p0 = 1/2 (n = T = 1) and W the lid width;
+//   G = 2 / H * int u dy, u = V_x / U_W on the line x = (x0 + x1) / 2 (the
+//       middle column, or the mean of the two middle columns), from the
+//       first zero of u below the lid (the main vortex's centre; linear
+//       between cell centres) to the lid (u extrapolated linearly over the
+//       top half cell); from the bottom wall when u has no zero.
+static void centre_line_metrics(const Inst &I, const bgk_problem &p, const double *mom, double L, double *out)
+{
+    const int nx = I.nx, ny = I.ny;
+    const double uw = I.uw, W = p.x1 - p.x0, H = p.y1 - p.y0, h = H / ny;
+    out[0] = -L / (0.5 * uw * W);
+    std::vector<double> u(ny);
+    for (int iy = 0; iy < ny; ++iy) {
+        const double *row = mom + 5 * (size_t)iy * nx;
+        const double vx = (nx & 1) ? row[5 * (nx / 2) + 1] : 0.5 * (row[5 * (nx / 2 - 1) + 1] + row[5 * (nx / 2) + 1]);
+        u[iy] = vx / uw;
+    }
+    // lowest row of the run of positive u that reaches the lid
+    int lo = ny - 1;
+    while (lo > 0 && u[lo - 1] > 0.0) --lo;
+    double area = 0.0;
+    if (lo == 0) {
+        const double ub = ny > 1 ? 1.5 * u[0] - 0.5 * u[1] : u[0];
+        area += 0.25 * h * (ub + u[0]);
+    } else if (u[lo] > 0.0) {
+        area += 0.5 * h * u[lo] * u[lo] / (u[lo] - u[lo - 1]);
+    }
+    for (int iy = lo; iy + 1 < ny; ++iy) area += 0.5 * h * (u[iy] + u[iy + 1]);
+    const double ut = ny > 1 ? 1.5 * u[ny - 1] - 0.5 * u[ny - 2] : u[ny - 1];
+    area += 0.25 * h * (u[ny - 1] + ut);
+    out[1] = 2.0 * area / H;
+}
+
+extern "C" int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f || !out) return fail(ctx, BGK_E_INVALID, "bgk_cavity_metrics: NULL buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (!ctx->lid_L) HIP_TRY(ctx, hipMalloc((void **)&ctx->lid_L, sizeof(double) * ctx->ninst));
+    TRY(ctx->precision == BGK_FP64 ? lid<double>(ctx, f, ctx->lid_L, nullptr, nullptr, s)
+                                   : lid<float>(ctx, f, ctx->lid_L, nullptr, nullptr, s));
+    TRY(bgk_moments(ctx, f, ctx->mom, stream));
+    std::vector<double> L(ctx->ninst), mom((size_t)ctx->ncells * 5);
+    HIP_TRY(ctx, hipMemcpyAsync(L.data(), ctx->lid_L, sizeof(double) * L.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(mom.data(), ctx->mom, sizeof(double) * mom.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (int i = 0; i < ctx->ninst; ++i) {
+        const Inst &I = ctx->h_inst[i];
+        if (I.kind != KIND_CAVITY || !(I.uw != 0.0)) {
+            out[2 * i] = out[2 * i + 1] = std::nan("");
+            continue;
+        }
+        centre_line_metrics(I, ctx->probs[i], mom.data() + 5 * (size_t)I.cell0, L[i], out + 2 * i);
+    }
+    return BGK_OK;
 }
 
 // ------------------------------------------------------------- autotuning

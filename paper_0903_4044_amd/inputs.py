@@ -96,6 +96,21 @@ CONFIGS = {
                                precision="fp32"),
 }
 
+# The driven-cavity runs of the Table of Sec. 5.2: rarefaction parameter
+# delta = 1 / Kn on the unit square, 160 x 160 cells, 20^3 velocities on
+# [-3, 3]^3, a lid speed of 0.01 sqrt(2 R T_w) (lid_mach = 0.01 / sqrt(5/6)),
+# walls at T_w = 1, run from rest to a steady state.
+TABLE_DELTAS = (0.1, 1.0, 10.0)
+
+
+def table_cavity(delta: float, **override) -> dict:
+    d = _base(kind="cavity", nx=160, ny=160, nv=(20, 20, 20), vlo=(-3.0,) * 3, vhi=(3.0,) * 3,
+              kn=1.0 / delta, lid_mach=0.01 / (5.0 / 6.0) ** 0.5, t_wall=1.0, steps=0,
+              maxwellian="conservative", precision="fp32")
+    d.update(override)
+    return d
+
+
 SIDES = (32, 48, 64, 96, 128)
 
 
