@@ -626,12 +626,23 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
     }
     if (c->shift) {
         const real *p = (const real *)params_buf<real>(c, c->pass_parity);
-        if (stream_nt(c))
-            hipLaunchKernelGGL((k_shift<real, true>), dim3(nb), dim3(c->sblock), 0, s, make_args(c),
-                               (const real *)src, (real *)dst, p, c->partial);
+        // the v_z tables of a cell's 2 Nvx source entries, staged in LDS when they fit in 64 KB
+        const size_t st = (size_t)4 * c->geo.nvx * c->geo.nvz * sizeof(real);
+        const bool stage = st <= 65536 && (int)st <= c->lds_max / 2;
+        const bool nt = stream_nt(c);
+        const Args a = make_args(c);
+        if (stage && nt)
+            hipLaunchKernelGGL((k_shift<real, true, true>), dim3(nb), dim3(c->sblock), st, s, a, (const real *)src,
+                               (real *)dst, p, c->partial);
+        else if (stage)
+            hipLaunchKernelGGL((k_shift<real, false, true>), dim3(nb), dim3(c->sblock), st, s, a, (const real *)src,
+                               (real *)dst, p, c->partial);
+        else if (nt)
+            hipLaunchKernelGGL((k_shift<real, true, false>), dim3(nb), dim3(c->sblock), 0, s, a, (const real *)src,
+                               (real *)dst, p, c->partial);
         else
-            hipLaunchKernelGGL((k_shift<real, false>), dim3(nb), dim3(c->sblock), 0, s, make_args(c),
-                               (const real *)src, (real *)dst, p, c->partial);
+            hipLaunchKernelGGL((k_shift<real, false, false>), dim3(nb), dim3(c->sblock), 0, s, a, (const real *)src,
+                               (real *)dst, p, c->partial);
     } else if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
     else stream_dispatch<real, 1>(c, nb, lds, src, dst, s);
     HIP_TRY(c, hipGetLastError());

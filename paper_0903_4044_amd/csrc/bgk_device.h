@@ -1178,15 +1178,41 @@ __global__ void __launch_bounds__(256)
 // A lane task is one (jx, jy) at one jz residue, as in the per-cell kernel
 // with VEC = 1; the two sources and their entries depend on v_x, so each
 // lane resolves them itself (entries from global memory instead of the
-// workgroup's slot table).  With |C| < 1 (m = 0) every operation, the
-// rounding bits and the moment epilogue are those of the per-cell kernel
-// with the limiter off, so the two agree bit for bit there.
-template <typename real, bool NTSTORE>
+// workgroup's slot table).  With STAGE the v_z tables of the 2 Nvx source
+// entries of the workgroup's cell (one pair per jx and source) are copied
+// to LDS once per cell, [jz][source][jx][2], so the jz loop issues two
+// global loads per element (the two sources' h) instead of six.  With
+// |C| < 1 (m = 0) every operation, the rounding bits and the moment
+// epilogue are those of the per-cell kernel with the limiter off, so the
+// two agree bit for bit there.
+
+// Source k (0: a = c - s m, 1: b = a - s) of cell c: the cell whose h is
+// read and the table entry that relaxes it (ghosts read cell c; their
+// entries have c0 = 0).
+__device__ __forceinline__ void shift_source(const Inst &I, int c, int sgn, int m, int k, int *cell, int *par)
+{
+    const int pos = c - sgn * (m + k);
+    if (pos >= 0 && pos < I.nx) { *cell = pos; *par = I.cell0 + pos; }
+    else if (I.kind == KIND_PER1) { *cell = ((pos % I.nx) + I.nx) % I.nx; *par = I.cell0 + *cell; }
+    else { *cell = c; *par = I.pseudo0 + (pos < 0 ? 0 : 1); }
+}
+
+__device__ __forceinline__ void shift_of(const Geo &g, const Inst &I, int jx, int *m, int *sgn, double *ac)
+{
+    const double vx = vnode(g, 0, jx);
+    *ac = fabs(vx) * I.cx;
+    *m = (int)floor(*ac);
+    *sgn = vx > 0.0 ? 1 : -1;
+}
+
+template <typename real, bool NTSTORE, bool STAGE>
 __global__ void __launch_bounds__(256)
     k_shift(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
             double *__restrict__ partial)
 {
     using V = vec_t<real, 1>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    real *stz = reinterpret_cast<real *>(smem);  // STAGE: [jz - z0][source][jx][2]
     __shared__ double vzt[NVMAX][2];
     const Geo &g = A.g;
     for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
@@ -1213,23 +1239,35 @@ __global__ void __launch_bounds__(256)
         const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;
         const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
         double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (STAGE) {
+            // the previous item's reads of stz ended at its closing barrier
+            const int nst = 2 * g.nvx * (z1 - z0);
+            for (int q = threadIdx.x; q < nst; q += blockDim.x) {
+                const int zl = q % (z1 - z0), r = q / (z1 - z0), jx = r % g.nvx, k = r / g.nvx;
+                int m, sgn, cell, par;
+                double ac;
+                shift_of(g, I, jx, &m, &sgn, &ac);
+                shift_source(I, c, sgn, m, k, &cell, &par);
+                const real *E = params + (long long)par * g.pe + g.tz + 2 * (z0 + zl);
+                real *d = stz + (((size_t)zl * 2 + k) * g.nvx + jx) * 2;
+                d[0] = E[0];
+                d[1] = E[1];
+            }
+            __syncthreads();
+        }
         for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
             const int p0 = task % g.npl, zr = task / g.npl;
             const int jy = p0 / g.nvx, jx = p0 - jy * g.nvx;
             const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
-            const double ac = fabs(vx) * I.cx;
-            const int m = (int)floor(ac);
+            int m, sgn;
+            double ac;
+            shift_of(g, I, jx, &m, &sgn, &ac);
             const real th = (real)(ac - (double)m);
-            const int sgn = vx > 0.0 ? 1 : -1;
-            // the two sources: cell of h and table entry (ghosts read cell c; their entries have c0 = 0)
             Tap<real, 1> tp[2];
             const real *Ez[2];
             for (int k = 0; k < 2; ++k) {
-                const int pos = c - sgn * (m + k);
                 int cell, par;
-                if (pos >= 0 && pos < I.nx) { cell = pos; par = I.cell0 + pos; }
-                else if (I.kind == KIND_PER1) { cell = ((pos % I.nx) + I.nx) % I.nx; par = I.cell0 + cell; }
-                else { cell = c; par = I.pseudo0 + (pos < 0 ? 0 : 1); }
+                shift_source(I, c, sgn, m, k, &cell, &par);
                 const real *E = params + (long long)par * g.pe;
                 tp[k] = make_tap_at<real, 1>(g, E, cell, p0, jx, jy);
                 Ez[k] = E + g.tz;
@@ -1254,9 +1292,22 @@ __global__ void __launch_bounds__(256)
                 load(h, jz);
                 for (; jz < z1; jz += A.zr) {
                     load(hn, jz + A.zr);
-                    const real a0 = Ez[0][2 * jz], b0 = Ez[0][2 * jz + 1];
+                    real a0, b0, a1, b1;
+                    if constexpr (STAGE) {
+                        const real *s0 = stz + ((size_t)(jz - z0) * 2 * g.nvx + jx) * 2;
+                        const real *s1 = s0 + 2 * g.nvx;
+                        a0 = s0[0];
+                        b0 = s0[1];
+                        a1 = s1[0];
+                        b1 = s1[1];
+                    } else {
+                        a0 = Ez[0][2 * jz];
+                        b0 = Ez[0][2 * jz + 1];
+                        a1 = Ez[1][2 * jz];
+                        b1 = Ez[1][2 * jz + 1];
+                    }
                     const V u0 = tp[0].relax_ab(h[0], a0, b0);
-                    const V u1 = tp[1].relax_ab(h[1], Ez[1][2 * jz], Ez[1][2 * jz + 1]);
+                    const V u1 = tp[1].relax_ab(h[1], a1, b1);
                     const real dx = th * (u0[0] - u1[0]), dy = 0;
                     real r;
                     if constexpr (sizeof(real) == 4) {
