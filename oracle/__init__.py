@@ -40,6 +40,7 @@ class Problem(ctypes.Structure):
         ("t_wall", ctypes.c_double),
         ("strang", ctypes.c_int), ("minmod", ctypes.c_int),
         ("conservative", ctypes.c_int),
+        ("reduced", ctypes.c_int),
     ]
 
 
@@ -116,6 +117,9 @@ def make_problem(cfg: dict) -> Problem:
     p.strang = 1 if cfg.get("splitting", "strang") == "strang" else 0
     p.minmod = {"minmod": 1, "none": 0, "shift": 2}[cfg.get("limiter", "minmod")]
     p.conservative = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
+    p.reduced = 1 if cfg.get("reduced", False) else 0
+    if p.reduced and (cfg["kind"] not in ("cavity", "periodic2d") or int(cfg["nv"][2]) != 2 or p.conservative):
+        raise ValueError("the reduced velocity space takes two-dimensional kinds, nv[2] = 2 and the point Maxwellian")
     return p
 
 
@@ -223,8 +227,8 @@ class Oracle:
 
     # -- reverse sweep (hand-derived adjoint) -----------------------------
     def _no_conservative(self):
-        if self.p.conservative:
-            raise NotImplementedError("the reverse sweep covers the point-value Maxwellian only")
+        if self.p.conservative or self.p.reduced:
+            raise NotImplementedError("the reverse sweep covers the point-value Maxwellian in full velocity space only")
 
     def relax_adjoint(self, x, mu, tau):
         """(dR_tau/dx)^T mu at x, and dL/dKn."""

@@ -34,6 +34,10 @@
  *   - two ghost layers per side: the far-field Maxwellians for the shock,
  *     the diffuse-wall rule of Eq. (bc_cavity) for the cavity;
  *   - dt = CFL / max_j sum_d |v_d(j)| / dx_d over velocity cell centres;
+ *   - the reduced velocity space for two-dimensional problems (the
+ *     projection the paper cites in Sec. 3 and Sec. 6): f is replaced by
+ *     g = int f dv_z and h = int v_z^2 f dv_z on the (v_x, v_y) grid, with
+ *     the v_z integrals of Eq. (Maxw) taken exactly and V_z = 0;
  *   - the conservative variant (Sec. 2.1, the remark after Eq. (exact)) takes
  *     the effective (n~, V~, T~) as the exact root of "grid moments of the
  *     discretized Maxwellian = the cell's n, V, T"; the collision frequency
@@ -68,6 +72,8 @@ typedef struct {
     int strang; /* 1: R_{dt/2} S R_{dt/2}; 0: R_dt S (Lie) */
     int minmod; /* 1: minmod slopes; 0: first-order upwind; 2: shift + first-order upwind */
     int conservative; /* 1: relaxations use the effective Maxwellian parameters */
+    int reduced; /* 1: two-dimensional kinds with v_z integrated out: plane jz = 0 holds
+                    g = int f dv_z, plane jz = 1 holds h = int v_z^2 f dv_z (nv[2] = 2) */
 } orc_problem;
 
 static const double GAMMA = 5.0 / 3.0;
@@ -77,34 +83,54 @@ static const double GAMMA = 5.0 / 3.0;
 static int is2d(const orc_problem *p) { return p->kind == ORC_CAVITY || p->kind == ORC_PERIODIC2; }
 static long ncell(const orc_problem *p) { return (long)p->nx * (is2d(p) ? p->ny : 1); }
 static long nvel(const orc_problem *p) { return (long)p->nv[0] * p->nv[1] * p->nv[2]; }
-static double dvel(const orc_problem *p, int a) { return (p->vhi[a] - p->vlo[a]) / p->nv[a]; }
+static double dvel(const orc_problem *p, int a)
+{
+    if (a == 2 && p->reduced) return 1.0; /* the two planes are integrals over v_z */
+    return (p->vhi[a] - p->vlo[a]) / p->nv[a];
+}
 static double dvol(const orc_problem *p) { return dvel(p, 0) * dvel(p, 1) * dvel(p, 2); }
 static double dxs(const orc_problem *p) { return (p->x1 - p->x0) / p->nx; }
 static double dys(const orc_problem *p) { return (p->y1 - p->y0) / p->ny; }
 
 /* Velocity of every node, Sec. 2.1: cell centres of a box cut into equal
- * cells, v_a(k) = lo_a + (k + 1/2) dv_a.  Returned as three arrays of Nv. */
-typedef struct { double *vx, *vy, *vz; long nv; } velgrid;
+ * cells, v_a(k) = lo_a + (k + 1/2) dv_a.  Returned as three arrays of Nv,
+ * with two weights per node: m, the node's share in mass and momentum, and
+ * e, an energy term beyond m |v|^2.  Full velocity space: m = 1, e = 0.
+ * Reduced (v_z integrated out, the projection the paper cites in Sec. 3 and
+ * Sec. 6): v_z = 0 on both planes; the g plane has m = 1, e = 0 and the h
+ * plane m = 0, e = 1 (h already is the v_z^2 moment). */
+typedef struct { double *vx, *vy, *vz, *m, *e; long nv; int reduced; } velgrid;
 
 static velgrid make_velgrid(const orc_problem *p)
 {
     velgrid g;
     g.nv = nvel(p);
+    g.reduced = p->reduced;
     g.vx = malloc(sizeof(double) * g.nv);
     g.vy = malloc(sizeof(double) * g.nv);
     g.vz = malloc(sizeof(double) * g.nv);
+    g.m = malloc(sizeof(double) * g.nv);
+    g.e = malloc(sizeof(double) * g.nv);
     for (int jz = 0; jz < p->nv[2]; ++jz)
         for (int jy = 0; jy < p->nv[1]; ++jy)
             for (int jx = 0; jx < p->nv[0]; ++jx) {
                 long j = ((long)jz * p->nv[1] + jy) * p->nv[0] + jx;
                 g.vx[j] = p->vlo[0] + (jx + 0.5) * dvel(p, 0);
                 g.vy[j] = p->vlo[1] + (jy + 0.5) * dvel(p, 1);
-                g.vz[j] = p->vlo[2] + (jz + 0.5) * dvel(p, 2);
+                if (p->reduced) {
+                    g.vz[j] = 0.0;
+                    g.m[j] = jz == 0 ? 1.0 : 0.0;
+                    g.e[j] = jz == 0 ? 0.0 : 1.0;
+                } else {
+                    g.vz[j] = p->vlo[2] + (jz + 0.5) * dvel(p, 2);
+                    g.m[j] = 1.0;
+                    g.e[j] = 0.0;
+                }
             }
     return g;
 }
 
-static void free_velgrid(velgrid *g) { free(g->vx); free(g->vy); free(g->vz); }
+static void free_velgrid(velgrid *g) { free(g->vx); free(g->vy); free(g->vz); free(g->m); free(g->e); }
 
 void orc_velocity_nodes(const orc_problem *p, double *vx, double *vy, double *vz)
 {
@@ -136,24 +162,31 @@ double orc_dt(const orc_problem *p)
 /* ------------------------------------------------------------- physics */
 
 /* Local Maxwellian, Eq. (Maxw), in normalised units. */
-void orc_maxwellian(const orc_problem *p, double n, const double V[3], double T, double *phi)
-{
-    velgrid g = make_velgrid(p);
-    double pre = n * pow(M_PI * T, -1.5);
-    for (long j = 0; j < g.nv; ++j) {
-        double cx = g.vx[j] - V[0], cy = g.vy[j] - V[1], cz = g.vz[j] - V[2];
-        phi[j] = pre * exp(-(cx * cx + cy * cy + cz * cz) / T);
-    }
-    free_velgrid(&g);
-}
-
+/* Reduced velocity space: the v_z integrals of Eq. (Maxw),
+ *   int Phi dv_z = n (pi T)^-1 exp(-((v_x - V_x)^2 + (v_y - V_y)^2) / T),
+ *   int v_z^2 Phi dv_z = (T / 2) times that  (V_z = 0). */
 static void maxwellian_on(const velgrid *g, double n, const double V[3], double T, double *phi)
 {
+    if (g->reduced) {
+        double pre = n / (M_PI * T);
+        for (long j = 0; j < g->nv; ++j) {
+            double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1];
+            phi[j] = pre * exp(-(cx * cx + cy * cy) / T) * (g->m[j] != 0.0 ? 1.0 : 0.5 * T);
+        }
+        return;
+    }
     double pre = n * pow(M_PI * T, -1.5);
     for (long j = 0; j < g->nv; ++j) {
         double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1], cz = g->vz[j] - V[2];
         phi[j] = pre * exp(-(cx * cx + cy * cy + cz * cz) / T);
     }
+}
+
+void orc_maxwellian(const orc_problem *p, double n, const double V[3], double T, double *phi)
+{
+    velgrid g = make_velgrid(p);
+    maxwellian_on(&g, n, V, T, phi);
+    free_velgrid(&g);
 }
 
 /* Macroscopic moments of one cell, Eq. (macroscopic), as velocity sums over
@@ -163,10 +196,10 @@ static void cell_moments(const velgrid *g, double dV, const double *f, double *n
 {
     double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     for (long j = 0; j < g->nv; ++j) {
-        s0 += f[j];
-        sx += g->vx[j] * f[j];
-        sy += g->vy[j] * f[j];
-        sz += g->vz[j] * f[j];
+        s0 += g->m[j] * f[j];
+        sx += g->m[j] * g->vx[j] * f[j];
+        sy += g->m[j] * g->vy[j] * f[j];
+        sz += g->m[j] * g->vz[j] * f[j];
     }
     *n = s0 * dV;
     V[0] = sx * dV / *n;
@@ -175,7 +208,7 @@ static void cell_moments(const velgrid *g, double dV, const double *f, double *n
     double s2 = 0.0;
     for (long j = 0; j < g->nv; ++j) {
         double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1], cz = g->vz[j] - V[2];
-        s2 += (cx * cx + cy * cy + cz * cz) * f[j];
+        s2 += (g->m[j] * (cx * cx + cy * cy + cz * cz) + g->e[j]) * f[j];
     }
     *T = 2.0 / 3.0 * s2 * dV / *n;
 }
@@ -389,8 +422,8 @@ static double wall_density(const velgrid *g, int axis, double sign, const double
     double num = 0.0, den = 0.0;
     for (long j = 0; j < g->nv; ++j) {
         double vn = sign * va[j];
-        if (vn < 0.0) num += -vn * g0[j];
-        else if (vn > 0.0) den += vn * phiw[j];
+        if (vn < 0.0) num += -vn * g->m[j] * g0[j];
+        else if (vn > 0.0) den += vn * g->m[j] * phiw[j];
     }
     return num / den;
 }
@@ -665,13 +698,13 @@ void orc_totals(const orc_problem *p, const double *f, double *tot /* [6] */)
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (long c = 0; c < nc; ++c)
         for (long j = 0; j < nv; ++j) {
-            double v = f[c * nv + j];
-            s[0] += v;
-            s[1] += g.vx[j] * v;
-            s[2] += g.vy[j] * v;
-            s[3] += g.vz[j] * v;
-            s[4] += (g.vx[j] * g.vx[j] + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j]) * v;
-            if (v > 0.0) s[5] += v * log(v);
+            double v = f[c * nv + j], mv = g.m[j] * v;
+            s[0] += mv;
+            s[1] += g.vx[j] * mv;
+            s[2] += g.vy[j] * mv;
+            s[3] += g.vz[j] * mv;
+            s[4] += (g.vx[j] * g.vx[j] + g.vy[j] * g.vy[j] + g.vz[j] * g.vz[j]) * mv + g.e[j] * v;
+            if (mv > 0.0) s[5] += mv * log(mv);
         }
     for (int k = 0; k < 6; ++k) tot[k] = s[k] * w;
     free_velgrid(&g);
@@ -695,8 +728,8 @@ double orc_lid_shear(const orc_problem *p, const double *f)
         double nW = wall_density(&g, 1, -1.0, ft, lid);
         double s_in = 0.0, s_out = 0.0;
         for (long j = 0; j < nv; ++j) {
-            if (g.vy[j] > 0.0) s_in += g.vx[j] * g.vy[j] * ft[j];
-            else if (g.vy[j] < 0.0) s_out += g.vx[j] * g.vy[j] * lid[j];
+            if (g.vy[j] > 0.0) s_in += g.m[j] * g.vx[j] * g.vy[j] * ft[j];
+            else if (g.vy[j] < 0.0) s_out += g.m[j] * g.vx[j] * g.vy[j] * lid[j];
         }
         L += dx * (s_in + nW * s_out) * dV;
     }

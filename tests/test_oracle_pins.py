@@ -547,6 +547,52 @@ def test_vortex_flow_rate_takes_the_top_vortex(oracle_mod):
     assert err[1] < 0.3 * err[0] and err[1] < 2e-4
 
 
+# ------------------------------------------------- reduced velocity space
+# Two-dimensional problems with v_z integrated out (g = int f dv_z,
+# h = int v_z^2 f dv_z), the projection the paper cites in Sec. 3 and Sec. 6.
+
+
+def test_reduced_maxwellian_moments(oracle_mod):
+    """The reduced Maxwellian pair has the moments of its parameters: n and V
+    from g, T from g's (v_x, v_y) spread plus h (on a resolving grid)."""
+    cfg = prob(kind="periodic2d", nx=2, ny=2, nv=(40, 40, 2), vlo=(-9, -9, -1), vhi=(9, 9, 1), reduced=True)
+    O = oracle_mod.Oracle(cfg)
+    for n, V, T in [(1.0, (0.0, 0.0), 1.0), (2.5, (0.7, -0.3), 1.7)]:
+        phi = O.maxwellian(n, np.array([V[0], V[1], 0.0]), T)
+        g, h = phi[:1600], phi[1600:]
+        np.testing.assert_allclose(h, 0.5 * T * g, rtol=1e-15)
+        m = O.moments(np.tile(phi, (O.ncell, 1)))[0]
+        np.testing.assert_allclose(m, [n, V[0], V[1], 0.0, T], rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["cavity", "periodic2d"])
+@pytest.mark.parametrize("splitting", ["strang", "lie"])
+def test_reduced_model_is_the_projection_of_the_full_one(oracle_mod, kind, splitting):
+    """With the linear (first-order upwind) streaming every operation commutes
+    with integrating over v_z: stepping the full model on a resolving v_z grid
+    and projecting equals stepping the projected state in the reduced model.
+    The initial state is even in v_z (V_z = 0) and varies with x, v_x, v_y."""
+    common = dict(kind=kind, nx=5, ny=4, kn=0.4, lid_mach=0.3, t_wall=1.2, splitting=splitting, limiter="none")
+    full = prob(nv=(6, 5, 24), vlo=(-3, -3, -6), vhi=(3, 3, 6), **common)
+    red = prob(nv=(6, 5, 2), vlo=(-3, -3, -1), vhi=(3, 3, 1), reduced=True, **common)
+    F, R = oracle_mod.Oracle(full), oracle_mod.Oracle(red)
+    xi = inputs.uniform((F.ncell, 1, 5, 6), seed=61, lo=-1, hi=1)
+    f0 = (F.initial_state().reshape(F.ncell, 24, 5, 6) * (1 + 0.3 * xi)).reshape(F.shape)
+    vz = F.velocity_nodes()[2].reshape(24, 5, 6)[:, 0, 0]
+    dvz = 0.5
+
+    def project(f):
+        f = f.reshape(-1, 24, 5, 6)
+        g = f.sum(axis=1) * dvz
+        h = (f * vz[None, :, None, None] ** 2).sum(axis=1) * dvz
+        return np.concatenate([g.reshape(-1, 30), h.reshape(-1, 30)], axis=1)
+
+    got = R.step(project(f0), 3)
+    want = project(F.step(f0, 3))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    np.testing.assert_allclose(R.moments(got), F.moments(F.step(f0, 3)), rtol=1e-11, atol=1e-13)
+
+
 # ------------------------------------------------------------------ twin
 
 
