@@ -299,20 +299,28 @@ static int effective_parameters(const velgrid *g, double dV, double n, const dou
         cell_moments(g, dV, phi, &nd, Vd, &Td);
         double J[5][5] = {{0}}, r[5] = {nd - n, Vd[0] - V[0], Vd[1] - V[1], Vd[2] - V[2], Td - T};
         for (long j = 0; j < g->nv; ++j) {
-            const double v[3] = {g->vx[j], g->vy[j], g->vz[j]};
+            const double v[3] = {g->vx[j], g->vy[j], g->vz[j]}, m = g->m[j];
             double dM[5], dP[5], cd2 = 0.0, ct2 = 0.0;
             for (int a = 0; a < 3; ++a) {
                 cd2 += (v[a] - Vd[a]) * (v[a] - Vd[a]);
                 ct2 += (v[a] - q[1 + a]) * (v[a] - q[1 + a]);
             }
-            dM[0] = dV;
-            for (int a = 0; a < 3; ++a) dM[1 + a] = dV * (v[a] - Vd[a]) / nd;
-            dM[4] = 2.0 / 3.0 * dV * (cd2 - 1.5 * Td) / nd;
+            dM[0] = m * dV;
+            for (int a = 0; a < 3; ++a) dM[1 + a] = m * dV * (v[a] - Vd[a]) / nd;
+            dM[4] = 2.0 / 3.0 * dV * (m * cd2 + g->e[j] - 1.5 * Td * m) / nd;
             dP[0] = phi[j] / q[0];
             for (int a = 0; a < 3; ++a) dP[1 + a] = phi[j] * 2.0 * (v[a] - q[1 + a]) / q[4];
-            dP[4] = phi[j] * (ct2 / (q[4] * q[4]) - 1.5 / q[4]);
+            /* T~ enters the prefactor as T~^(-3/2); in the reduced space as
+             * T~^(-1) on the g plane and T~^0 on the h plane (h = (T~/2) g) */
+            const double k = g->reduced ? (m != 0.0 ? 1.0 : 0.0) : 1.5;
+            dP[4] = phi[j] * (ct2 / (q[4] * q[4]) - k / q[4]);
             for (int row = 0; row < 5; ++row)
                 for (int col = 0; col < 5; ++col) J[row][col] += dM[row] * dP[col];
+        }
+        if (g->reduced) { /* V_z = 0 is not an unknown there */
+            for (int k = 0; k < 5; ++k) J[3][k] = J[k][3] = 0.0;
+            J[3][3] = 1.0;
+            r[3] = 0.0;
         }
         if (solve5(J, r) != 0) break;
         for (int k = 0; k < 5; ++k) q[k] -= r[k];

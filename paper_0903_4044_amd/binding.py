@@ -43,6 +43,7 @@ class Problem(ctypes.Structure):
         ("t_wall", ctypes.c_double),
         ("splitting", ctypes.c_int), ("limiter", ctypes.c_int),
         ("maxwellian", ctypes.c_int),
+        ("reduced", ctypes.c_int),
     ]
 
 
@@ -115,6 +116,7 @@ def to_struct(cfg: dict) -> Problem:
     p.splitting = 0 if cfg.get("splitting", "strang") == "strang" else 1
     p.limiter = {"minmod": 0, "none": 1, "shift": 2}[cfg.get("limiter", "minmod")]
     p.maxwellian = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
+    p.reduced = 1 if cfg.get("reduced", False) else 0
     return p
 
 

@@ -698,7 +698,7 @@ __global__ void __launch_bounds__(256) k_lid_sums(Args A, const real *__restrict
         for (long long j = threadIdx.x; j < g.nv; j += blockDim.x) {
             const int jx = (int)(j % g.nvx), jy = (int)((j / g.nvx) % g.nvy);
             const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
-            if (vy > 0.0) {
+            if (vy > 0.0 && (!g.red || j < g.npl)) {  // reduced: the g plane carries mass
                 acc[0] += vx * vy * (double)fc[j];
                 acc[1] += vy * (double)fc[j];
             }
@@ -717,9 +717,11 @@ __device__ __forceinline__ void lid_constants(const Geo &g, const Inst &I, doubl
     for (long long j = threadIdx.x & 63; j < g.nv; j += 64) {
         const int jx = (int)(j % g.nvx), jy = (int)((j / g.nvx) % g.nvy), jz = (int)(j / g.npl);
         const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy), vz = vnode(g, 2, jz);
+        if (g.red && jz > 0) continue;  // reduced: the g plane carries mass and momentum
         if (vy < 0.0) {
-            const double c2 = (vx - I.uw) * (vx - I.uw) + vy * vy + vz * vz;
-            const double phi = pw * exp(-c2 / I.tw);
+            const double c2 = g.red ? (vx - I.uw) * (vx - I.uw) + vy * vy
+                                    : (vx - I.uw) * (vx - I.uw) + vy * vy + vz * vz;
+            const double phi = pw * exp(-c2 / I.tw) * (g.red ? zfactor(g, 0, 0.0, I.tw) : 1.0);
             const double dphi = phi * (c2 / (I.tw * I.tw) - 1.5 / I.tw);
             k += vx * vy * phi;
             d += -vy * phi;

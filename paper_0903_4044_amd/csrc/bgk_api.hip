@@ -187,6 +187,13 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (p.splitting != BGK_STRANG && p.splitting != BGK_LIE) return bad("unknown splitting");
     if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT && p.limiter != BGK_SHIFT) return bad("unknown limiter");
     if (p.maxwellian != BGK_POINT && p.maxwellian != BGK_CONSERVATIVE) return bad("unknown Maxwellian form");
+    if (p.reduced != 0 && p.reduced != 1) return bad("reduced must be 0 or 1");
+    if (p.reduced && (!two || p.nv[2] != 2)) {
+        snprintf(b, sizeof b, "problem %d: the reduced velocity space takes two-dimensional kinds and nv[2] = 2",
+                 idx);
+        msg = b;
+        return BGK_E_UNSUPPORTED;
+    }
     if (p.limiter == BGK_SHIFT && two) {
         snprintf(b, sizeof b, "problem %d: shift streaming is one-dimensional", idx);
         msg = b;
@@ -218,6 +225,7 @@ static bool vec_valid(const bgk_ctx *c, int v)
     const Geo &g = c->geo;
     if (v == 1) return true;
     if (c->shift) return false;  // the translation-form kernel takes one jx per lane task
+    if (g.red) return false;     // reduced: the column fold needs one jx per lane task
     if (v == 4 && c->precision == BGK_FP64) return false;
     if (g.nvx % v) return false;
     for (int k = 0; k < g.nvx; k += v) {
@@ -294,6 +302,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
         const bgk_problem &p = probs[i], &q = probs[0];
         if (is2d_kind(p.kind) != is2d_kind(q.kind))
             return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must have the same dimension");
+        if (p.reduced != q.reduced)
+            return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must share the velocity space (reduced or not)");
         if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
             return fail(nullptr, BGK_E_UNSUPPORTED, "shift streaming cannot share a context with other limiters");
         for (int a = 0; a < 3; ++a)
@@ -321,9 +331,14 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     g.npl = g.nvx * g.nvy;
     g.nv = (long long)g.npl * g.nvz;
     g.dV = 1.0;
+    g.red = probs[0].reduced ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = probs[0].vlo[a];
         g.dv[a] = (probs[0].vhi[a] - probs[0].vlo[a]) / probs[0].nv[a];
+        if (a == 2 && g.red) {  // the two planes are integrals over v_z
+            g.lo[a] = 0.0;
+            g.dv[a] = 1.0;
+        }
         g.dV *= g.dv[a];
     }
     g.tx1 = 4;
@@ -887,6 +902,8 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
     if (ctx->conservative)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of the effective Maxwellian parameters");
+    if (ctx->geo.red)
+        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep in the reduced velocity space");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
                                       : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
@@ -921,6 +938,7 @@ extern "C" int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double
     if (!ctx) return BGK_E_INVALID;
     if (!f || !lam || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_lid_shear_grad: NULL buffer");
     if (lam == f) return fail(ctx, BGK_E_ALIAS, "bgk_lid_shear_grad: lam must not alias f");
+    if (ctx->geo.red) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_lid_shear_grad: not in the reduced velocity space");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, nullptr, lam, grad_params, s)
                                       : lid<float>(ctx, f, nullptr, lam, grad_params, s);

@@ -59,6 +59,7 @@ struct Geo {
     long long nv;               // nvx * nvy * nvz
     double lo[3], dv[3];
     double dV;
+    int red;                    // 1: v_z integrated out (plane 0 g = int f dv_z, plane 1 h = int v_z^2 f dv_z)
     int pe;                     // params entry stride (elements)
     int tx1, ty1, tx2, ty2, tz; // entry offsets
 };
@@ -124,6 +125,34 @@ __device__ __forceinline__ int strip_cell(const Inst &I, int q)
 }
 
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
+
+// The v_z axis.  Full velocity space: nodes v_z(k).  Reduced velocity space
+// (two-dimensional problems, the projection the paper cites in Sec. 3 and
+// Sec. 6): plane 0 holds g = int f dv_z and plane 1 h = int v_z^2 f dv_z, so
+// V_z = 0 and the v_z integrals of Eq. (Maxw) are exact.  Per plane: its
+// share m in mass and momentum, its v_z and its energy term zz beyond
+// m |v|^2: (1, v_z, v_z^2) in full velocity space, (1, 0, 0) for g and
+// (0, 0, 1) for h.
+struct ZW { double m, z, zz; };
+
+__device__ __forceinline__ ZW zweights(const Geo &g, int k)
+{
+    if (g.red) return k == 0 ? ZW{1.0, 0.0, 0.0} : ZW{0.0, 0.0, 1.0};
+    const double vz = vnode(g, 2, k);
+    return ZW{1.0, vz, vz * vz};
+}
+
+// The Maxwellian's factor on plane k: exp(-(v_z - V_z)^2 / T), or in reduced
+// velocity space the integrals sqrt(pi T) (g) and (T / 2) sqrt(pi T) (h).
+__device__ __forceinline__ double zfactor(const Geo &g, int k, double Vz, double T)
+{
+    if (g.red) {
+        const double s = sqrt(M_PI * T);
+        return k == 0 ? s : 0.5 * T * s;
+    }
+    const double d = vnode(g, 2, k) - Vz;
+    return exp(-d * d / T);
+}
 
 __device__ __forceinline__ float minmod3(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 
@@ -282,16 +311,16 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
 #pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const V h = ld<V>(fc, (uint32_t)((jz * g.npl + p0) * (int)sizeof(real)));
+            const ZW w = zweights(g, jz);
             double sh = 0.0;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const double he = (double)h[e];
-                A0[e] += he;
+                A0[e] = __builtin_fma(w.m, he, A0[e]);
                 sh += he;
             }
-            const double vz = vnode(g, 2, jz);
-            Az += vz * sh;
-            Azz += vz * vz * sh;
+            Az += w.z * sh;
+            Azz += w.zz * sh;
         }
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
@@ -412,8 +441,13 @@ __device__ __forceinline__ void lane_tables(const Geo &g, const double V[3], dou
             const int k = lane + W * s;
             t.e[a][s] = 0.0;
             if (W * s >= nv_of(g, a)) continue;  // uniform: no second slot up to W points
-            const double d = vnode(g, a, k) - V[a];
-            if (k < nv_of(g, a)) t.e[a][s] = exp(-d * d / T);
+            if (k >= nv_of(g, a)) continue;
+            if (a == 2) {
+                t.e[a][s] = zfactor(g, k, V[a], T);
+            } else {
+                const double d = vnode(g, a, k) - V[a];
+                t.e[a][s] = exp(-d * d / T);
+            }
         }
 }
 
@@ -434,7 +468,15 @@ __device__ __forceinline__ void wave_table_sums(const Geo &g, const Tables &t, d
         double s0 = 0, s1 = 0, s2 = 0, sm = 0, sp = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const double v = vnode(g, a, lane + W * q), x = t.e[a][q];
+            const double x = t.e[a][q];
+            if (a == 2) {
+                const ZW w = zweights(g, lane + W * q);
+                s0 += w.m * x;
+                s1 += w.z * x;
+                s2 += w.zz * x;
+                continue;
+            }
+            const double v = vnode(g, a, lane + W * q);
             s0 += x;
             s1 += v * x;
             s2 += v * v * x;
@@ -492,6 +534,24 @@ __device__ __forceinline__ void effective_tables(const Geo &g, Relax *r, Tables 
         double res[3], jvv[3], jvt[3], jtv[3], jtt = 0.0, rt = -r->T, s0[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            if (c == 2 && g.red) {
+                // reduced velocity space: h = (T~ / 2) g on every node, so the
+                // v_z variance is T~ / 2 exactly and V_z = 0 is no unknown
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int k = lane + W * q;
+                    t.e[c][q] = k < 2 ? zfactor(g, k, 0.0, Tt) : 0.0;
+                }
+                s0[c] = zfactor(g, 0, 0.0, Tt);
+                if (done) continue;
+                res[c] = 0.0;
+                jvv[c] = 1.0;
+                jvt[c] = 0.0;
+                jtv[c] = 0.0;
+                jtt += 1.0 / 3.0;
+                rt += Tt / 3.0;
+                continue;
+            }
             double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -870,13 +930,15 @@ __global__ void __launch_bounds__(256)
     real *sp = reinterpret_cast<real *>(smem);
     __shared__ SlotInfo SI;
     // v_z and v_z^2 of every plane (wave-uniform per plane: one LDS broadcast
-    // instead of recomputing them per lane)
+    // instead of recomputing them per lane); in reduced velocity space the
+    // planes' mass shares and energy terms (the column fold takes the mass
+    // from the first sum there; reduced contexts run with VEC = 1)
     __shared__ double vzt[NVMAX][2];
     const Geo &g = A.g;
     for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
-        const double vz = vnode(g, 2, k);
-        vzt[k][0] = vz;
-        vzt[k][1] = vz * vz;
+        const ZW w = zweights(g, k);
+        vzt[k][0] = g.red ? w.m : w.z;
+        vzt[k][1] = w.zz;
     }
     // (the first barrier of the item loop orders these writes before any read)
     // Work items (cell, jz chunk).  A grid smaller than the item count makes
@@ -1161,7 +1223,8 @@ __global__ void __launch_bounds__(256)
         }
 #pragma unroll
         for (int k = 0; k < VEC; ++k)
-            fold_column(acc, vnode(g, 0, jx0 + k), vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
+            if (g.red) fold_column(acc, vnode(g, 0, jx0 + k), vy, k == 0 ? Az : 0.0, 0.0, k == 0 ? Azz : 0.0);
+            else fold_column(acc, vnode(g, 0, jx0 + k), vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
     }
     block_sum_store<NQ>(acc, partial + (long long)L * NQ);
     __syncthreads();  // LDS (slots, tables, reduction) is reused by the next item
@@ -1414,6 +1477,10 @@ __global__ void __launch_bounds__(256) k_init(Args A, real *__restrict__ f)
         const int jx = p % g.nvx, jy = p / g.nvx;
         const double dx = vnode(g, 0, jx) - V, vy = vnode(g, 1, jy);
         for (int jz = z0; jz < z1; ++jz) {
+            if (g.red) {
+                f[off + (long long)jz * g.npl + p] = (real)(P * exp(-(dx * dx + vy * vy) / T) * zfactor(g, jz, 0.0, T));
+                continue;
+            }
             const double vz = vnode(g, 2, jz);
             f[off + (long long)jz * g.npl + p] = (real)(P * exp(-(dx * dx + vy * vy + vz * vz) / T));
         }

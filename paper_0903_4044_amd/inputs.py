@@ -28,6 +28,8 @@ density in n_r, length in the domain unit, time in length / sqrt(2 R T_r)):
     maxwellian 'point' (Eq. Maxw at the cell's moments) or 'conservative'
                (Eq. Maxw at the effective parameters whose grid moments are the
                cell's, Sec. 2.1, the remark after Eq. exact)
+    reduced    True: two-dimensional kinds with v_z integrated out (nv[2] = 2,
+               planes g = int f dv_z and h = int v_z^2 f dv_z)
     steps      number of time steps of the workload
     precision  'fp64' or 'fp32' (storage/streaming precision of f)
 """

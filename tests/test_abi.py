@@ -106,3 +106,16 @@ def test_maxwellian_form_rules(B):
     assert B.load().bgk_init(arr, 1, 0, ctypes.byref(h)) == B.E_INVALID
     assert not h.value
     assert "Maxwellian" in B.load().bgk_last_error(None).decode()
+
+
+def test_reduced_velocity_space_rules(B):
+    """Reduced velocity space: two-dimensional kinds with nv[2] = 2 only, the
+    same for every instance of a context."""
+    cav = inputs.config("cavity_64_adjoint", nv=(24, 24, 2), reduced=True)
+    assert init_code(B, dict(cav, nv=(24, 24, 4)))[0] == B.E_UNSUPPORTED
+    shock = inputs.config("shock_m1.5_fp64", nv=(32, 32, 2), reduced=True)
+    assert init_code(B, shock)[0] == B.E_UNSUPPORTED
+    h = ctypes.c_void_p()
+    mixed = (B.Problem * 2)(B.to_struct(cav), B.to_struct(dict(cav, reduced=False)))
+    assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED
+    assert not h.value

@@ -1,0 +1,105 @@
+"""GPU parity of the reduced velocity space (two-dimensional problems with v_z
+integrated out: planes g = int f dv_z and h = int v_z^2 f dv_z, the
+projection the paper cites in Sec. 3 and Sec. 6) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0903_4044_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_0903_4044_amd import binding
+    binding.load()
+    return binding
+
+
+def reduced(kind, **kw):
+    d = dict(kind=kind, nx=13, ny=10, x0=0.0, x1=1.0, y0=0.0, y1=1.0, nv=(20, 16, 2), vlo=(-3.0, -3.0, -1.0),
+             vhi=(3.0, 3.0, 1.0), kn=0.3, omega=0.5, cfl=0.5, dt=0.0, mach=0.0, lid_mach=0.3, t_wall=1.1,
+             splitting="strang", limiter="minmod", maxwellian="point", reduced=True)
+    d.update(kw)
+    return d
+
+
+def dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=dtype, device="cuda")
+
+
+def perturbed(O, seed):
+    return O.initial_state() * (1 + 0.2 * inputs.uniform(O.shape, seed=seed, lo=-1, hi=1))
+
+
+@pytest.mark.parametrize("kind", ["cavity", "periodic2d"])
+@pytest.mark.parametrize("splitting,limiter", [("strang", "minmod"), ("lie", "none")])
+def test_reduced_matches_oracle_fp64(B, oracle_mod, kind, splitting, limiter):
+    cfg = reduced(kind, splitting=splitting, limiter=limiter)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 101)
+    ref = O.step(f0, 5)
+    C = B.Context(cfg, "fp64", tune="off")
+    ran = 0
+    for vsplit in (1, 2):
+        for unroll in (1, 2, 3, 4):
+            try:
+                C.set_launch(1, unroll, vsplit, 0)
+            except B.BGKError:
+                continue
+            y = C.step(dev(f0, torch.float64), n=5).cpu().numpy().reshape(O.shape)
+            np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max(), err_msg=str((vsplit, unroll)))
+            ran += 1
+    assert ran >= 4
+    np.testing.assert_allclose(C.moments(dev(ref, torch.float64)).cpu().numpy(), O.moments(ref), rtol=1e-12,
+                               atol=1e-14)
+
+
+def test_reduced_matches_oracle_fp32(B, oracle_mod):
+    cfg = reduced("cavity")
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 102)
+    ref = O.step(f0, 20)
+    C = B.Context(cfg, "fp32", tune="off")
+    got = C.moments(C.step(dev(f0, torch.float32), n=20)).cpu().numpy()
+    want = O.moments(ref)
+    en = np.max(np.abs(got[:, 0] - want[:, 0]) / want[:, 0])
+    eV = np.max(np.abs(got[:, 1:3] - want[:, 1:3])) / (0.3 * (5 / 6) ** 0.5)
+    eT = np.max(np.abs(got[:, 4] - want[:, 4]) / want[:, 4])
+    assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+def test_reduced_initial_state_and_metrics(B, oracle_mod):
+    """Initial state (the reduced rest Maxwellian pair) and the cavity metrics
+    after a short run, against the oracle."""
+    cfg = reduced("cavity", nx=12, ny=11)
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp64", tune="off")
+    x = C.initial_state()
+    np.testing.assert_allclose(x.cpu().numpy().reshape(O.shape), O.initial_state(), rtol=1e-14, atol=0)
+    f = O.step(O.initial_state(), 50)
+    np.testing.assert_allclose(C.cavity_metrics(dev(f, torch.float64))[0], O.cavity_metrics(f), rtol=1e-12)
+    y = C.step(x, n=50)
+    np.testing.assert_allclose(C.cavity_metrics(y)[0], O.cavity_metrics(f), rtol=1e-11)
+
+
+def test_reduced_adjoint_refused(B, oracle_mod):
+    C = B.Context(reduced("cavity"), "fp64", tune="off")
+    x = C.initial_state()
+    with pytest.raises(B.BGKError) as ei:
+        C.step_adjoint(x, torch.zeros_like(x))
+    assert ei.value.code == B.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kind", ["cavity", "periodic2d"])
+def test_reduced_conservative_matches_oracle(B, oracle_mod, kind):
+    """The conservative Maxwellian in the reduced space (v_z variance T~/2
+    exactly): FP64 parity with the oracle."""
+    cfg = reduced(kind, maxwellian="conservative")
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 103)
+    ref = O.step(f0, 4)
+    C = B.Context(cfg, "fp64", tune="off")
+    y = C.step(dev(f0, torch.float64), n=4).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())

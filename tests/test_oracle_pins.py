@@ -593,6 +593,27 @@ def test_reduced_model_is_the_projection_of_the_full_one(oracle_mod, kind, split
     np.testing.assert_allclose(R.moments(got), F.moments(F.step(f0, 3)), rtol=1e-11, atol=1e-13)
 
 
+def test_reduced_effective_parameters_and_conservation(oracle_mod):
+    """Conservative Maxwellian in the reduced space: the effective parameters
+    of a sampled reduced Maxwellian's grid moments are its parameters, and a
+    periodic run conserves mass, momentum and energy to rounding (the point
+    form drifts)."""
+    cfg = prob(kind="periodic2d", nx=3, ny=3, nv=(8, 8, 2), vlo=(-3, -3, -1), vhi=(3, 3, 1), kn=0.3,
+               reduced=True, maxwellian="conservative")
+    O, P = oracle_mod.Oracle(cfg), oracle_mod.Oracle(dict(cfg, maxwellian="point"))
+    phi = O.maxwellian(1.3, np.array([0.3, -0.2, 0.0]), 0.8)
+    m = O.moments(np.tile(phi, (O.ncell, 1)))[0]
+    assert np.max(np.abs(m - [1.3, 0.3, -0.2, 0.0, 0.8])) > 1e-5
+    q, it = O.effective_parameters(m[0], m[1:4], m[4])
+    np.testing.assert_allclose(q, [1.3, 0.3, -0.2, 0.0, 0.8], rtol=0, atol=2e-14)
+    assert it <= 6
+    f = np.tile(O.maxwellian(1.0, np.array([0.2, 0.0, 0.0]), 1.0), (O.ncell, 1))
+    f *= 1 + 0.4 * inputs.uniform(O.shape, seed=43, lo=-1, hi=1)
+    t0 = O.totals(f)[:5]
+    np.testing.assert_allclose(O.totals(O.step(f, 6))[:5], t0, rtol=1e-13, atol=1e-14)
+    assert abs(P.totals(P.step(f, 6))[4] - t0[4]) > 1e-7 * abs(t0[4])
+
+
 # ------------------------------------------------------------------ twin
 
 
