@@ -159,3 +159,20 @@ def test_adjoint_refused(B, oracle_mod):
     with pytest.raises(B.BGKError) as ei:
         C.step_adjoint(f0, torch.zeros_like(f0))
     assert ei.value.code == B.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("over", [dict(kind="cavity", nx=1, ny=1),
+                                  dict(kind="shock", nx=5, nv=(128, 6, 4), vlo=(-5.0, -3.0, -3.0),
+                                       vhi=(6.0, 3.0, 3.0))])
+def test_conservative_edge_sizes(B, oracle_mod, over):
+    """A one-cell cavity and a 128-node velocity axis (two table slots per
+    lane in the Newton solve)."""
+    over = dict(over)
+    kind = over.pop("kind")
+    cfg = small(kind, **over)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 95)
+    ref = O.step(f0, 3)
+    C = B.Context(cfg, "fp64", tune="off")
+    y = C.step(dev(f0, torch.float64), n=3).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())

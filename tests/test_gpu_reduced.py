@@ -103,3 +103,34 @@ def test_reduced_conservative_matches_oracle(B, oracle_mod, kind):
     C = B.Context(cfg, "fp64", tune="off")
     y = C.step(dev(f0, torch.float64), n=4).cpu().numpy().reshape(O.shape)
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("over", [dict(nx=1, ny=1), dict(kind="periodic2d", nx=2, ny=2, nv=(128, 128, 2),
+                                                         vlo=(-6.0, -6.0, -1.0), vhi=(6.0, 6.0, 1.0))])
+def test_reduced_edge_sizes(B, oracle_mod, over):
+    """A one-cell cavity (every face a wall) and the largest velocity axes
+    (128 nodes: two table slots per lane in k_prep)."""
+    cfg = reduced(over.get("kind", "cavity"), **{k: v for k, v in over.items() if k != "kind"})
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 104)
+    ref = O.step(f0, 3)
+    C = B.Context(cfg, "fp64", tune="off")
+    y = C.step(dev(f0, torch.float64), n=3).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_reduced_batch_of_cavities(B, oracle_mod):
+    """Cavities of uneven size in one context, each matching its own oracle."""
+    probs = [reduced("cavity", nx=7, ny=5, kn=0.2), reduced("cavity", nx=12, ny=9, lid_mach=0.1)]
+    C = B.Context(probs, "fp64", tune="off")
+    f = C.empty()
+    refs = []
+    for i, p in enumerate(probs):
+        O = oracle_mod.Oracle(p)
+        f0 = perturbed(O, 105 + i)
+        C.instance_view(f, i).copy_(torch.from_numpy(f0))
+        refs.append(O.step(f0, 4))
+    y = C.step(f, n=4)
+    for i, ref in enumerate(refs):
+        got = C.instance_view(y, i).cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
