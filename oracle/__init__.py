@@ -118,8 +118,9 @@ def make_problem(cfg: dict) -> Problem:
     p.minmod = {"minmod": 1, "none": 0, "shift": 2}[cfg.get("limiter", "minmod")]
     p.conservative = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
     p.reduced = 1 if cfg.get("reduced", False) else 0
-    if p.reduced and (cfg["kind"] not in ("cavity", "periodic2d") or int(cfg["nv"][2]) != 2):
-        raise ValueError("the reduced velocity space takes two-dimensional kinds and nv[2] = 2")
+    two = cfg["kind"] in ("cavity", "periodic2d")
+    if p.reduced and (int(cfg["nv"][2]) != 2 or (not two and int(cfg["nv"][1]) != 1)):
+        raise ValueError("the reduced velocity space takes nv[2] = 2 (and nv[1] = 1 for one-dimensional kinds)")
     return p
 
 

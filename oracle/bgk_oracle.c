@@ -72,8 +72,11 @@ typedef struct {
     int strang; /* 1: R_{dt/2} S R_{dt/2}; 0: R_dt S (Lie) */
     int minmod; /* 1: minmod slopes; 0: first-order upwind; 2: shift + first-order upwind */
     int conservative; /* 1: relaxations use the effective Maxwellian parameters */
-    int reduced; /* 1: two-dimensional kinds with v_z integrated out: plane jz = 0 holds
-                    g = int f dv_z, plane jz = 1 holds h = int v_z^2 f dv_z (nv[2] = 2) */
+    int reduced; /* 1: the velocity components the problem does not stream along are
+                    integrated out: v_z for two-dimensional kinds (nv[2] = 2; plane jz = 0
+                    holds g = int f dv_z, plane 1 h = int v_z^2 f dv_z), v_y and v_z for
+                    one-dimensional kinds (nv[1] = 1, nv[2] = 2; g = int f dv_y dv_z,
+                    h = int (v_y^2 + v_z^2) f dv_y dv_z) */
 } orc_problem;
 
 static const double GAMMA = 5.0 / 3.0;
@@ -83,9 +86,13 @@ static const double GAMMA = 5.0 / 3.0;
 static int is2d(const orc_problem *p) { return p->kind == ORC_CAVITY || p->kind == ORC_PERIODIC2; }
 static long ncell(const orc_problem *p) { return (long)p->nx * (is2d(p) ? p->ny : 1); }
 static long nvel(const orc_problem *p) { return (long)p->nv[0] * p->nv[1] * p->nv[2]; }
+/* number of velocity components integrated out (0: full velocity space) */
+static int nred(const orc_problem *p) { return p->reduced ? (is2d(p) ? 1 : 2) : 0; }
+
 static double dvel(const orc_problem *p, int a)
 {
-    if (a == 2 && p->reduced) return 1.0; /* the two planes are integrals over v_z */
+    if (a == 2 && nred(p) >= 1) return 1.0; /* the two planes are integrals over v_z */
+    if (a == 1 && nred(p) == 2) return 1.0; /* and over v_y */
     return (p->vhi[a] - p->vlo[a]) / p->nv[a];
 }
 static double dvol(const orc_problem *p) { return dvel(p, 0) * dvel(p, 1) * dvel(p, 2); }
@@ -99,13 +106,13 @@ static double dys(const orc_problem *p) { return (p->y1 - p->y0) / p->ny; }
  * Reduced (v_z integrated out, the projection the paper cites in Sec. 3 and
  * Sec. 6): v_z = 0 on both planes; the g plane has m = 1, e = 0 and the h
  * plane m = 0, e = 1 (h already is the v_z^2 moment). */
-typedef struct { double *vx, *vy, *vz, *m, *e; long nv; int reduced; } velgrid;
+typedef struct { double *vx, *vy, *vz, *m, *e; long nv; int reduced; } velgrid; /* reduced: components out */
 
 static velgrid make_velgrid(const orc_problem *p)
 {
     velgrid g;
     g.nv = nvel(p);
-    g.reduced = p->reduced;
+    g.reduced = nred(p);
     g.vx = malloc(sizeof(double) * g.nv);
     g.vy = malloc(sizeof(double) * g.nv);
     g.vz = malloc(sizeof(double) * g.nv);
@@ -116,7 +123,7 @@ static velgrid make_velgrid(const orc_problem *p)
             for (int jx = 0; jx < p->nv[0]; ++jx) {
                 long j = ((long)jz * p->nv[1] + jy) * p->nv[0] + jx;
                 g.vx[j] = p->vlo[0] + (jx + 0.5) * dvel(p, 0);
-                g.vy[j] = p->vlo[1] + (jy + 0.5) * dvel(p, 1);
+                g.vy[j] = nred(p) == 2 ? 0.0 : p->vlo[1] + (jy + 0.5) * dvel(p, 1);
                 if (p->reduced) {
                     g.vz[j] = 0.0;
                     g.m[j] = jz == 0 ? 1.0 : 0.0;
@@ -162,16 +169,20 @@ double orc_dt(const orc_problem *p)
 /* ------------------------------------------------------------- physics */
 
 /* Local Maxwellian, Eq. (Maxw), in normalised units. */
-/* Reduced velocity space: the v_z integrals of Eq. (Maxw),
- *   int Phi dv_z = n (pi T)^-1 exp(-((v_x - V_x)^2 + (v_y - V_y)^2) / T),
- *   int v_z^2 Phi dv_z = (T / 2) times that  (V_z = 0). */
+/* Reduced velocity space: the integrals of Eq. (Maxw) over the components
+ * taken out (V = 0 along them),
+ *   over v_z:      int Phi dv_z = n (pi T)^-1 exp(-((v_x - V_x)^2 + (v_y - V_y)^2) / T),
+ *                  int v_z^2 Phi dv_z = (T / 2) times that;
+ *   over v_y, v_z: int Phi = n (pi T)^-1/2 exp(-(v_x - V_x)^2 / T),
+ *                  int (v_y^2 + v_z^2) Phi = T times that. */
 static void maxwellian_on(const velgrid *g, double n, const double V[3], double T, double *phi)
 {
     if (g->reduced) {
-        double pre = n / (M_PI * T);
+        const double pre = g->reduced == 1 ? n / (M_PI * T) : n / sqrt(M_PI * T);
+        const double hfac = g->reduced == 1 ? 0.5 * T : T;
         for (long j = 0; j < g->nv; ++j) {
             double cx = g->vx[j] - V[0], cy = g->vy[j] - V[1];
-            phi[j] = pre * exp(-(cx * cx + cy * cy) / T) * (g->m[j] != 0.0 ? 1.0 : 0.5 * T);
+            phi[j] = pre * exp(-(cx * cx + cy * cy) / T) * (g->m[j] != 0.0 ? 1.0 : hfac);
         }
         return;
     }
@@ -310,17 +321,19 @@ static int effective_parameters(const velgrid *g, double dV, double n, const dou
             dM[4] = 2.0 / 3.0 * dV * (m * cd2 + g->e[j] - 1.5 * Td * m) / nd;
             dP[0] = phi[j] / q[0];
             for (int a = 0; a < 3; ++a) dP[1 + a] = phi[j] * 2.0 * (v[a] - q[1 + a]) / q[4];
-            /* T~ enters the prefactor as T~^(-3/2); in the reduced space as
-             * T~^(-1) on the g plane and T~^0 on the h plane (h = (T~/2) g) */
-            const double k = g->reduced ? (m != 0.0 ? 1.0 : 0.0) : 1.5;
+            /* T~ enters the prefactor as T~^(-3/2); in the reduced spaces as
+             * T~^(-1) (g) and T~^0 (h = (T~/2) g) with v_z out, T~^(-1/2)
+             * (g) and T~^(1/2) (h = T~ g) with v_y and v_z out */
+            const double k = g->reduced == 1 ? (m != 0.0 ? 1.0 : 0.0)
+                           : g->reduced == 2 ? (m != 0.0 ? 0.5 : -0.5) : 1.5;
             dP[4] = phi[j] * (ct2 / (q[4] * q[4]) - k / q[4]);
             for (int row = 0; row < 5; ++row)
                 for (int col = 0; col < 5; ++col) J[row][col] += dM[row] * dP[col];
         }
-        if (g->reduced) { /* V_z = 0 is not an unknown there */
-            for (int k = 0; k < 5; ++k) J[3][k] = J[k][3] = 0.0;
-            J[3][3] = 1.0;
-            r[3] = 0.0;
+        for (int a = 3 - g->reduced; a < 3 && g->reduced; ++a) { /* V = 0 along the components out */
+            for (int k = 0; k < 5; ++k) J[1 + a][k] = J[k][1 + a] = 0.0;
+            J[1 + a][1 + a] = 1.0;
+            r[1 + a] = 0.0;
         }
         if (solve5(J, r) != 0) break;
         for (int k = 0; k < 5; ++k) q[k] -= r[k];

@@ -614,6 +614,61 @@ def test_reduced_effective_parameters_and_conservation(oracle_mod):
     assert abs(P.totals(P.step(f, 6))[4] - t0[4]) > 1e-7 * abs(t0[4])
 
 
+@pytest.mark.parametrize("kind,limiter,cfl", [("shock", "none", 0.5), ("periodic1d", "none", 0.5),
+                                               ("shock", "shift", 3.3)])
+@pytest.mark.parametrize("splitting", ["strang", "lie"])
+def test_reduced_1d_model_is_the_projection_of_the_full_one(oracle_mod, kind, limiter, cfl, splitting):
+    """One-dimensional problems with v_y and v_z integrated out (g = int f,
+    h = int (v_y^2 + v_z^2) f over both): with linear streaming (first-order
+    upwind or its translation form) stepping the full model on resolving
+    (v_y, v_z) grids (32 nodes on [-8, 8]) and projecting equals stepping the
+    projected state."""
+    common = dict(kind=kind, nx=7, x0=-1.0 if kind == "shock" else 0.0, kn=0.4, mach=1.5, cfl=cfl,
+                  splitting=splitting, limiter=limiter, omega=0.74)
+    full = prob(nv=(8, 32, 32), vlo=(-4, -8, -8), vhi=(5, 8, 8), **common)
+    red = prob(nv=(8, 1, 2), vlo=(-4, -1, -1), vhi=(5, 1, 1), reduced=True, **common)
+    F, R = oracle_mod.Oracle(full), oracle_mod.Oracle(red)
+    xi = inputs.uniform((F.ncell, 1, 1, 8), seed=62, lo=-1, hi=1)
+    f0 = (F.initial_state().reshape(F.ncell, 32, 32, 8) * (1 + 0.3 * xi)).reshape(F.shape)
+    _, vy, vz = (v.reshape(32, 32, 8)[:, :, 0] for v in F.velocity_nodes())
+    dA = 0.5 * 0.5
+
+    def project(f):
+        f = f.reshape(-1, 32, 32, 8)
+        g = f.sum(axis=(1, 2)) * dA
+        h = (f * (vy ** 2 + vz ** 2)[None, :, :, None]).sum(axis=(1, 2)) * dA
+        return np.concatenate([g, h], axis=1)
+
+    got = R.step(project(f0), 3)
+    want = project(F.step(f0, 3))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_reduced_1d_maxwellian_and_effective_parameters(oracle_mod):
+    """The 1D reduced Maxwellian pair (h = T g) has the moments of its
+    parameters on a resolving grid; on a coarse one the effective parameters
+    of a sampled pair's moments are its parameters."""
+    fine = prob(kind="periodic1d", nx=2, nv=(60, 1, 2), vlo=(-9, -1, -1), vhi=(9, 1, 1), reduced=True)
+    O = oracle_mod.Oracle(fine)
+    phi = O.maxwellian(1.7, np.array([0.6, 0.0, 0.0]), 1.3)
+    np.testing.assert_allclose(phi[60:], 1.3 * phi[:60], rtol=1e-15)
+    np.testing.assert_allclose(O.moments(np.tile(phi, (2, 1)))[0], [1.7, 0.6, 0, 0, 1.3], rtol=1e-11, atol=1e-13)
+    coarse = prob(kind="periodic1d", nx=2, nv=(8, 1, 2), vlo=(-3, -1, -1), vhi=(3, 1, 1), reduced=True,
+                  maxwellian="conservative")
+    C = oracle_mod.Oracle(coarse)
+    phi = C.maxwellian(1.1, np.array([0.4, 0.0, 0.0]), 0.9)
+    m = C.moments(np.tile(phi, (2, 1)))[0]
+    assert np.max(np.abs(m - [1.1, 0.4, 0, 0, 0.9])) > 1e-5
+    q, it = C.effective_parameters(m[0], m[1:4], m[4])
+    np.testing.assert_allclose(q, [1.1, 0.4, 0, 0, 0.9], rtol=0, atol=2e-14)
+    assert it <= 6
+    # quadratic convergence from defects near 1e-2 (6 nodes on [-2.5, 2.5]):
+    # at most 5 steps with the exact Jacobian, 6 with a slipped T~ exponent
+    V = oracle_mod.Oracle(dict(coarse, nv=(6, 1, 2), vlo=(-2.5, -1, -1), vhi=(2.5, 1, 1)))
+    for v, T, most in [(0.5, 1.0, 5), (-0.7, 0.6, 4), (0.0, 1.5, 5)]:
+        assert V.effective_parameters(1.0, np.array([v, 0.0, 0.0]), T)[1] <= most
+
+
 # ------------------------------------------------------------------ twin
 
 
