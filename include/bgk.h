@@ -102,13 +102,17 @@ typedef struct bgk_problem {
     int limiter;            /* BGK_MINMOD, BGK_NOLIMIT or BGK_SHIFT (all instances of a context
                                use BGK_SHIFT or none does) */
     int maxwellian;         /* BGK_POINT or BGK_CONSERVATIVE (per instance) */
-    int reduced;            /* 1: velocity space with v_z integrated out (the projection the paper
-                               cites in Sec. 3 and Sec. 6), two-dimensional kinds with nv[2] = 2:
+    int reduced;            /* 1: reduced velocity space (the projection the paper cites in
+                               Sec. 3 and Sec. 6): the components the problem does not stream
+                               along are integrated out.  Two-dimensional kinds: nv[2] = 2,
                                plane jz = 0 of f holds g = int f dv_z and plane 1
-                               h = int v_z^2 f dv_z on the (v_x, v_y) grid, the v_z integrals of
-                               Eq. (Maxw) are exact and V_z = 0; vlo[2], vhi[2] are ignored; the
-                               minmod limiter acts on g and h separately.  0: full velocity space.
-                               The same for all instances of a context.  No reverse sweep. */
+                               h = int v_z^2 f dv_z on the (v_x, v_y) grid.  One-dimensional
+                               kinds: nv[1] = 1, nv[2] = 2, g = int f dv_y dv_z and
+                               h = int (v_y^2 + v_z^2) f dv_y dv_z on the v_x grid.  V = 0 along
+                               the components out and the integrals of Eq. (Maxw) are exact;
+                               their vlo, vhi are ignored; the minmod limiter acts on g and h
+                               separately.  0: full velocity space.  The same for all instances
+                               of a context.  No reverse sweep. */
 } bgk_problem;
 
 typedef struct bgk_ctx bgk_ctx;

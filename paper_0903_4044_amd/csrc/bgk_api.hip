@@ -176,6 +176,7 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (p.kind == BGK_PERIODIC_2D && (p.nx < 2 || p.ny < 2)) return bad("periodic boxes need nx, ny >= 2");
     if (!(p.x1 > p.x0) || (two && !(p.y1 > p.y0))) return bad("empty spatial box");
     for (int a = 0; a < 3; ++a) {
+        if (a == 1 && p.reduced && !two && p.nv[1] == 1) continue;  // the single node v_y = 0
         if (p.nv[a] < 2 || p.nv[a] > NVMAX) {
             msg = "velocity cells per component must be in [2, 128]";
             return BGK_E_UNSUPPORTED;
@@ -188,9 +189,9 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT && p.limiter != BGK_SHIFT) return bad("unknown limiter");
     if (p.maxwellian != BGK_POINT && p.maxwellian != BGK_CONSERVATIVE) return bad("unknown Maxwellian form");
     if (p.reduced != 0 && p.reduced != 1) return bad("reduced must be 0 or 1");
-    if (p.reduced && (!two || p.nv[2] != 2)) {
-        snprintf(b, sizeof b, "problem %d: the reduced velocity space takes two-dimensional kinds and nv[2] = 2",
-                 idx);
+    if (p.reduced && (p.nv[2] != 2 || (!two && p.nv[1] != 1))) {
+        snprintf(b, sizeof b, "problem %d: the reduced velocity space takes nv[2] = 2 (and nv[1] = 1 for "
+                              "one-dimensional kinds)", idx);
         msg = b;
         return BGK_E_UNSUPPORTED;
     }
@@ -331,12 +332,16 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     g.npl = g.nvx * g.nvy;
     g.nv = (long long)g.npl * g.nvz;
     g.dV = 1.0;
-    g.red = probs[0].reduced ? 1 : 0;
+    g.red = probs[0].reduced ? (is2d_kind(probs[0].kind) ? 1 : 2) : 0;
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = probs[0].vlo[a];
         g.dv[a] = (probs[0].vhi[a] - probs[0].vlo[a]) / probs[0].nv[a];
-        if (a == 2 && g.red) {  // the two planes are integrals over v_z
+        if (a == 2 && g.red) {  // the two planes are integrals over v_z (and v_y)
             g.lo[a] = 0.0;
+            g.dv[a] = 1.0;
+        }
+        if (a == 1 && g.red == 2) {  // the single node v_y = 0
+            g.lo[a] = -0.5;
             g.dv[a] = 1.0;
         }
         g.dV *= g.dv[a];

@@ -59,7 +59,7 @@ struct Geo {
     long long nv;               // nvx * nvy * nvz
     double lo[3], dv[3];
     double dV;
-    int red;                    // 1: v_z integrated out (plane 0 g = int f dv_z, plane 1 h = int v_z^2 f dv_z)
+    int red;                    // components integrated out: 1 v_z (2D kinds), 2 v_y and v_z (1D kinds)
     int pe;                     // params entry stride (elements)
     int tx1, ty1, tx2, ty2, tz; // entry offsets
 };
@@ -127,9 +127,12 @@ __device__ __forceinline__ int strip_cell(const Inst &I, int q)
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
 
 // The v_z axis.  Full velocity space: nodes v_z(k).  Reduced velocity space
-// (two-dimensional problems, the projection the paper cites in Sec. 3 and
-// Sec. 6): plane 0 holds g = int f dv_z and plane 1 h = int v_z^2 f dv_z, so
-// V_z = 0 and the v_z integrals of Eq. (Maxw) are exact.  Per plane: its
+// (the projection the paper cites in Sec. 3 and Sec. 6): the components a
+// problem does not stream along are integrated out, v_z for two-dimensional
+// problems (plane 0 holds g = int f dv_z, plane 1 h = int v_z^2 f dv_z) and
+// v_y, v_z for one-dimensional ones (g = int f dv_y dv_z, h = int (v_y^2 +
+// v_z^2) f dv_y dv_z, and the v_y axis is the single node v_y = 0), so V = 0
+// along them and the integrals of Eq. (Maxw) are exact.  Per plane: its
 // share m in mass and momentum, its v_z and its energy term zz beyond
 // m |v|^2: (1, v_z, v_z^2) in full velocity space, (1, 0, 0) for g and
 // (0, 0, 1) for h.
@@ -143,9 +146,11 @@ __device__ __forceinline__ ZW zweights(const Geo &g, int k)
 }
 
 // The Maxwellian's factor on plane k: exp(-(v_z - V_z)^2 / T), or in reduced
-// velocity space the integrals sqrt(pi T) (g) and (T / 2) sqrt(pi T) (h).
+// velocity space the integrals over the components out: sqrt(pi T) (g) and
+// (T / 2) sqrt(pi T) (h) over v_z; pi T (g) and pi T^2 (h) over v_y, v_z.
 __device__ __forceinline__ double zfactor(const Geo &g, int k, double Vz, double T)
 {
+    if (g.red == 2) return k == 0 ? M_PI * T : M_PI * T * T;
     if (g.red) {
         const double s = sqrt(M_PI * T);
         return k == 0 ? s : 0.5 * T * s;
@@ -534,22 +539,27 @@ __device__ __forceinline__ void effective_tables(const Geo &g, Relax *r, Tables 
         double res[3], jvv[3], jvt[3], jtv[3], jtt = 0.0, rt = -r->T, s0[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            if (c == 2 && g.red) {
-                // reduced velocity space: h = (T~ / 2) g on every node, so the
-                // v_z variance is T~ / 2 exactly and V_z = 0 is no unknown
+            if ((c == 2 && g.red) || (c == 1 && g.red == 2)) {
+                // reduced velocity space: V = 0 along the components out is no
+                // unknown; h = (T~ / 2) g (v_z out) or h = T~ g (v_y, v_z out)
+                // on every node, so their share of the temperature is exact;
+                // a v_y axis taken out is the single node v_y = 0 (factor 1)
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int k = lane + W * q;
-                    t.e[c][q] = k < 2 ? zfactor(g, k, 0.0, Tt) : 0.0;
+                    t.e[c][q] = c == 1 ? (k == 0 ? 1.0 : 0.0) : (k < 2 ? zfactor(g, k, 0.0, Tt) : 0.0);
                 }
-                s0[c] = zfactor(g, 0, 0.0, Tt);
+                s0[c] = c == 1 ? 1.0 : zfactor(g, 0, 0.0, Tt);
                 if (done) continue;
                 res[c] = 0.0;
                 jvv[c] = 1.0;
                 jvt[c] = 0.0;
                 jtv[c] = 0.0;
-                jtt += 1.0 / 3.0;
-                rt += Tt / 3.0;
+                if (c == 2) {
+                    const double share = g.red == 2 ? 1.0 : 0.5;  // (h / g) / T~
+                    jtt += 2.0 / 3.0 * share;
+                    rt += 2.0 / 3.0 * share * Tt;
+                }
                 continue;
             }
             double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
@@ -1279,9 +1289,9 @@ __global__ void __launch_bounds__(256)
     __shared__ double vzt[NVMAX][2];
     const Geo &g = A.g;
     for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
-        const double vz = vnode(g, 2, k);
-        vzt[k][0] = vz;
-        vzt[k][1] = vz * vz;
+        const ZW w = zweights(g, k);  // as in k_stream: mass shares first when reduced
+        vzt[k][0] = g.red ? w.m : w.z;
+        vzt[k][1] = w.zz;
     }
     __syncthreads();
     const int nitems = A.ncells * A.vsplit;
@@ -1396,7 +1406,8 @@ __global__ void __launch_bounds__(256)
                     h[1] = hn[1];
                 }
             }
-            fold_column(acc, vx, vy, A0, Az, Azz);
+            if (g.red) fold_column(acc, vx, vy, Az, 0.0, Azz);
+            else fold_column(acc, vx, vy, A0, Az, Azz);
         }
         block_sum_store<NQ>(acc, partial + (long long)L * NQ);
         __syncthreads();
@@ -1465,7 +1476,11 @@ __global__ void __launch_bounds__(256) k_init(Args A, real *__restrict__ f)
     const int c = gc - I.cell0;
     double n = 1.0, V = 0.0, T = 1.0;
     if (I.kind == KIND_SHOCK) {
-        // Sec. 4.1: upstream state for x < 0, downstream state for x >= 0.
+#pragma clang fp contract(off)
+        // Sec. 4.1: upstream state for x < 0, downstream state for x >= 0.  The
+        // centre is rounded after the product and after the sum (no fused
+        // multiply-add), so a centre on x = 0 falls on the same side as in a
+        // plain evaluation.
         const double x = I.x0 + (c + 0.5) * I.dx;
         const double *st = x < 0.0 ? I.up : I.dn;
         n = st[0]; V = st[1]; T = st[2];

@@ -114,7 +114,8 @@ def test_reduced_velocity_space_rules(B):
     cav = inputs.config("cavity_64_adjoint", nv=(24, 24, 2), reduced=True)
     assert init_code(B, dict(cav, nv=(24, 24, 4)))[0] == B.E_UNSUPPORTED
     shock = inputs.config("shock_m1.5_fp64", nv=(32, 32, 2), reduced=True)
-    assert init_code(B, shock)[0] == B.E_UNSUPPORTED
+    assert init_code(B, shock)[0] == B.E_UNSUPPORTED  # one-dimensional kinds take nv[1] = 1
+    assert init_code(B, dict(shock, nv=(32, 1, 4)))[0] == B.E_UNSUPPORTED
     h = ctypes.c_void_p()
     mixed = (B.Problem * 2)(B.to_struct(cav), B.to_struct(dict(cav, reduced=False)))
     assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED

@@ -125,6 +125,19 @@ def test_initial_state_and_moments(B, oracle_mod):
         np.testing.assert_allclose(C.moments(f).cpu().numpy(), O.moments(ref), rtol=1e-12, atol=1e-13)
 
 
+@pytest.mark.parametrize("nx", [9, 15])
+def test_shock_initial_state_with_a_centre_on_zero(B, oracle_mod, nx):
+    """An odd cell count on a symmetric box puts the middle centre on x = 0
+    (rounded there without a fused multiply-add): it takes the downstream
+    state on the GPU as in the oracle."""
+    cfg = small("shock", nx=nx)
+    O = oracle_mod.Oracle(cfg)
+    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6)):
+        C = B.Context(cfg, prec, tune="off")
+        got = C.initial_state().double().cpu().numpy().reshape(O.shape)
+        np.testing.assert_allclose(got, O.initial_state(), rtol=tol, atol=0)
+
+
 def test_batched_matches_single_and_oracle(B, oracle_mod):
     """Uneven instances in one context: each equals its own oracle run and
     its own single-instance context bit for bit."""

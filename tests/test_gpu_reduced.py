@@ -134,3 +134,47 @@ def test_reduced_batch_of_cavities(B, oracle_mod):
     for i, ref in enumerate(refs):
         got = C.instance_view(y, i).cpu().numpy()
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def reduced_1d(kind, **kw):
+    d = dict(kind=kind, nx=15, ny=1, x0=-2.0 if kind == "shock" else 0.0, x1=2.0 if kind == "shock" else 1.0,
+             y0=0.0, y1=1.0, nv=(24, 1, 2), vlo=(-4.0, -1.0, -1.0), vhi=(5.0, 1.0, 1.0), kn=0.3, omega=0.74,
+             cfl=0.5, dt=0.0, mach=1.5, lid_mach=0.0, t_wall=1.0, splitting="strang", limiter="minmod",
+             maxwellian="point", reduced=True)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kind", ["shock", "periodic1d"])
+@pytest.mark.parametrize("over", [dict(), dict(splitting="lie", limiter="none"),
+                                  dict(splitting="lie", limiter="shift", cfl=3.3),
+                                  dict(maxwellian="conservative"),
+                                  dict(splitting="lie", limiter="shift", cfl=3.3, maxwellian="conservative")])
+def test_reduced_1d_matches_oracle(B, oracle_mod, kind, over):
+    """One-dimensional problems with v_y and v_z integrated out (g and h on
+    the v_x grid): per-cell and translation-form streaming, point and
+    conservative Maxwellians, FP64 to 1e-12 and FP32 moments to 1e-5."""
+    cfg = reduced_1d(kind, **over)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 106)
+    ref = O.step(f0, 6)
+    C = B.Context(cfg, "fp64", tune="off")
+    y = C.step(dev(f0, torch.float64), n=6).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    C32 = B.Context(cfg, "fp32", tune="off")
+    got = C32.moments(C32.step(dev(f0, torch.float32), n=6)).cpu().numpy()
+    want = O.moments(ref)
+    en = np.max(np.abs(got[:, 0] - want[:, 0]) / want[:, 0])
+    eV = np.max(np.abs(got[:, 1] - want[:, 1])) / 1.4
+    eT = np.max(np.abs(got[:, 4] - want[:, 4]) / want[:, 4])
+    assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+def test_reduced_1d_initial_state(B, oracle_mod):
+    """The reduced far-field pair on each side; with an odd cell count the
+    middle centre lies on x = 0 and takes the downstream state on both sides."""
+    cfg = reduced_1d("shock")
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, "fp64", tune="off")
+    np.testing.assert_allclose(C.initial_state().cpu().numpy().reshape(O.shape), O.initial_state(), rtol=1e-14,
+                               atol=0)
