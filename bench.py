@@ -331,14 +331,20 @@ def main():
                 ("shock_m3_fp32_conservative", [inputs.config("shock_m3_fp32_conservative")], "fp32", 500, 20,
                  False),
                 ("cavity_128_fp32_conservative", [inputs.config("cavity_128_fp32_conservative")], "fp32", 200, 10,
-                 False)]
+                 False),
+                # the paper's shock runs with v_y and v_z integrated out (16 x 2 and 30 x 2 values per cell)
+                ("shock_m1.5_paper_fp32_reduced", [inputs.config("shock_m1.5_paper_reduced")], "fp32", 400, 20,
+                 False),
+                ("shock_m3_paper_fp32_reduced", [inputs.config("shock_m3_paper_reduced")], "fp32", 200, 10, False)]
         wanted = set(x for x in args.extras.split(",") if x)
         for name, probs, p, steps, warm, graph in runs:
             if wanted and name not in wanted:
                 continue
             s, k, pts, shp = run_workload(binding, torch, probs, p, steps, warm, True, True, graph)
+            cells = sum(inputs.ncells(q) for q in probs)
             e = {"updates_per_s": pts * steps / s, "ns_per_update": s / (pts * steps) * 1e9, "steps": steps,
-                 "points": pts, "launch": shp, "precision": p, "graph": graph}
+                 "points": pts, "cell_steps_per_s": cells * steps / s, "launch": shp, "precision": p,
+                 "graph": graph}
             if k == k:  # timed kernels (not NaN)
                 a = bytes_per_update(p) * pts / (k * 1e-3) / 1e9
                 e.update({"kernel_ms": k, "achieved_GBs": a, "frac": a / PEAK_HBM_GBS})

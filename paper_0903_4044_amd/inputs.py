@@ -91,6 +91,16 @@ CONFIGS = {
                                           vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
                                           lid_mach=0.1, t_wall=1.0, steps=5000,
                                           precision="fp32", maxwellian="conservative"),
+    # The paper's shock runs in the reduced velocity space (v_y, v_z
+    # integrated out: g and h on the v_x grid of the boxes above).
+    "shock_m1.5_paper_reduced": _base(kind="shock", nx=18432, x0=-35.0, x1=35.0,
+                                      nv=(16, 1, 2), vlo=(-5.0, -1.0, -1.0), vhi=(7.0, 1.0, 1.0),
+                                      kn=1.0, omega=0.74, dt=0.05, mach=1.5, splitting="lie",
+                                      limiter="shift", steps=400, precision="fp32", reduced=True),
+    "shock_m3_paper_reduced": _base(kind="shock", nx=18432, x0=-35.0, x1=35.0,
+                                    nv=(30, 1, 2), vlo=(-10.0, -1.0, -1.0), vhi=(12.0, 1.0, 1.0),
+                                    kn=1.0, omega=0.74, dt=0.05, mach=3.0, splitting="lie",
+                                    limiter="shift", steps=200, precision="fp32", reduced=True),
     # Adjoint workload: 64^2 cavity, 200 steps.
     "cavity_64_adjoint": _base(kind="cavity", nx=64, ny=64, nv=(24, 24, 24),
                                vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
