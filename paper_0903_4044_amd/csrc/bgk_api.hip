@@ -256,7 +256,14 @@ static void task_shape(const Geo &g, int vec, int zchunk, int *zr_out, int *bloc
         *zr_out = zr;
         for (int b = 256; b >= 64; b -= 64)
             if (t % b == 0) { *block_out = b; break; }
-        break;
+        return;
+    }
+    // reduced velocity space with planes of fewer than 64 lane groups (one-
+    // dimensional problems: N_vx values per plane): one wave per workgroup,
+    // filled with as many jz residues as the chunk has
+    if (g.red && groups < 64) {
+        *zr_out = std::max(1, std::min(zchunk, (64 + groups - 1) / groups));
+        *block_out = 64;
     }
 }
 
