@@ -420,11 +420,43 @@ __device__ __forceinline__ void finish_relax(const Inst &I, double tau, Relax *r
     r->P = r->n * pi_t_m32(r->T);
 }
 
-// Sum over the W-lane segment of the wave that holds this lane (butterfly).
+// A double from another lane of the same 16-lane row (DPP move of both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// A double from lane (this lane xor 16) within its 32-lane half (swizzle).
+__device__ __forceinline__ double swizzle_xor16(double x)
+{
+    constexpr int PAT = 0x1F | (0x10 << 10);  // bit mode: and 0x1F, or 0, xor 0x10
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, PAT);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), PAT);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the W-lane segment of the wave that holds this lane.  Pairs of
+// lanes exchange partial sums and add them, so every lane of the segment
+// ends with the same bits: swaps within quads (DPP quad permutations), then
+// quads (half-row mirror) and half rows (row mirror) of a 16-lane row, then
+// rows through a swizzle and across the two halves through a permute.  Lanes
+// beyond a segment's data hold zeros, so a segment's sum equals that of a
+// wider one.
 template <int W = 64>
 __device__ __forceinline__ double wave_sum(double x)
 {
-    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
+    static_assert(W == 16 || W == 32 || W == 64, "segments of 16, 32 or 64 lanes");
+    x += dpp_double<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_double<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_double<0x141>(x);  // row_half_mirror
+    x += dpp_double<0x140>(x);  // row_mirror
+    if constexpr (W >= 32) x += swizzle_xor16(x);
+    if constexpr (W == 64) x += __shfl_xor(x, 32, 64);
     return x;
 }
 
