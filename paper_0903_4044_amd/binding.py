@@ -187,7 +187,10 @@ class Context:
         if tune == "table":
             shape = load_tuned().get(self.key)
             if shape:
-                self.set_launch(shape["vec"], shape["unroll"], shape["vsplit"], shape.get("persist", 0))
+                try:  # a shape recorded for another streaming form of the same size class may not apply
+                    self.set_launch(shape["vec"], shape["unroll"], shape["vsplit"], shape.get("persist", 0))
+                except BGKError:
+                    pass
 
     def _check(self, rc):
         if rc != OK:

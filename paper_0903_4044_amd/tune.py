@@ -21,6 +21,12 @@ def workloads():
     yield "cavity_128_fp64", [inputs.config("cavity_128_fp32")], "fp64"
     yield "cavity_64_fp32", [inputs.config("cavity_64_adjoint")], "fp32"
     yield "batch_64_fp32", inputs.batch_cavities(), "fp32"
+    yield "shock_m1.5_paper_fp32", [inputs.config("shock_m1.5_paper")], "fp32"
+    yield "shock_m3_paper_fp32", [inputs.config("shock_m3_paper")], "fp32"
+    yield "shock_m1.5_paper_reduced_fp32", [inputs.config("shock_m1.5_paper_reduced")], "fp32"
+    yield "shock_m3_paper_reduced_fp32", [inputs.config("shock_m3_paper_reduced")], "fp32"
+    yield "table_cavity_160_fp32", [inputs.table_cavity(1.0)], "fp32"
+    yield "table_cavity_160_reduced_fp32", [inputs.table_cavity(1.0, nv=(20, 20, 2), reduced=True)], "fp32"
 
 
 def main() -> int:
