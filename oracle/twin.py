@@ -7,7 +7,9 @@ same passages of the paper: Eqs. (Maxw), (macroscopic), (frequency) of Sec. 2,
 the splitting and Eqs. (upwind), (relaxation) of Sec. 2.1, Eqs. (bc_shock),
 (RH) of Sec. 4.1 and Eq. (bc_cavity) of Sec. 5.1, with the same readings
 (minmod flux-form streaming, Strang or Lie composition, two ghost layers,
-discrete zero-mass-flux wall density, lid Mach number at T_r).
+discrete zero-mass-flux wall density, lid Mach number at T_r), and the same
+variants (translation-form streaming, effective Maxwellian parameters, the
+reduced velocity space).
 """
 from __future__ import annotations
 
@@ -33,9 +35,25 @@ class Twin:
             h = (hi - lo) / k
             axes.append(lo + h * (np.arange(k) + 0.5))
         self.dv = [(float(cfg["vhi"][a]) - float(cfg["vlo"][a])) / int(cfg["nv"][a]) for a in range(3)]
+        # reduced velocity space: the components the problem does not stream
+        # along are integrated out; the z axis then holds two planes, the
+        # integral g and the moment h of the transverse speed squared
+        self.out = (1 if self.two else 2) if cfg.get("reduced", False) else 0
+        if self.out:
+            axes[2] = np.zeros(2)
+            self.dv[2] = 1.0
+        if self.out == 2:
+            axes[1] = np.zeros(1)
+            self.dv[1] = 1.0
         self.dV = self.dv[0] * self.dv[1] * self.dv[2]
         # broadcastable velocity components over (jz, jy, jx)
         self.VZ, self.VY, self.VX = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        # per node: share in mass and momentum, extra energy term
+        self.W = np.ones_like(self.VX)
+        self.E = np.zeros_like(self.VX)
+        if self.out:
+            self.W[1] = 0.0
+            self.E[1] = 1.0
         self.dx = (float(cfg["x1"]) - float(cfg["x0"])) / self.nx
         self.dy = (float(cfg["y1"]) - float(cfg["y0"])) / self.ny if self.two else 1.0
         self.kn = float(cfg["kn"])
@@ -68,15 +86,21 @@ class Twin:
         c2 = ((self.VX - u[..., 0, None, None, None]) ** 2
               + (self.VY - u[..., 1, None, None, None]) ** 2
               + (self.VZ - u[..., 2, None, None, None]) ** 2)
+        if self.out:
+            # integrals over the components out of the Maxwellian (g) and of
+            # it times their speed squared (h = out * T / 2 times g)
+            g = n / (math.pi * T) ** (1.5 - 0.5 * self.out) * np.exp(-c2 / T)
+            return np.where(self.W > 0, g, 0.5 * self.out * T * g)
         return n / (math.pi * T) ** 1.5 * np.exp(-c2 / T)
 
     def macro(self, f5):
         ax = (-3, -2, -1)
-        n = f5.sum(axis=ax) * self.dV
-        u = np.stack([(f5 * V).sum(axis=ax) for V in (self.VX, self.VY, self.VZ)], -1) * self.dV / n[..., None]
+        mf = f5 * self.W
+        n = mf.sum(axis=ax) * self.dV
+        u = np.stack([(mf * V).sum(axis=ax) for V in (self.VX, self.VY, self.VZ)], -1) * self.dV / n[..., None]
         c2 = ((self.VX - u[..., 0, None, None, None]) ** 2 + (self.VY - u[..., 1, None, None, None]) ** 2
               + (self.VZ - u[..., 2, None, None, None]) ** 2)
-        T = (c2 * f5).sum(axis=ax) * self.dV / n * (2.0 / 3.0)
+        T = ((c2 * self.W + self.E) * f5).sum(axis=ax) * self.dV / n * (2.0 / 3.0)
         return n, u, T
 
     def effective(self, n, u, T):
@@ -89,13 +113,18 @@ class Twin:
 
         target = np.array([n, u[0], u[1], u[2], T], dtype=float)
         scale = np.array([n, math.sqrt(T), math.sqrt(T), math.sqrt(T), T])
+        free = [0, 1, 2, 3, 4] if not self.out else ([0, 1, 2, 4] if self.out == 1 else [0, 1, 4])
 
-        def resid(q):
+        def resid(x):
+            q = target.copy()
+            q[free] = x
             m = self.macro(self.maxwell(q[0], q[1:4], q[4]))
-            return (np.array([m[0], *m[1], m[2]]) - target) / scale
+            return ((np.array([m[0], *m[1], m[2]]) - target) / scale)[free]
 
-        sol = root(resid, target.copy(), method="hybr", options={"xtol": 1e-15})
-        return sol.x
+        sol = root(resid, target[free].copy(), method="hybr", options={"xtol": 1e-15})
+        q = target.copy()
+        q[free] = sol.x
+        return q
 
     def relax(self, f5, tau):
         n, u, T = self.macro(f5)
@@ -124,8 +153,8 @@ class Twin:
         phiw = self.maxwell(1.0, np.array([uw, 0.0, 0.0]), float(self.cfg["t_wall"]))
         out_mask = vn_inward > 0
         in_mask = vn_inward < 0
-        arrive = (np.where(in_mask, -vn_inward, 0.0) * g_adj).sum(axis=(-3, -2, -1))
-        leave = (np.where(out_mask, vn_inward, 0.0) * phiw).sum()
+        arrive = (np.where(in_mask, -vn_inward, 0.0) * self.W * g_adj).sum(axis=(-3, -2, -1))
+        leave = (np.where(out_mask, vn_inward, 0.0) * self.W * phiw).sum()
         nw = arrive / leave
         return np.where(out_mask, nw[..., None, None, None] * phiw, g_adj)
 
