@@ -778,6 +778,10 @@ void orc_cavity_metrics(const orc_problem *p, const double *f, double *out /* [2
 {
     const int nx = p->nx, ny = p->ny;
     const double uw = lid_speed(p), W = p->x1 - p->x0, H = p->y1 - p->y0, dy = H / ny;
+    if (p->kind != ORC_CAVITY || uw == 0.0) { /* defined for a cavity with a moving lid */
+        out[0] = out[1] = NAN;
+        return;
+    }
     out[0] = -orc_lid_shear(p, f) / (0.5 * uw * W);
     double *mom = malloc(sizeof(double) * 5 * ncell(p));
     double *u = malloc(sizeof(double) * ny);

@@ -530,6 +530,13 @@ def test_vortex_flow_rate_linear_profile(oracle_mod, nx):
         assert O.cavity_metrics(f)[1] == pytest.approx(s * (1 - a) ** 2, rel=1e-10)
 
 
+def test_cavity_metrics_undefined_elsewhere(oracle_mod):
+    """No lid motion or no cavity: D and G are NaN."""
+    for cfg in (metric_cfg(4, 4) | dict(lid_mach=0.0), prob(kind="periodic2d", nx=4, ny=4, nv=(8, 8, 4))):
+        O = oracle_mod.Oracle(cfg)
+        assert np.all(np.isnan(O.cavity_metrics(O.initial_state())))
+
+
 def test_vortex_flow_rate_takes_the_top_vortex(oracle_mod):
     """Two sign changes on the centre line: the integral starts at the upper
     zero (the main vortex's centre) and converges at second order in dy."""
