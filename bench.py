@@ -295,6 +295,7 @@ def main():
     bpu = bytes_per_update(prec)
     achieved = bpu * points / (kms * 1e-3) / 1e9
     traffic = read_traffic(args.workload)
+    kname = "k_shift" if cfg.get("limiter") == "shift" else "k_stream"  # the streaming kernel of this workload
     out = {
         "metric": "phase-space point updates/s",
         "value": value,
@@ -313,9 +314,9 @@ def main():
                    "moments": "f64", "launch": shape},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_stream", "kernel_ms": kms, "bytes_per_update": bpu},
+                     "kernel": kname, "kernel_ms": kms, "bytes_per_update": bpu},
     }
-    print(f"# {args.workload}: {value:.4g} updates/s, k_stream {kms * 1e3:.1f} us, "
+    print(f"# {args.workload}: {value:.4g} updates/s, {kname} {kms * 1e3:.1f} us, "
           f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
 
     if not args.no_extras:
