@@ -74,3 +74,34 @@ def test_autotune_keeps_parity(B, oracle_mod, name):
     ref = O.step(f0, 4)
     y = C.step(x, n=4).cpu().numpy().reshape(O.shape)
     np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def run_batch(B, oracle_mod, probs, nsteps, seed):
+    C = B.Context(probs, "fp64", tune="off")
+    f = C.empty()
+    refs = []
+    for i, p in enumerate(probs):
+        O = oracle_mod.Oracle(p)
+        f0 = O.initial_state() * (1 + 0.2 * inputs.uniform(O.shape, seed=seed + i, lo=-1, hi=1))
+        C.instance_view(f, i).copy_(torch.from_numpy(f0))
+        refs.append(O.step(f0, nsteps))
+    y = C.step(f, n=nsteps)
+    for i, ref in enumerate(refs):
+        got = C.instance_view(y, i).cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max(), err_msg=str(i))
+
+
+def test_batch_mixes_maxwellian_forms(B, oracle_mod):
+    """The Maxwellian form is per instance: a conservative and a point-value
+    cavity of different sizes in one context each match their own oracle."""
+    a = config("conservative_cavity")
+    b = dict(a, nx=5, ny=9, maxwellian="point", kn=0.8)
+    run_batch(B, oracle_mod, [a, b], 4, 300)
+
+
+def test_batch_of_translation_form_shocks(B, oracle_mod):
+    """Shocks of uneven length and Mach number streamed in the translation
+    form in one context (each with its own Courant numbers)."""
+    a = config("shift_shock")
+    b = dict(a, nx=23, mach=2.2, x0=-3.0, x1=1.5)
+    run_batch(B, oracle_mod, [a, b], 5, 310)
