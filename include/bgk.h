@@ -24,8 +24,14 @@
  * context back to back; instance k starts at element f_offset(k) and is
  * laid out f[cell][jz][jy][jx] (velocity fastest, jx fastest of all;
  * cell = iy * nx + ix).  Elements are double for BGK_FP64 and float for
- * BGK_FP32.  The context owns only its own device work space (one extra f
- * buffer, per-cell tables and moment partials), allocated in bgk_init.
+ * BGK_FP32.  Every buffer the size of f is the caller's: besides f and its
+ * output, bgk_step takes a workspace of ws_step_bytes (its ping-pong
+ * buffer) and bgk_step_adjoint one of ws_adjoint_bytes (two f-sized
+ * intermediate states), both reported by bgk_sizes.  The context owns only
+ * small per-cell and per-instance device data (table entries of the
+ * Maxwellians, moment partial sums, the reverse sweep's per-cell
+ * coefficients, the rounding counter), allocated in bgk_init and at the
+ * first reverse-sweep or lid-shear call.
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
  * stream).  Work is enqueued asynchronously; no call below synchronises the
@@ -120,7 +126,8 @@ typedef struct bgk_ctx bgk_ctx;
 /* Create a context for n_probs instances stepped together (one launch per
  * kernel for all of them).  All instances must share the velocity grid and
  * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
- * instance's dt, and allocates the context's device work space on the current
+ * instance's dt, and allocates the context's small device data (per-cell
+ * table entries and moment partial sums, no f-sized buffer) on the current
  * device.  precision: BGK_FP64 or BGK_FP32.
  * Errors: BGK_E_INVALID (also for a maxwellian field other than BGK_POINT and
  * BGK_CONSERVATIVE), BGK_E_CFL (Courant sum > 2/3; not checked for
@@ -137,8 +144,12 @@ int bgk_free(bgk_ctx *ctx);
 /* Human-readable description of the last error (never NULL). */
 const char *bgk_last_error(const bgk_ctx *ctx);
 
-/* Sizes: total f elements over all instances, total spatial cells. */
-int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells);
+/* Sizes: total f elements over all instances, total spatial cells, and
+ * the bytes of the caller-owned workspaces: ws_step_bytes for bgk_step and
+ * bgk_autotune (one f-sized buffer), ws_adjoint_bytes for bgk_step_adjoint
+ * (two).  Any output pointer may be NULL. */
+int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells, size_t *ws_step_bytes,
+              size_t *ws_adjoint_bytes);
 
 /* Per-instance layout: element offset of the instance in f, index of its
  * first cell in per-cell arrays, and its time step. */
@@ -151,8 +162,13 @@ int bgk_initial_state(bgk_ctx *ctx, void *f, void *stream);
 
 /* Advance all instances by n_steps >= 0 time steps:
  * f_out = (one step)^n_steps (f_in).  f_in is read only; f_out must not
- * alias f_in (BGK_E_ALIAS).  Both hold f_elems elements on the device. */
-int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *stream);
+ * overlap f_in (BGK_E_ALIAS).  Both hold f_elems elements on the device.
+ * ws: the caller's device workspace of ws_step_bytes (bgk_sizes), the
+ * ping-pong buffer of the intermediate streaming passes; its contents are
+ * overwritten.  It may be NULL for n_steps <= 1 (BGK_E_INVALID for
+ * n_steps >= 2) and must not overlap f_in or f_out (BGK_E_ALIAS).  With
+ * graph replay on, the workspace address is part of the captured graph. */
+int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *ws, void *stream);
 
 /* Moments of Eq. (macroscopic) of f, per cell: mom[cell][5] =
  * (n, Vx, Vy, Vz, T), double, device, n_cells * 5 elements. */
@@ -178,14 +194,16 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
  * state f (device, f_elems elements, read only; synchronises the stream) and
  * keeps the fastest by the steady time of a real step (streaming pass and
  * table preparation, (10 steps - 2 steps) / 8, after an untimed warm-up
- * of a few steps; the four fastest of the
- * sweep are timed twice more and ranked by their best time); it borrows a
- * temporary f-sized device buffer for the steps' output during the call (if
- * that allocation fails it times bare streaming passes over f instead); on
- * an error the previous shape stays in use; bgk_get_launch reports the shape in use and, after
- * autotuning, the measured time per step in microseconds; bgk_set_launch
- * applies a shape (BGK_E_INVALID if not valid for the context). */
-int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream);
+ * of a few steps; the four fastest of the sweep are timed twice more and
+ * ranked by their best time).  The timed steps write into `scratch` (the
+ * caller's device buffer of f_elems elements, overwritten) with `ws` (of
+ * ws_step_bytes) as their workspace; f, scratch and ws must not overlap
+ * (BGK_E_ALIAS), none may be NULL (BGK_E_INVALID).  On an error the
+ * previous shape stays in use; bgk_get_launch reports the shape in use
+ * and, after autotuning, the measured time per step in microseconds;
+ * bgk_set_launch applies a shape (BGK_E_INVALID if not valid for the
+ * context). */
+int bgk_autotune(bgk_ctx *ctx, const void *f, void *scratch, void *ws, void *stream);
 int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us);
 int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int persist);
 
@@ -244,15 +262,18 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * Minmod branch decisions are those of the forward map at f_n: a limited
  * slope is differentiated as 0 unless both differences have the same strict
  * sign, else as the smaller-magnitude difference (the backward one on a tie
- * of magnitudes).  The first call allocates the context's reverse-sweep work
- * space (two extra f buffers and per-cell coefficients); BGK_E_HIP if that
- * fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9 (1D) table entries per
+ * of magnitudes).  ws: the caller's device workspace of ws_adjoint_bytes
+ * (bgk_sizes; two f-sized intermediate states, overwritten), not overlapping
+ * f_n, lam_next or lam_n (BGK_E_ALIAS); NULL gives BGK_E_INVALID.  The first
+ * call allocates the context's per-cell reverse-sweep coefficients;
+ * BGK_E_HIP if that fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9
+ * (1D) table entries per
  * workgroup exceed the device's LDS, for BGK_SHIFT contexts (no reverse
  * sweep of the translation form) and for contexts with a BGK_CONSERVATIVE
  * instance (no reverse sweep of the effective parameters' solve).
  * Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
-                     void *stream);
+                     void *ws, void *stream);
 
 /* Shear stress on the moving lid (Sec. 5.1 cavity; the xy momentum flux
  * through the top wall, integrated along it):

@@ -72,21 +72,21 @@ def load(path: str = LIB_PATH):
     L.bgk_free.argtypes = [vp]
     L.bgk_last_error.argtypes = [vp]
     L.bgk_last_error.restype = ctypes.c_char_p
-    L.bgk_sizes.argtypes = [vp, sz, sz]
+    L.bgk_sizes.argtypes = [vp, sz, sz, sz, sz]
     L.bgk_instance_info.argtypes = [vp, ctypes.c_int, sz, sz, dp]
     L.bgk_initial_state.argtypes = [vp, vp, vp]
-    L.bgk_step.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    L.bgk_step.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
     L.bgk_moments.argtypes = [vp, vp, vp, vp]
     L.bgk_check.argtypes = [vp, vp, vp]
     L.bgk_set_timing.argtypes = [vp, ctypes.c_int]
     L.bgk_set_rounding_seed.argtypes = [vp, ctypes.c_uint]
     L.bgk_get_rounding_seed.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
     L.bgk_timing.argtypes = [vp, dp, ip]
-    L.bgk_autotune.argtypes = [vp, vp, vp]
+    L.bgk_autotune.argtypes = [vp, vp, vp, vp, vp]
     L.bgk_get_launch.argtypes = [vp, ip, ip, ip, ip, dp]
     L.bgk_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.bgk_set_graph.argtypes = [vp, ctypes.c_int]
-    L.bgk_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.bgk_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.bgk_lid_shear.argtypes = [vp, vp, vp, vp]
     L.bgk_lid_shear_grad.argtypes = [vp, vp, vp, vp, vp]
     L.bgk_cavity_metrics.argtypes = [vp, vp, dp, vp]
@@ -172,9 +172,11 @@ class Context:
         if rc != OK:
             raise BGKError(rc, self.L.bgk_last_error(None).decode())
         self.h = h
-        fe, nc = ctypes.c_size_t(), ctypes.c_size_t()
-        self._check(self.L.bgk_sizes(self.h, ctypes.byref(fe), ctypes.byref(nc)))
+        fe, nc, ws, wa = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.L.bgk_sizes(self.h, ctypes.byref(fe), ctypes.byref(nc), ctypes.byref(ws), ctypes.byref(wa)))
         self.f_elems, self.ncells = fe.value, nc.value
+        self.ws_step_bytes, self.ws_adjoint_bytes = ws.value, wa.value
+        self._ws = {}  # caller-owned workspaces (torch), made at first use
         self.nvel = inputs.nvel(self.problems[0])
         self.offsets, self.cell_offsets, self.dts = [], [], []
         for i in range(len(self.problems)):
@@ -211,6 +213,19 @@ class Context:
     def empty(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.f_elems, dtype=self.dtype, device=device)
 
+    def workspace(self, kind: str = "step", device="cuda") -> torch.Tensor:
+        """The workspace of bgk_step ("step") or bgk_step_adjoint ("adjoint"):
+        a torch byte tensor of the size bgk_sizes reports, kept for later calls."""
+        ws = self._ws.get(kind)
+        if ws is None:
+            n = self.ws_step_bytes if kind == "step" else self.ws_adjoint_bytes
+            ws = self._ws[kind] = torch.empty(n, dtype=torch.uint8, device=device)
+        return ws
+
+    def release_workspaces(self):
+        """Drop the workspaces (the next call that needs one makes it again)."""
+        self._ws.clear()
+
     def instance_view(self, f: torch.Tensor, i: int) -> torch.Tensor:
         n = inputs.ncells(self.problems[i]) * self.nvel
         o = self.offsets[i]
@@ -225,7 +240,8 @@ class Context:
     def step(self, f_in: torch.Tensor, f_out: torch.Tensor | None = None, n: int = 1, stream=None) -> torch.Tensor:
         f_out = torch.empty_like(f_in) if f_out is None else f_out
         assert f_in.dtype == self.dtype and f_in.numel() == self.f_elems and f_out.numel() == self.f_elems
-        self._check(self.L.bgk_step(self.h, _ptr(f_in), _ptr(f_out), int(n), _stream_handle(stream)))
+        ws = _ptr(self.workspace("step", f_in.device)) if n >= 2 else None
+        self._check(self.L.bgk_step(self.h, _ptr(f_in), _ptr(f_out), int(n), ws, _stream_handle(stream)))
         return f_out
 
     def moments(self, f: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
@@ -245,7 +261,7 @@ class Context:
         lam_n = torch.empty_like(lam_next) if lam_n is None else lam_n
         grad = self.grad_buffer(f_n.device) if grad is None else grad
         self._check(self.L.bgk_step_adjoint(self.h, _ptr(f_n), _ptr(lam_next), _ptr(lam_n), _ptr(grad),
-                                            _stream_handle(stream)))
+                                            _ptr(self.workspace("adjoint", f_n.device)), _stream_handle(stream)))
         return lam_n, grad
 
     def lid_shear(self, f: torch.Tensor, stream=None) -> torch.Tensor:
@@ -274,8 +290,12 @@ class Context:
         return self.L.bgk_check(self.h, _ptr(f), _stream_handle(stream))
 
     def autotune(self, f: torch.Tensor, stream=None) -> dict:
-        """Time every valid streaming-kernel shape on state f; keep the fastest."""
-        self._check(self.L.bgk_autotune(self.h, _ptr(f), _stream_handle(stream)))
+        """Time every valid streaming-kernel shape on state f; keep the fastest.
+        The timed steps write into a temporary torch buffer."""
+        scratch = torch.empty_like(f)
+        self._check(self.L.bgk_autotune(self.h, _ptr(f), _ptr(scratch), _ptr(self.workspace("step", f.device)),
+                                        _stream_handle(stream)))
+        del scratch
         return self.launch()
 
     def launch(self) -> dict:

@@ -48,17 +48,18 @@ struct bgk_ctx {
     // hipGraph replay of two-step chunks (stream, prep, stream, prep); key:
     // (f_out, which buffer the chunk starts from, table parity)
     bool use_graph = false;
-    struct Chunk { const void *f_out; int from_out; int parity; hipGraphExec_t exec; };
+    struct Chunk { const void *f_out; const void *ws; int from_out; int parity; hipGraphExec_t exec; };
     std::vector<Chunk> chunks;
     int ncu = 256;             // compute units of the device
     double tuned_us = 0.0;     // streaming-kernel time of the chosen shape when autotuned
     // current streaming pass: table parity it reads
     int pass_parity = 0;
     size_t esize = 8;
-    // device memory owned by the context
+    // device memory owned by the context (per-cell and per-entry data only;
+    // every f-sized buffer is the caller's)
     Inst *d_inst = nullptr;
     int *d_cell_prefix = nullptr, *d_pseudo_prefix = nullptr;
-    void *work = nullptr;      // one f-sized buffer for the ping-pong
+    void *work = nullptr;      // the caller's workspace during a bgk_step call (ping-pong buffer)
     void *params = nullptr;    // 2 x (ncells + npseudo) * pe elements (parity buffers)
     double *partial = nullptr; // ncells * vsplit_max * NQ
     double *mom = nullptr;     // ncells * 5 (bgk_check)
@@ -66,7 +67,8 @@ struct bgk_ctx {
     bool adj_ready = false;
     bool adjoint_fits = true;  // reverse-sweep tables fit the device's LDS
     int lds_max = 65536;       // device LDS per workgroup (bytes)
-    void *adj_h = nullptr, *adj_hb = nullptr;                     // f-sized: h = S(R_a f), abar
+    void *adj_h = nullptr, *adj_hb = nullptr;                     // during a reverse step: h = S(R_a f), abar
+                                                                  // (the two halves of the caller's workspace)
     double *info_f = nullptr, *info_h = nullptr;                  // ncells * NINFO
     double *adj_sums = nullptr, *adj_wsum = nullptr;              // ncells * vsplit_max * (NSUM, NWALL)
     double *adj_coef = nullptr;                                   // ncells * NCOEF
@@ -130,11 +132,9 @@ static void release(bgk_ctx *c)
     (void)hipFree(c->d_inst);
     (void)hipFree(c->d_cell_prefix);
     (void)hipFree(c->d_pseudo_prefix);
-    (void)hipFree(c->work);
     (void)hipFree(c->params);
     (void)hipFree(c->partial);
     (void)hipFree(c->mom);
-    for (void *q : {c->adj_h, c->adj_hb}) (void)hipFree(q);
     for (double *q : {c->info_f, c->info_h, c->adj_sums, c->adj_wsum, c->adj_coef, c->adj_dw, c->gk, c->gt, c->lid})
         (void)hipFree(q);
     (void)hipFree(c->lid_L);
@@ -297,28 +297,36 @@ static void choose_launch(bgk_ctx *c)
     c->block = 256;
 }
 
-extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out)
+// Host-side set-up of a context: validation, geometry, instance tables,
+// time steps and the default launch shape.  No device memory is touched.
+// Returns a status code and sets msg on failure.
+static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ctx *c, std::string &msg)
 {
-    if (!out) return fail(nullptr, BGK_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (!probs || n_probs < 1) return fail(nullptr, BGK_E_INVALID, "need at least one problem");
-    if (precision != BGK_FP64 && precision != BGK_FP32) return fail(nullptr, BGK_E_INVALID, "unknown precision");
-    for (int i = 0; i < n_probs; ++i) {
-        std::string msg;
-        int rc = validate(probs[i], i, msg);
-        if (rc) return fail(nullptr, rc, msg);
-        const bgk_problem &p = probs[i], &q = probs[0];
-        if (is2d_kind(p.kind) != is2d_kind(q.kind))
-            return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must have the same dimension");
-        if (p.reduced != q.reduced)
-            return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must share the velocity space (reduced or not)");
-        if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
-            return fail(nullptr, BGK_E_UNSUPPORTED, "shift streaming cannot share a context with other limiters");
-        for (int a = 0; a < 3; ++a)
-            if (p.nv[a] != q.nv[a] || p.vlo[a] != q.vlo[a] || p.vhi[a] != q.vhi[a])
-                return fail(nullptr, BGK_E_UNSUPPORTED, "all instances must share the velocity grid");
+    if (!probs || n_probs < 1) {
+        msg = "need at least one problem";
+        return BGK_E_INVALID;
     }
-    bgk_ctx *c = new bgk_ctx;
+    if (precision != BGK_FP64 && precision != BGK_FP32) {
+        msg = "unknown precision";
+        return BGK_E_INVALID;
+    }
+    for (int i = 0; i < n_probs; ++i) {
+        int rc = validate(probs[i], i, msg);
+        if (rc) return rc;
+        const bgk_problem &p = probs[i], &q = probs[0];
+        const char *why = nullptr;
+        if (is2d_kind(p.kind) != is2d_kind(q.kind)) why = "all instances must have the same dimension";
+        else if (p.reduced != q.reduced) why = "all instances must share the velocity space (reduced or not)";
+        else if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
+            why = "shift streaming cannot share a context with other limiters";
+        for (int a = 0; a < 3 && !why; ++a)
+            if (p.nv[a] != q.nv[a] || p.vlo[a] != q.vlo[a] || p.vhi[a] != q.vhi[a])
+                why = "all instances must share the velocity grid";
+        if (why) {
+            msg = why;
+            return BGK_E_UNSUPPORTED;
+        }
+    }
     c->precision = precision;
     c->esize = precision == BGK_FP64 ? 8 : 4;
     c->ninst = n_probs;
@@ -375,8 +383,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
             char b[160];
             snprintf(b, sizeof b, "velocity grid needs %zu bytes of LDS per workgroup; the device allows %d", fwd,
                      lds_max);
-            delete c;
-            return fail(nullptr, BGK_E_UNSUPPORTED, b);
+            msg = b;
+            return BGK_E_UNSUPPORTED;
         }
         c->adjoint_fits = adj <= (size_t)lds_max;
     }
@@ -421,8 +429,8 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
         }
         const int np = p.kind == BGK_SHOCK_1D ? 2 : p.kind == BGK_CAVITY_2D ? 2 * I.nx + 2 * I.ny : 0;
         if ((long long)I.ncell * g.nv * (long long)c->esize >= (1LL << 31) * 2LL) {
-            release(c);
-            return fail(nullptr, BGK_E_UNSUPPORTED, "one instance must hold fewer than 2^32 bytes of f");
+            msg = "one instance must hold fewer than 2^32 bytes of f";
+            return BGK_E_UNSUPPORTED;
         }
         c->h_inst.push_back(I);
         c->h_cell_prefix.push_back(I.cell0 + I.ncell);
@@ -435,6 +443,23 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     c->f_elems = (size_t)f_off;
 
     choose_launch(c);
+    return BGK_OK;
+}
+
+extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bgk_ctx **out)
+{
+    if (!out) return fail(nullptr, BGK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    bgk_ctx *c = new bgk_ctx;
+    {
+        std::string msg;
+        const int rc = plan_ctx(probs, n_probs, precision, c, msg);
+        if (rc) {
+            delete c;
+            return fail(nullptr, rc, msg);
+        }
+    }
+    const Geo &g = c->geo;
 
 #define ALLOC(ptr, bytes)                                                         \
     do {                                                                          \
@@ -448,7 +473,6 @@ extern "C" int bgk_init(const bgk_problem *probs, int n_probs, int precision, bg
     ALLOC(c->d_inst, sizeof(Inst) * n_probs);
     ALLOC(c->d_cell_prefix, sizeof(int) * (n_probs + 1));
     ALLOC(c->d_pseudo_prefix, sizeof(int) * (n_probs + 1));
-    ALLOC(c->work, c->f_elems * c->esize);
     ALLOC(c->params, 2 * (size_t)(c->ncells + c->npseudo) * g.pe * c->esize);
     ALLOC(c->partial, sizeof(double) * (size_t)c->ncells * c->vsplit_max * NQ);
     ALLOC(c->mom, sizeof(double) * (size_t)c->ncells * 5);
@@ -480,11 +504,15 @@ extern "C" const char *bgk_last_error(const bgk_ctx *ctx)
     return ctx ? ctx->err.c_str() : g_init_error.c_str();
 }
 
-extern "C" int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells)
+extern "C" int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells, size_t *ws_step_bytes,
+                         size_t *ws_adjoint_bytes)
 {
     if (!ctx) return BGK_E_INVALID;
+    const size_t fb = ctx->f_elems * ctx->esize;
     if (f_elems) *f_elems = ctx->f_elems;
     if (n_cells) *n_cells = (size_t)ctx->ncells;
+    if (ws_step_bytes) *ws_step_bytes = fb;          // the ping-pong buffer of bgk_step
+    if (ws_adjoint_bytes) *ws_adjoint_bytes = 2 * fb;  // h = S(R_a f_n) and the streamed adjoint
     return BGK_OK;
 }
 
@@ -733,7 +761,8 @@ static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t
             const int parity = (k - 1) % 2;
             hipGraphExec_t exec = nullptr;
             for (auto &ch : c->chunks)
-                if (ch.f_out == f_out && ch.from_out == from_out && ch.parity == parity) exec = ch.exec;
+                if (ch.f_out == f_out && ch.ws == c->work && ch.from_out == from_out && ch.parity == parity)
+                    exec = ch.exec;
             if (!exec) {
                 hipGraph_t graph;
                 HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -745,7 +774,7 @@ static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t
                 e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-                c->chunks.push_back({f_out, from_out, parity, exec});
+                c->chunks.push_back({f_out, c->work, from_out, parity, exec});
             }
             HIP_TRY(c, hipGraphLaunch(exec, s));
         }
@@ -768,9 +797,7 @@ static int ensure_lid(bgk_ctx *c)
 static int ensure_adjoint(bgk_ctx *c)
 {
     if (c->adj_ready) return BGK_OK;
-    const size_t fb = c->f_elems * c->esize, nc = (size_t)c->ncells, np = nc * c->vsplit_max;
-    HIP_TRY(c, hipMalloc(&c->adj_h, fb));
-    HIP_TRY(c, hipMalloc(&c->adj_hb, fb));
+    const size_t nc = (size_t)c->ncells, np = nc * c->vsplit_max;
     HIP_TRY(c, hipMalloc((void **)&c->info_f, sizeof(double) * nc * NINFO));
     HIP_TRY(c, hipMalloc((void **)&c->info_h, sizeof(double) * nc * NINFO));
     HIP_TRY(c, hipMalloc((void **)&c->adj_sums, sizeof(double) * np * NSUM));
@@ -903,12 +930,24 @@ static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam
     return BGK_OK;
 }
 
+// Does [a, a + na) overlap [b, b + nb)?
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
 extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
-                                void *stream)
+                                void *ws, void *stream)
 {
     if (!ctx) return BGK_E_INVALID;
-    if (!f_n || !lam_next || !lam_n || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_step_adjoint: NULL buffer");
+    if (!f_n || !lam_next || !lam_n || !grad_params || !ws)
+        return fail(ctx, BGK_E_INVALID, "bgk_step_adjoint: NULL buffer");
     if (lam_n == f_n || lam_n == lam_next) return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: lam_n must not alias inputs");
+    const size_t fb = ctx->f_elems * ctx->esize;
+    for (const void *q : {f_n, lam_next, (const void *)lam_n})
+        if (overlaps(ws, 2 * fb, q, fb))
+            return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: the workspace must not overlap f_n, lam_next or lam_n");
     if (!ctx->adjoint_fits)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
@@ -917,8 +956,12 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (ctx->geo.red)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep in the reduced velocity space");
     hipStream_t s = (hipStream_t)stream;
-    return ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
-                                      : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
+    ctx->adj_h = ws;
+    ctx->adj_hb = (char *)ws + fb;
+    const int rc = ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
+                                              : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
+    ctx->adj_h = ctx->adj_hb = nullptr;
+    return rc;
 }
 
 template <typename real>
@@ -1018,31 +1061,6 @@ extern "C" int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void
 
 // ------------------------------------------------------------- autotuning
 
-// Streaming passes that re-read f (used when no scratch state can be had).
-template <typename real>
-static int time_stream(bgk_ctx *c, const void *f, hipStream_t s, int reps, double *us)
-{
-    hipEvent_t a, b;
-    HIP_TRY(c, hipEventCreate(&a));
-    HIP_TRY(c, hipEventCreate(&b));
-    c->pass_parity = 0;
-    const bool timing = c->timing;
-    c->timing = false;
-    int rc = launch_stream<real>(c, f, c->work, s);  // warm
-    if (!rc) rc = hipEventRecord(a, s) == hipSuccess ? 0 : BGK_E_HIP;
-    for (int r = 0; r < reps && !rc; ++r) rc = launch_stream<real>(c, f, c->work, s);
-    if (!rc) rc = hipEventRecord(b, s) == hipSuccess ? 0 : BGK_E_HIP;
-    float ms = 0.0f;
-    if (!rc) rc = hipEventSynchronize(b) == hipSuccess ? 0 : BGK_E_HIP;
-    if (!rc) rc = hipEventElapsedTime(&ms, a, b) == hipSuccess ? 0 : BGK_E_HIP;
-    c->timing = timing;
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    if (rc) return fail(c, rc, "autotune: timing failed");
-    *us = 1e3 * ms / reps;
-    return BGK_OK;
-}
-
 // Time of one step in the steady part of bgk_step: (10 steps - 2 steps) / 8,
 // so the once-per-call passes (moments of the input, closing relaxation)
 // cancel; f -> tmp, with graph replay, timing and the rounding seed saved
@@ -1076,12 +1094,13 @@ static int time_steps(bgk_ctx *c, const void *f, void *tmp, hipStream_t s, doubl
     return BGK_OK;
 }
 
-// Try the candidate shapes on f and keep the fastest: by the steady step
-// time of real steps when a scratch state fits, else by streaming passes
-// that re-read f.  The four fastest of the sweep are timed twice more and
-// ranked by their best time (one timing varies by a few percent).
+// Try the candidate shapes on f and keep the fastest by the steady step time
+// of real steps (f -> tmp, the caller's scratch state; the ping-pong buffer
+// is the caller's workspace, already in c->work).  The four fastest of the
+// sweep are timed twice more and ranked by their best time (one timing
+// varies by a few percent).
 template <typename real>
-static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
+static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
 {
     TRY(launch_moments<real>(c, f, s));
     TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
@@ -1093,17 +1112,12 @@ static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
         const int v = std::min(vsplit_for(c, t), c->vsplit_max);
         if (std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
     }
-    void *tmp = nullptr;  // output state of the timed steps (optional)
-    if (hipMalloc(&tmp, c->f_elems * c->esize) != hipSuccess) {
-        tmp = nullptr;
-        (void)hipGetLastError();
-    }
     auto measure = [&](const Cand &k, double *us) {
         set_shape(c, k.vec, k.unroll, k.vsplit, k.persist);
-        return tmp ? time_steps<real>(c, f, tmp, s, us) : time_stream<real>(c, f, s, 4, us);
+        return time_steps<real>(c, f, tmp, s, us);
     };
     int rc = BGK_OK;
-    if (tmp) {
+    {
         // untimed warm-up: the first shapes of a cold device otherwise time slow
         double us = 0.0;
         for (int r = 0; r < 3 && !rc; ++r) rc = time_steps<real>(c, f, tmp, s, &us);
@@ -1129,10 +1143,7 @@ static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
             if (!rc) rc = measure(k, &us);
             if (!rc) k.us = std::min(k.us, us);
         }
-    if (tmp) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(tmp);
-    }
+    (void)hipStreamSynchronize(s);
     if (rc || cands.empty()) {
         set_shape(c, start.vec, start.unroll, start.vsplit, start.persist);
         return rc ? rc : fail(c, BGK_E_INVALID, "autotune: no valid shape");
@@ -1145,12 +1156,19 @@ static int autotune(bgk_ctx *c, const void *f, hipStream_t s)
     return BGK_OK;
 }
 
-extern "C" int bgk_autotune(bgk_ctx *ctx, const void *f, void *stream)
+extern "C" int bgk_autotune(bgk_ctx *ctx, const void *f, void *scratch, void *ws, void *stream)
 {
     if (!ctx) return BGK_E_INVALID;
-    if (!f) return fail(ctx, BGK_E_INVALID, "bgk_autotune: NULL buffer");
+    if (!f || !scratch || !ws) return fail(ctx, BGK_E_INVALID, "bgk_autotune: NULL buffer");
+    const size_t fb = ctx->f_elems * ctx->esize;
+    if (overlaps(scratch, fb, f, fb) || overlaps(ws, fb, f, fb) || overlaps(ws, fb, scratch, fb))
+        return fail(ctx, BGK_E_ALIAS, "bgk_autotune: f, scratch and the workspace must not overlap");
     hipStream_t s = (hipStream_t)stream;
-    return ctx->precision == BGK_FP64 ? autotune<double>(ctx, f, s) : autotune<float>(ctx, f, s);
+    ctx->work = ws;
+    const int rc = ctx->precision == BGK_FP64 ? autotune<double>(ctx, f, scratch, s)
+                                              : autotune<float>(ctx, f, scratch, s);
+    ctx->work = nullptr;
+    return rc;
 }
 
 extern "C" int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us)
@@ -1174,19 +1192,26 @@ extern "C" int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int
     return BGK_OK;
 }
 
-extern "C" int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *stream)
+extern "C" int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *ws, void *stream)
 {
     if (!ctx) return BGK_E_INVALID;
     if (!f_in || !f_out) return fail(ctx, BGK_E_INVALID, "bgk_step: NULL buffer");
     if (n_steps < 0) return fail(ctx, BGK_E_INVALID, "bgk_step: n_steps < 0");
-    if (f_in == f_out) return fail(ctx, BGK_E_ALIAS, "bgk_step: f_in and f_out must differ");
+    const size_t fb = ctx->f_elems * ctx->esize;
+    if (overlaps(f_in, fb, f_out, fb)) return fail(ctx, BGK_E_ALIAS, "bgk_step: f_in and f_out must not overlap");
+    if (n_steps >= 2 && !ws) return fail(ctx, BGK_E_INVALID, "bgk_step: n_steps >= 2 needs the workspace");
+    if (n_steps >= 2 && (overlaps(ws, fb, f_in, fb) || overlaps(ws, fb, f_out, fb)))
+        return fail(ctx, BGK_E_ALIAS, "bgk_step: the workspace must not overlap f_in or f_out");
     hipStream_t s = (hipStream_t)stream;
     if (n_steps == 0) {
-        HIP_TRY(ctx, hipMemcpyAsync(f_out, f_in, ctx->f_elems * ctx->esize, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(ctx, hipMemcpyAsync(f_out, f_in, fb, hipMemcpyDeviceToDevice, s));
         return BGK_OK;
     }
-    return ctx->precision == BGK_FP64 ? do_step<double>(ctx, f_in, f_out, n_steps, s)
-                                      : do_step<float>(ctx, f_in, f_out, n_steps, s);
+    ctx->work = n_steps >= 2 ? ws : nullptr;
+    const int rc = ctx->precision == BGK_FP64 ? do_step<double>(ctx, f_in, f_out, n_steps, s)
+                                              : do_step<float>(ctx, f_in, f_out, n_steps, s);
+    ctx->work = nullptr;
+    return rc;
 }
 
 extern "C" int bgk_moments(bgk_ctx *ctx, const void *f, double *mom, void *stream)
@@ -1281,3 +1306,4 @@ extern "C" int bgk_timing(bgk_ctx *ctx, double *ms, int *launches)
     ctx->ev_used = 0;
     return BGK_OK;
 }
+

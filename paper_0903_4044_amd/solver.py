@@ -9,6 +9,14 @@ The backward pass recomputes states from checkpoints: the forward pass keeps
 f every `every` steps, and the backward pass re-runs each segment forward
 (storing its states) before sweeping back through it, so memory is
 (nsteps / every + every) states instead of nsteps.
+
+The recomputed states are the forward pass's own, bit for bit.  A call of n
+steps keeps the relaxations between its streaming passes fused and
+materialises only its final state (in FP32 rounded stochastically, with
+random bits keyed by the context's rounding counter).  So the forward pass
+advances one step per call, as the recomputation does, and records the
+rounding seed at each checkpoint; the backward pass sets that seed before it
+recomputes a segment and restores the caller's seed at the end.
 """
 from __future__ import annotations
 
@@ -23,6 +31,32 @@ def _check_param(value: torch.Tensor, expected: float, name: str):
         raise ValueError(f"{name}={v} differs from the Context's {expected}; build a Context for it")
 
 
+def forward_checkpoints(solver: Context, f0: torch.Tensor, nsteps: int, every: int):
+    """Steps f0 forward nsteps times; returns (f_N, the state at the start of
+    every segment of `every` steps, the rounding seed at each of them)."""
+    checkpoints, seeds = [], []
+    f = f0
+    done = 0
+    while done < nsteps:
+        checkpoints.append(f)
+        seeds.append(solver.seed())
+        k = min(every, nsteps - done)
+        for _ in range(k):
+            f = solver.step(f, n=1)
+        done += k
+    return f, checkpoints, seeds
+
+
+def recompute_segment(solver: Context, start: torch.Tensor, seed: int, k: int):
+    """The states f^0 .. f^(k-1) of a segment from its checkpoint and seed,
+    as the forward pass computed them (one step per call)."""
+    solver.set_seed(seed)
+    states = [start]
+    for _ in range(k - 1):
+        states.append(solver.step(states[-1], n=1))
+    return states
+
+
 class Rollout(torch.autograd.Function):
     """f_N = step^nsteps(f_0) for a single-instance Context."""
 
@@ -31,16 +65,9 @@ class Rollout(torch.autograd.Function):
         p = solver.problems[0]
         _check_param(kn, p["kn"], "kn")
         _check_param(tw, p.get("t_wall", 1.0), "t_wall")
-        checkpoints = []
-        f = f0.detach().contiguous()
-        done = 0
-        while done < nsteps:
-            checkpoints.append(f)
-            k = min(every, nsteps - done)
-            f = solver.step(f, n=k)
-            done += k
+        f, checkpoints, seeds = forward_checkpoints(solver, f0.detach().contiguous(), nsteps, every)
         ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
-        ctx.checkpoints = checkpoints
+        ctx.checkpoints, ctx.seeds = checkpoints, seeds
         ctx.shapes = (kn.shape, tw.shape)
         ctx.devices = (kn.device, tw.device)
         return f
@@ -52,15 +79,15 @@ class Rollout(torch.autograd.Function):
         lam = lam.to(solver.dtype).contiguous().clone()
         grad = solver.grad_buffer(lam.device)
         other = torch.empty_like(lam)
+        caller_seed = solver.seed()
         for seg in range(len(ctx.checkpoints) - 1, -1, -1):
             k = min(every, nsteps - seg * every)
-            states = [ctx.checkpoints[seg]]
-            for _ in range(k - 1):
-                states.append(solver.step(states[-1], n=1))
+            states = recompute_segment(solver, ctx.checkpoints[seg], ctx.seeds[seg], k)
             for i in range(k - 1, -1, -1):
                 solver.step_adjoint(states[i], lam, other, grad)
                 lam, other = other, lam
-        ctx.checkpoints = None
+        solver.set_seed(caller_seed)
+        ctx.checkpoints = ctx.seeds = None
         g = grad[0]
         return (lam, g[0].reshape(ctx.shapes[0]).to(ctx.devices[0]), g[1].reshape(ctx.shapes[1]).to(ctx.devices[1]),
                 None, None, None)

@@ -173,3 +173,37 @@ def test_full_adjoint_workload(B, prec):
             fd = (_loss(B, dict(cfg, **{key: cfg[key] + h}), prec, x, nsteps) -
                   _loss(B, dict(cfg, **{key: cfg[key] - h}), prec, x, nsteps)) / (2 * h)
             assert got == pytest.approx(fd, rel=1e-5), key
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_checkpoint_recompute_reproduces_forward(B, oracle_mod, prec):
+    """The backward pass recomputes each checkpoint segment from its stored
+    state and rounding seed; the recomputed states are the forward pass's,
+    bit for bit (FP32 included: the same rounding counters), so the reverse
+    sweep differentiates the trajectory the loss was computed on.  The
+    caller's rounding seed is restored after the backward pass."""
+    from paper_0903_4044_amd import solver
+    cfg = small("cavity", nx=6, ny=5)
+    O = oracle_mod.Oracle(cfg)
+    C = B.Context(cfg, prec)
+    f0 = dev(O.initial_state() * (1 + 0.2 * inputs.uniform(O.shape, seed=37, lo=-1, hi=1)), C.dtype)
+    nsteps, every = 11, 4
+    C.set_seed(500)
+    fN, ckpt, seeds = solver.forward_checkpoints(C, f0, nsteps, every)
+    assert len(ckpt) == 3 and seeds[0] == 500
+    ends = ckpt[1:] + [fN]
+    for seg in range(len(ckpt)):
+        k = min(every, nsteps - seg * every)
+        states = solver.recompute_segment(C, ckpt[seg], seeds[seg], k)
+        last = C.step(states[-1], n=1)
+        assert torch.equal(last, ends[seg]), seg
+    # through autograd: the seed after backward is the caller's
+    C.set_seed(900)
+    x = f0.clone().requires_grad_(True)
+    kn = torch.tensor(cfg["kn"], dtype=torch.float64, requires_grad=True)
+    tw = torch.tensor(cfg["t_wall"], dtype=torch.float64, requires_grad=True)
+    L = solver.lid_shear(solver.rollout(x, kn, tw, C, nsteps, every=every), tw, C)
+    s_after_forward = C.seed()
+    L.backward()
+    assert C.seed() == s_after_forward
+    assert torch.isfinite(x.grad).all()

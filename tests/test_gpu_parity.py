@@ -411,3 +411,34 @@ def test_graph_replay_matches_eager(B):
                 C.moments(out)  # eager work between replays
         C.set_graph(False)
     torch.cuda.synchronize()
+
+
+def test_workspace_is_the_callers(B):
+    """bgk_sizes reports the workspaces (one f for bgk_step, two for the
+    reverse sweep); bgk_step needs one for n >= 2 and rejects one that
+    overlaps f_in or f_out; the output matches a run with the binding's own
+    workspace."""
+    cfg = small("cavity", nx=5, ny=4, nv=(12, 12, 8))
+    C = B.Context(cfg, "fp32")
+    fb = C.f_elems * 4
+    assert C.ws_step_bytes == fb and C.ws_adjoint_bytes == 2 * fb
+    L = B.load()
+    s = torch.cuda.current_stream().cuda_stream
+    x = C.initial_state()
+    y = torch.full_like(x, float("nan"))
+    C.set_seed(3)
+    assert L.bgk_step(C.h, x.data_ptr(), y.data_ptr(), 2, None, s) == B.E_INVALID
+    big = torch.empty(3 * C.f_elems, dtype=torch.float32, device="cuda")
+    assert L.bgk_step(C.h, x.data_ptr(), big.data_ptr(), 2, big[C.f_elems // 2:].data_ptr(), s) == B.E_ALIAS
+    assert L.bgk_step(C.h, big.data_ptr(), big[C.f_elems // 2:].data_ptr(), 1, None, s) == B.E_ALIAS
+    ws = torch.empty(fb, dtype=torch.uint8, device="cuda")
+    assert L.bgk_step(C.h, x.data_ptr(), y.data_ptr(), 3, ws.data_ptr(), s) == B.OK
+    C.set_seed(3)
+    z = C.step(x, n=3)
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    assert L.bgk_step(C.h, x.data_ptr(), y.data_ptr(), 1, None, s) == B.OK  # one step needs no workspace
+    g = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lam = torch.ones_like(x)
+    assert L.bgk_step_adjoint(C.h, x.data_ptr(), lam.data_ptr(), y.data_ptr(), g.data_ptr(), None, s) == B.E_INVALID
+    torch.cuda.synchronize()
