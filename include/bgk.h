@@ -207,23 +207,26 @@ int bgk_autotune(bgk_ctx *ctx, const void *f, void *scratch, void *ws, void *str
 int bgk_get_launch(const bgk_ctx *ctx, int *vec, int *unroll, int *vsplit, int *persist, double *tuned_us);
 int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int persist);
 
-/* Graph replay.  When on (default off), bgk_step captures the steady
- * two-step part of its launch sequence (streaming pass, table preparation,
- * streaming pass, table preparation) into a hipGraph the first time a given
- * output buffer is used, and replays it for the middle steps; graphs are
- * kept until the launch shape changes, graph replay is switched off or the
- * context is freed.  Ignored while kernel timing is on and on the NULL
- * (legacy default) stream, which cannot be captured.  The output buffer's
- * address is part of the graph: do not free and reuse it for another buffer
- * while graph replay is on. */
+/* Graph replay.  When on (default off), bgk_step captures every launch of
+ * the call after the one that sets the rounding counter (moments of f_in,
+ * tables, all n_steps streaming passes and tables, closing relaxation) into
+ * one hipGraph the first time a combination (f_in, f_out, ws, n_steps,
+ * timing on or off) is used, and replays that graph when the combination
+ * comes again; up to four graphs are kept per context (the least recently
+ * used is dropped), until the launch shape changes, graph replay is
+ * switched off or the context is freed.  The buffer addresses are part of a
+ * graph: do not free and reuse them for other buffers while graph replay is
+ * on.  Ignored while kernel timing is on (HIP reports no elapsed time for
+ * events that graph nodes record, so timed calls launch eagerly) and on the
+ * NULL (legacy default) stream, which cannot be captured. */
 int bgk_set_graph(bgk_ctx *ctx, int on);
 
 /* Timing of the streaming kernel.  capacity > 0 turns timing on and creates
  * that many HIP event pairs up front (more are created on demand); while on,
  * bgk_step records a pair around every launch of the streaming kernel on
- * `stream`.  capacity = 0 turns timing off.  bgk_timing synchronises and
- * returns the summed device time (ms) and the launch count since the last
- * reset, then resets. */
+ * `stream` (calls launch eagerly while timing is on).  capacity = 0 turns
+ * timing off.  bgk_timing synchronises and returns the summed device time
+ * (ms) and the launch count since the last reset, then resets. */
 int bgk_set_timing(bgk_ctx *ctx, int capacity);
 int bgk_timing(bgk_ctx *ctx, double *ms, int *launches);
 

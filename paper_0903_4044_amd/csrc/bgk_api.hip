@@ -45,11 +45,17 @@ struct bgk_ctx {
     int persist = 0;           // streaming kernel: 0 one workgroup per item, else resident workgroups per CU
     bool shift = false;        // every instance streams in the translation form (k_shift)
     bool conservative = false; // some instance relaxes with the effective Maxwellian parameters
-    // hipGraph replay of two-step chunks (stream, prep, stream, prep); key:
-    // (f_out, which buffer the chunk starts from, table parity)
+    // hipGraph replay of whole bgk_step calls (every launch after the one that
+    // sets the rounding counter); key: (f_in, f_out, workspace, steps).
     bool use_graph = false;
-    struct Chunk { const void *f_out; const void *ws; int from_out; int parity; hipGraphExec_t exec; };
+    struct Chunk {
+        const void *f_in, *f_out, *ws;
+        int n;
+        hipGraphExec_t exec;
+        unsigned long long used;  // last use, for eviction
+    };
     std::vector<Chunk> chunks;
+    unsigned long long graph_clock = 0;
     int ncu = 256;             // compute units of the device
     double tuned_us = 0.0;     // streaming-kernel time of the chosen shape when autotuned
     // current streaming pass: table parity it reads
@@ -126,6 +132,8 @@ static Args make_args(const bgk_ctx *c)
     return a;
 }
 
+static void drop_graphs(bgk_ctx *c);
+
 static void release(bgk_ctx *c)
 {
     if (!c) return;
@@ -145,7 +153,7 @@ static void release(bgk_ctx *c)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    for (auto &k : c->chunks) (void)hipGraphExecDestroy(k.exec);
+    drop_graphs(c);
     delete c;
 }
 
@@ -236,9 +244,15 @@ static bool vec_valid(const bgk_ctx *c, int v)
     return true;
 }
 
+static void drop_chunk(bgk_ctx::Chunk &k)
+{
+    if (k.exec) (void)hipGraphExecDestroy(k.exec);
+    k.exec = nullptr;
+}
+
 static void drop_graphs(bgk_ctx *c)
 {
-    for (auto &k : c->chunks) (void)hipGraphExecDestroy(k.exec);
+    for (auto &k : c->chunks) drop_chunk(k);
     c->chunks.clear();
 }
 
@@ -741,48 +755,81 @@ static int one_pass(bgk_ctx *c, int k, int n, const void *src, void *dst, hipStr
     return launch_prep<real>(c, k < n ? MODE_MID : MODE_FINAL, c->vsplit, k % 2, s);
 }
 
+// Every launch of n >= 1 steps after the rounding counter is set: the
+// moments of f_in, the opening tables, n streaming passes each followed by
+// the next tables, and the closing relaxation into f_out.
+template <typename real>
+static int step_launches(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t s)
+{
+    TRY(launch_moments<real>(c, f_in, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    auto X = [&](int k) -> void * { return k == 0 ? const_cast<void *>(f_in) : ((n - k) % 2 == 0 ? f_out : c->work); };
+    for (int k = 1; k <= n; ++k) TRY(one_pass<real>(c, k, n, X(k - 1), X(k), s));
+    return launch_final<real>(c, f_out, f_out, n % 2, s);
+}
+
+constexpr size_t MAX_GRAPHS = 4;  // whole-call graphs kept per context (least recently used dropped)
+
+// Capture step_launches for (f_in, f_out, workspace, n) into a graph.
+template <typename real>
+static int capture_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t s, bgk_ctx::Chunk &ch)
+{
+    ch.f_in = f_in;
+    ch.f_out = f_out;
+    ch.ws = c->work;
+    ch.n = n;
+    ch.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    const int rc = step_launches<real>(c, f_in, f_out, n, s);
+    e = hipStreamEndCapture(s, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc ? rc : fail(c, BGK_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&ch.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return BGK_OK;
+}
+
 template <typename real>
 static int do_step(bgk_ctx *c, const void *f_in, void *f_out, int n, hipStream_t s)
 {
     // rounding counter of pass k (1-based) is seed + k - 1; the tables after
-    // each pass advance it on the device, so graph replays advance it too
+    // each pass advance it on the device.  Set outside any graph: its value
+    // changes from call to call.
     hipLaunchKernelGGL(k_set_pass, dim3(1), dim3(64), 0, s, c->pass, c->seed);
     HIP_TRY(c, hipGetLastError());
     c->seed += (uint32_t)n;
-    TRY(launch_moments<real>(c, f_in, s));
-    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
-    auto X = [&](int k) -> void * { return k == 0 ? const_cast<void *>(f_in) : ((n - k) % 2 == 0 ? f_out : c->work); };
-    int k = 1;
-    TRY(one_pass<real>(c, k, n, X(0), X(1), s));
-    if (c->use_graph && !c->timing && s != nullptr) {  // the legacy default stream cannot be captured
-        for (k = 2; k + 1 <= n - 1; k += 2) {
-            // passes k, k+1: X(k-1) -> X(k) -> X(k+1) == X(k-1); tables (k-1)%2 -> k%2 -> (k-1)%2
-            const int from_out = X(k - 1) == f_out ? 1 : 0;
-            const int parity = (k - 1) % 2;
-            hipGraphExec_t exec = nullptr;
-            for (auto &ch : c->chunks)
-                if (ch.f_out == f_out && ch.ws == c->work && ch.from_out == from_out && ch.parity == parity)
-                    exec = ch.exec;
-            if (!exec) {
-                hipGraph_t graph;
-                HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                int rc = one_pass<real>(c, k, n, X(k - 1), X(k), s);
-                if (!rc) rc = one_pass<real>(c, k + 1, n, X(k), X(k + 1), s);
-                hipError_t e = hipStreamEndCapture(s, &graph);
-                if (rc) return rc;
-                if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (e != hipSuccess) return fail(c, BGK_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-                c->chunks.push_back({f_out, c->work, from_out, parity, exec});
-            }
-            HIP_TRY(c, hipGraphLaunch(exec, s));
+    // graphs step aside while kernel timing is on (HIP reports no elapsed
+    // time for events recorded by graph nodes) and on the legacy default
+    // stream, which cannot be captured
+    if (!c->use_graph || c->timing || s == nullptr) return step_launches<real>(c, f_in, f_out, n, s);
+    bgk_ctx::Chunk *ch = nullptr;
+    for (auto &k : c->chunks)
+        if (k.f_in == f_in && k.f_out == f_out && k.ws == c->work && k.n == n) ch = &k;
+    if (!ch) {
+        if (c->chunks.size() >= MAX_GRAPHS) {
+            size_t lru = 0;
+            for (size_t i = 1; i < c->chunks.size(); ++i)
+                if (c->chunks[i].used < c->chunks[lru].used) lru = i;
+            drop_chunk(c->chunks[lru]);
+            c->chunks.erase(c->chunks.begin() + (long)lru);
         }
-    } else {
-        k = 2;
+        bgk_ctx::Chunk nc;
+        const int rc = capture_step<real>(c, f_in, f_out, n, s, nc);
+        if (rc) {
+            drop_chunk(nc);
+            return rc;
+        }
+        c->chunks.push_back(std::move(nc));
+        ch = &c->chunks.back();
     }
-    for (; k <= n; ++k) TRY(one_pass<real>(c, k, n, X(k - 1), X(k), s));
-    return launch_final<real>(c, f_out, f_out, n % 2, s);
+    ch->used = ++c->graph_clock;
+    HIP_TRY(c, hipGraphLaunch(ch->exec, s));
+    return BGK_OK;
 }
 
 // ------------------------------------------------------------- reverse sweep
@@ -1295,14 +1342,18 @@ extern "C" int bgk_timing(bgk_ctx *ctx, double *ms, int *launches)
 {
     if (!ctx) return BGK_E_INVALID;
     double tot = 0.0;
-    for (size_t i = 0; i < ctx->ev_used; ++i) {
-        HIP_TRY(ctx, hipEventSynchronize(ctx->events[i].second));
+    int count = 0;
+    auto add = [&](const std::pair<hipEvent_t, hipEvent_t> &e) -> int {
+        HIP_TRY(ctx, hipEventSynchronize(e.second));
         float t = 0.0f;
-        HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->events[i].first, ctx->events[i].second));
+        HIP_TRY(ctx, hipEventElapsedTime(&t, e.first, e.second));
         tot += t;
-    }
+        count++;
+        return BGK_OK;
+    };
+    for (size_t i = 0; i < ctx->ev_used; ++i) TRY(add(ctx->events[i]));
     if (ms) *ms = tot;
-    if (launches) *launches = (int)ctx->ev_used;
+    if (launches) *launches = count;
     ctx->ev_used = 0;
     return BGK_OK;
 }
