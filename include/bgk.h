@@ -39,8 +39,8 @@
  *
  * Errors.  Every call returns a status code (BGK_OK = 0).  No exception or
  * abort crosses the ABI.  bgk_last_error(ctx) describes the last failure on
- * that context; bgk_last_error(NULL) describes the last failed bgk_init of
- * the calling thread.
+ * that context; bgk_last_error(NULL) describes the last failed bgk_init or
+ * bgk_step_noalloc of the calling thread.
  */
 #ifndef BGK_H
 #define BGK_H
@@ -169,6 +169,29 @@ int bgk_initial_state(bgk_ctx *ctx, void *f, void *stream);
  * n_steps >= 2) and must not overlap f_in or f_out (BGK_E_ALIAS).  With
  * graph replay on, the workspace address is part of the captured graph. */
 int bgk_step(bgk_ctx *ctx, const void *f_in, void *f_out, int n_steps, void *ws, void *stream);
+
+/* Allocation-free variant of bgk_step, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It takes the problems instead of a
+ * context and advances them by n_steps exactly as a context made by
+ * bgk_init(probs, n_probs, precision, ...) would in its first bgk_step call:
+ * same validation and status codes, the default launch shape (no tuned
+ * shape), graph replay and kernel timing off, FP32 rounding counters
+ * 0 .. n_steps.  f_in, f_out and ws are as for bgk_step (ws of the
+ * ws_step_bytes a context would report: the f bytes, the caller's).  It
+ * calls no hipMalloc, hipFree or other allocating routine: the device data a
+ * context would own (instance tables, Maxwellian table entries, moment
+ * partial sums, the rounding counter) lives in one static device array of
+ * BGK_NOALLOC_SCRATCH_MIB MiB per GPU, held until the process ends; problems
+ * that need more return BGK_E_UNSUPPORTED before any device work.  The
+ * array's device address is looked up at the first call on each device.
+ * Every call on a GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller.  Asynchronous on `stream`; on
+ * failure bgk_last_error(NULL) describes the error. */
+#define BGK_NOALLOC_SCRATCH_MIB 64
+int bgk_step_noalloc(const bgk_problem *probs, int n_probs, int precision, const void *f_in, void *f_out,
+                     int n_steps, void *ws, void *stream);
 
 /* Moments of Eq. (macroscopic) of f, per cell: mom[cell][5] =
  * (n, Vx, Vy, Vz, T), double, device, n_cells * 5 elements. */

@@ -51,7 +51,7 @@ EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_
            "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
            "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph",
            "bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad", "bgk_set_rounding_seed",
-           "bgk_get_rounding_seed", "bgk_cavity_metrics")
+           "bgk_get_rounding_seed", "bgk_cavity_metrics", "bgk_step_noalloc")
 
 TUNED_PATH = os.path.join(HERE, "tuned.json")
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     L.bgk_lid_shear.argtypes = [vp, vp, vp, vp]
     L.bgk_lid_shear_grad.argtypes = [vp, vp, vp, vp, vp]
     L.bgk_cavity_metrics.argtypes = [vp, vp, dp, vp]
+    L.bgk_step_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -147,6 +148,23 @@ def _stream_handle(stream=None) -> int:
 def _ptr(t: torch.Tensor) -> int:
     assert t.is_cuda and t.is_contiguous()
     return int(t.data_ptr())
+
+
+def step_noalloc(problems, precision: str, f_in: torch.Tensor, f_out: torch.Tensor, n: int,
+                 ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """bgk_step_noalloc: n steps of `problems` (a dict or a list of dicts)
+    without a context; the library allocates nothing.  ws: a device buffer of
+    at least f_in's bytes (needed for n >= 2), the caller's."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    L = load()
+    arr = (Problem * len(problems))(*[to_struct(p) for p in problems])
+    code = FP64 if precision == "fp64" else FP32
+    rc = L.bgk_step_noalloc(arr, len(problems), code, _ptr(f_in), _ptr(f_out), int(n),
+                            _ptr(ws) if ws is not None else None, _stream_handle(stream))
+    if rc != OK:
+        raise BGKError(rc, L.bgk_last_error(None).decode())
+    return f_out
 
 
 class Context:

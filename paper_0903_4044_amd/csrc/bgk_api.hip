@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1358,3 +1359,118 @@ extern "C" int bgk_timing(bgk_ctx *ctx, double *ms, int *launches)
     return BGK_OK;
 }
 
+// ------------------------------------------------------------- allocation-free step
+// bgk_step_noalloc: the step of bgk_step for callers that cannot allocate
+// device memory.  The per-call device data a context would own (instance
+// tables, the Maxwellian table entries of both parities, the moment partial
+// sums, the rounding counter) is carved from one static device array of
+// NOALLOC_SCRATCH_BYTES; each device holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel: its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)BGK_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;  // device address of `scratch`, per device
+
+static int scratch_address(int dev, void **out, std::string &msg)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return BGK_E_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BGK_OK;
+}
+
+// Host data reaches the device through kernel arguments (copied when the
+// launch is enqueued), so no staging buffer has to outlive the call.
+constexpr int UPLOAD_CHUNK = 2048;
+struct UploadChunk { unsigned char b[UPLOAD_CHUNK]; };
+
+__global__ void k_upload(UploadChunk c, int n, unsigned char *__restrict__ dst)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.b[i];
+}
+
+static int upload(const void *src, size_t n, void *dst, hipStream_t s, std::string &msg)
+{
+    const unsigned char *p = (const unsigned char *)src;
+    for (size_t o = 0; o < n; o += UPLOAD_CHUNK) {
+        UploadChunk c;
+        const int k = (int)std::min<size_t>(UPLOAD_CHUNK, n - o);
+        memcpy(c.b, p + o, (size_t)k);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, c, k, (unsigned char *)dst + o);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            msg = std::string("k_upload: ") + hipGetErrorString(e);
+            return BGK_E_HIP;
+        }
+    }
+    return BGK_OK;
+}
+
+extern "C" int bgk_step_noalloc(const bgk_problem *probs, int n_probs, int precision, const void *f_in, void *f_out,
+                                int n_steps, void *ws, void *stream)
+{
+    bgk_ctx c;  // host-side plan; its device pointers are carved from the scratch array
+    std::string msg;
+    int rc = plan_ctx(probs, n_probs, precision, &c, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    // layout of the scratch array, 256-byte aligned pieces
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_inst = up(sizeof(Inst) * n_probs), b_pre = up(sizeof(int) * (n_probs + 1));
+    const size_t b_par = up(2 * (size_t)(c.ncells + c.npseudo) * c.geo.pe * c.esize);
+    const size_t b_part = up(sizeof(double) * (size_t)c.ncells * c.vsplit_max * NQ), b_pass = 256;
+    const size_t total = b_inst + 2 * b_pre + b_par + b_part + b_pass;
+    if (total > NOALLOC_SCRATCH_BYTES) {
+        char b[200];
+        snprintf(b, sizeof b, "bgk_step_noalloc: the problems need %.1f MiB of device scratch; the static array holds %d MiB",
+                 (double)total / (1 << 20), BGK_NOALLOC_SCRATCH_MIB);
+        return fail(nullptr, BGK_E_UNSUPPORTED, b);
+    }
+    if (!f_in || !f_out) return fail(nullptr, BGK_E_INVALID, "bgk_step_noalloc: NULL buffer");
+    if (n_steps < 0) return fail(nullptr, BGK_E_INVALID, "bgk_step_noalloc: n_steps < 0");
+    const size_t fb = c.f_elems * c.esize;
+    if (overlaps(f_in, fb, f_out, fb))
+        return fail(nullptr, BGK_E_ALIAS, "bgk_step_noalloc: f_in and f_out must not overlap");
+    if (n_steps >= 2 && !ws) return fail(nullptr, BGK_E_INVALID, "bgk_step_noalloc: n_steps >= 2 needs the workspace");
+    if (n_steps >= 2 && (overlaps(ws, fb, f_in, fb) || overlaps(ws, fb, f_out, fb)))
+        return fail(nullptr, BGK_E_ALIAS, "bgk_step_noalloc: the workspace must not overlap f_in or f_out");
+    hipStream_t s = (hipStream_t)stream;
+    if (n_steps == 0) {
+        const hipError_t e = hipMemcpyAsync(f_out, f_in, fb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(nullptr, BGK_E_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+        return BGK_OK;
+    }
+    void *base = nullptr;
+    rc = scratch_address(c.device, &base, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    unsigned char *q = (unsigned char *)base;
+    c.d_inst = (Inst *)q;
+    q += b_inst;
+    c.d_cell_prefix = (int *)q;
+    q += b_pre;
+    c.d_pseudo_prefix = (int *)q;
+    q += b_pre;
+    c.params = q;
+    q += b_par;
+    c.partial = (double *)q;
+    q += b_part;
+    c.pass = (uint32_t *)q;
+    rc = upload(c.h_inst.data(), sizeof(Inst) * n_probs, c.d_inst, s, msg);
+    if (!rc) rc = upload(c.h_cell_prefix.data(), sizeof(int) * (n_probs + 1), c.d_cell_prefix, s, msg);
+    if (!rc) rc = upload(c.h_pseudo_prefix.data(), sizeof(int) * (n_probs + 1), c.d_pseudo_prefix, s, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    c.work = n_steps >= 2 ? ws : nullptr;
+    rc = precision == BGK_FP64 ? do_step<double>(&c, f_in, f_out, n_steps, s) : do_step<float>(&c, f_in, f_out, n_steps, s);
+    if (rc) return fail(nullptr, rc, c.err);
+    return BGK_OK;
+}
