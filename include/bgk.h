@@ -321,14 +321,13 @@ int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double *grad_para
  * out[2k] = D, the mean shear stress on the lid in units of p0 U_W
  * (p0 = 1/2, the pressure of the gas at rest with n = T = 1):
  * D = -L / (p0 U_W (x1 - x0)), L as in bgk_lid_shear; out[2k + 1] = G, the
- * flow rate of the main vortex: 2 / (y1 - y0) times the integral of
+ * flow rate of the main vortex as Sec. 5.2 defines it: the integral of
  * V_x / U_W along the vertical line through the middle of the cavity (the
  * middle column, or the mean of the two middle columns), from the first
- * zero below the lid (linear between cell centres) up to the lid (linear
- * extrapolation over the top half cell), or from the bottom wall if there
- * is no zero.  The factor 2 is the normalisation under which the Table's
- * reference values are met.  NaN for non-cavity instances and for a lid at
- * rest.  f: device, f_elems elements; out: host, 2 n_probs doubles.
+ * zero below the lid (the vortex centre; linear between cell centres) up to
+ * the lid (linear extrapolation over the top half cell), or from the bottom
+ * wall if there is no zero, divided by the height (y1 - y0).  NaN for
+ * non-cavity instances and for a lid at rest.  f: device, f_elems elements; out: host, 2 n_probs doubles.
  * Synchronises `stream`; errors: BGK_E_INVALID, BGK_E_HIP. */
 int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void *stream);
 

@@ -769,8 +769,8 @@ double orc_lid_shear(const orc_problem *p, const double *f)
  *        the vertical line through the middle of the cavity (the middle
  *        column, or the mean of the two middle columns for even nx), from
  *        the vortex centre (the zero of u met first going down from the lid)
- *        up to the lid, in units of the height H, times 2 (the reading that
- *        matches the reference values the Table quotes).
+ *        up to the lid, in units of the height H, as Sec. 5.2 defines it (the
+ *        paper gives no further normalisation).
  * u is taken as linear between cell centres (the zero by linear
  * interpolation) and extrapolated linearly over the half cell next to the
  * lid; with no zero the integral starts at the bottom wall. */
@@ -807,7 +807,7 @@ void orc_cavity_metrics(const orc_problem *p, const double *f, double *out /* [2
     for (int iy = top; iy < ny - 1; ++iy) G += 0.5 * (u[iy] + u[iy + 1]) * dy;
     double ulid = ny > 1 ? u[ny - 1] + 0.5 * (u[ny - 1] - u[ny - 2]) : u[ny - 1];
     G += 0.25 * dy * (u[ny - 1] + ulid);
-    out[1] = 2.0 * G / H;
+    out[1] = G / H;
     free(u);
     free(mom);
 }

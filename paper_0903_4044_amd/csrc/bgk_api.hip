@@ -1051,7 +1051,7 @@ extern "C" int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double
 // lid shear and the moments of the centre line.
 //   D = -L / (p0 U_W W): mean lid shear stress in units of p0 U_W, with
 //       p0 = 1/2 (n = T = 1) and W the lid width;
-//   G = 2 / H * int u dy, u = V_x / U_W on the line x = (x0 + x1) / 2 (the
+//   G = 1 / H * int u dy, u = V_x / U_W on the line x = (x0 + x1) / 2 (the
 //       middle column, or the mean of the two middle columns), from the
 //       first zero of u below the lid (the main vortex's centre; linear
 //       between cell centres) to the lid (u extrapolated linearly over the
@@ -1080,7 +1080,7 @@ static void centre_line_metrics(const Inst &I, const bgk_problem &p, const doubl
     for (int iy = lo; iy + 1 < ny; ++iy) area += 0.5 * h * (u[iy] + u[iy + 1]);
     const double ut = ny > 1 ? 1.5 * u[ny - 1] - 0.5 * u[ny - 2] : u[ny - 1];
     area += 0.25 * h * (u[ny - 1] + ut);
-    out[1] = 2.0 * area / H;
+    out[1] = area / H;
 }
 
 extern "C" int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void *stream)

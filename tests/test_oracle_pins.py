@@ -487,7 +487,8 @@ def test_shift_streaming_far_field_inflow(oracle_mod):
 
 # ------------------------------------------------------- cavity metrics
 # D and G of the Table of Sec. 5.2: mean lid shear stress over p0 U_W and
-# twice the main vortex's centre-line flow rate.
+# the main vortex's centre-line flow rate (the integral of V_x / U_W from the
+# vortex centre up to the lid, over the height).
 
 
 def metric_cfg(nx, ny, nv=(24, 16, 16)):
@@ -519,15 +520,15 @@ def test_lid_shear_metric_free_molecular_limit(oracle_mod):
 
 @pytest.mark.parametrize("nx", [6, 7])
 def test_vortex_flow_rate_linear_profile(oracle_mod, nx):
-    """u = s (y - a) + k (x - 1/2): on the centre line G = 2 int_a^1 u dy =
-    s (1 - a)^2, exact for the piecewise-linear rule; the x term vanishes
+    """u = s (y - a) + k (x - 1/2): on the centre line G = int_a^1 u dy =
+    s (1 - a)^2 / 2, exact for the piecewise-linear rule; the x term vanishes
     only at x = 1/2 (even nx: mean of the middle columns, odd nx: the middle
     column), so a wrong column changes G."""
     cfg = metric_cfg(nx, 10)
     O = oracle_mod.Oracle(cfg)
     for s, a in [(0.8, 0.37), (1.3, 0.61)]:
         f = shear_state(O, cfg, lambda x, y: s * (y - a) + 0.4 * (x - 0.5))
-        assert O.cavity_metrics(f)[1] == pytest.approx(s * (1 - a) ** 2, rel=1e-10)
+        assert O.cavity_metrics(f)[1] == pytest.approx(s * (1 - a) ** 2 / 2, rel=1e-10)
 
 
 def test_cavity_metrics_undefined_elsewhere(oracle_mod):
@@ -545,7 +546,7 @@ def test_vortex_flow_rate_takes_the_top_vortex(oracle_mod):
     def u(y):
         return (y - a) * (y - b)
 
-    exact = 2 * ((1 - b) ** 3 / 3 + (b - a) * (1 - b) ** 2 / 2)
+    exact = (1 - b) ** 3 / 3 + (b - a) * (1 - b) ** 2 / 2
     err = []
     for ny in (20, 40):
         cfg = metric_cfg(4, ny)
