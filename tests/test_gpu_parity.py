@@ -442,3 +442,90 @@ def test_workspace_is_the_callers(B):
     lam = torch.ones_like(x)
     assert L.bgk_step_adjoint(C.h, x.data_ptr(), lam.data_ptr(), y.data_ptr(), g.data_ptr(), None, s) == B.E_INVALID
     torch.cuda.synchronize()
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    return np.load(path) if os.path.exists(path) else None
+
+
+def test_cavity_128_fp32_golden(B):
+    """128^2 cavity, 24^3 velocities, FP32 f, lid Mach 0.1, Kn 0.1: moments
+    against the stored oracle run (tests/golden/make_golden.py) at every
+    stored step count, up to the workload's 5000 steps, within 1e-5."""
+    G = _golden("cavity_128_fp32_oracle.npz")
+    if G is None:
+        pytest.skip("golden file not generated")
+    cfg = inputs.config("cavity_128_fp32")
+    C = B.Context(cfg, "fp32")
+    assert C.dts[0] == pytest.approx(float(G["dt"]), rel=1e-14)
+    f = C.initial_state()
+    done, worst = 0, {}
+    for m in [int(s) for s in G["steps"]]:
+        f = C.step(f, n=m - done)
+        done = m
+        e = moment_errors(C.moments(f).cpu().numpy(), G[f"moments_{m}"], cfg)
+        worst[m] = e
+        assert max(e) <= 1e-5, (m, e)
+    print("cavity_128_fp32 moment errors by step:", {m: tuple(f"{x:.2e}" for x in e) for m, e in worst.items()})
+
+
+def test_batch_64_cavities_golden(B):
+    """The seeded batch of 64 uneven cavities in one FP32 context, on a
+    persistent grid (2 workgroups per compute unit walking all 425 472 work
+    items) with graph replay on a side stream: the instances whose oracle
+    runs are stored (tests/golden/make_batch_golden.py) match them within
+    1e-5 after 1, 10, 100 and 1000 steps.  Steps 100 to 1000 are nine
+    100-step calls ping-ponging between two buffers, so each of the two
+    captured graphs is replayed."""
+    import glob
+    import os
+    files = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "batch_cavity_*_oracle.npz")))
+    if not files:
+        pytest.skip("golden files not generated")
+    gold = [np.load(p) for p in files]
+    probs = inputs.batch_cavities()
+    C = B.Context(probs, "fp32")
+    shape = C.launch()
+    C.set_launch(shape["vec"], shape["unroll"], shape["vsplit"], 2)
+    for G in gold:
+        i = int(G["index"])
+        assert probs[i]["nx"] == int(G["side"]) and probs[i]["kn"] == pytest.approx(float(G["kn"]), rel=1e-15)
+        assert C.dts[i] == pytest.approx(float(G["dt"]), rel=1e-14)
+    side = torch.cuda.Stream()
+    seen = {}
+
+    def check(f, m):
+        mom = C.moments(f).cpu().numpy()
+        for G in gold:
+            if f"moments_{m}" not in G.files:
+                continue
+            i = int(G["index"])
+            c0 = C.cell_offsets[i]
+            ref = G[f"moments_{m}"]
+            e = moment_errors(mom[c0:c0 + ref.shape[0]], ref, probs[i])
+            seen[(i, m)] = e
+            assert max(e) <= 1e-5, (i, m, e)
+
+    with torch.cuda.stream(side):
+        C.set_graph(True)
+        x = C.initial_state()
+        a = C.empty()
+        b = C.empty()
+        C.step(x, a, n=1)
+        check(a, 1)
+        C.step(a, b, n=9)
+        check(b, 10)
+        C.step(b, a, n=90)
+        check(a, 100)
+        del x
+        src, dst = a, b
+        for _ in range(9):
+            C.step(src, dst, n=100)
+            src, dst = dst, src
+        check(src, 1000)
+        C.set_graph(False)
+    torch.cuda.synchronize()
+    assert any(m == 1000 for _, m in seen), "no stored instance reached 1000 steps"
+    print("batch moment errors:", {k: tuple(f"{x:.2e}" for x in e) for k, e in sorted(seen.items())})
