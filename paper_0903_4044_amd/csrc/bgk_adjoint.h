@@ -88,7 +88,8 @@ __global__ void __launch_bounds__(256) k_adj_sums(Args A, const real *__restrict
     const double *in = info + (long long)gc * NINFO;
     build_phi(g, in, T);
     const long long off = I.f0 + (long long)(gc - I.cell0) * g.nv;
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     double acc[NSUM] = {0, 0, 0, 0, 0, 0};
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
@@ -165,7 +166,8 @@ __global__ void __launch_bounds__(256) k_adj_apply(Args A, const real *__restric
     const double G0 = G[0], G1 = G[1], G2 = G[2], G3 = G[3], G4 = G[4], E = G[5];
     const real *mc = mu + I.f0 + (long long)(gc - I.cell0) * g.nv;
     real *oc = out + I.f0 + (long long)(gc - I.cell0) * g.nv;
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const double dV = g.dV;
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
@@ -369,7 +371,8 @@ __global__ void __launch_bounds__(256)
     const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));  // below 2^32 (init)
     const __amdgpu_buffer_rsrc_t frs = make_rsrc(fb, ibytes), lrs = make_rsrc(lb, ibytes);
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const bool lim = I.minmod != 0;
     const bool cav = I.kind == KIND_CAVITY;
     // walls whose emitted ghosts this cell's stencils read: 0 left, 1 right, 2 bottom, 3 top

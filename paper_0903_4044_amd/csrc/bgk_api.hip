@@ -301,7 +301,9 @@ static int vsplit_for(const bgk_ctx *c, int target_wg)
 // Default shape (measured on MI355X for the paper's grids; bgk_autotune refines it).
 static void choose_launch(bgk_ctx *c)
 {
-    c->vsplit_max = vsplit_for(c, 8192);
+    // up to 4 jz chunks per cell even on large grids: smaller work items keep
+    // the y-neighbour rows of the cells in flight resident in each XCD's L2
+    c->vsplit_max = std::max(vsplit_for(c, 8192), std::min(c->geo.nvz, 4));
     int vec = 1;
     for (int v : {4, 2})
         if (vec_valid(c, v)) { vec = v; break; }
@@ -1160,6 +1162,8 @@ static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
         const int v = std::min(vsplit_for(c, t), c->vsplit_max);
         if (std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
     }
+    for (int v : {2, 4})
+        if (v <= c->vsplit_max && std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
     auto measure = [&](const Cand &k, double *us) {
         set_shape(c, k.vec, k.unroll, k.vsplit, k.persist);
         return time_steps<real>(c, f, tmp, s, us);

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace bgk {
 
 constexpr int NVMAX = 128;        // per velocity component
@@ -125,6 +127,16 @@ __device__ __forceinline__ int strip_cell(const Inst &I, int q)
 }
 
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
+
+// The jz planes [z0, z1) of chunk `split` of `vsplit`: chunks start on even
+// planes (pairs of planes share one rounding hash), the last chunk takes an
+// odd last plane.
+__device__ __forceinline__ void chunk_bounds(int nvz, int vsplit, int split, int *z0, int *z1)
+{
+    const int npair = nvz >> 1;
+    *z0 = 2 * (split * npair / vsplit);
+    *z1 = split == vsplit - 1 ? nvz : 2 * ((split + 1) * npair / vsplit);
+}
 
 // The v_z axis.  Full velocity space: nodes v_z(k).  Reduced velocity space
 // (the projection the paper cites in Sec. 3 and Sec. 6): the components a
@@ -278,6 +290,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), BUF_WORD3);
 }
 
+// Buffer store of V (4, 8 or 16 bytes); NT marks it non-temporal (the slc
+// bit of the cache policy operand on this ISA family).
+template <typename V, bool NT>
+__device__ __forceinline__ void buf_st(V v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    constexpr int aux = NT ? 2 : 0;
+    if constexpr (sizeof(V) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, aux);
+    else if constexpr (sizeof(V) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vec_t<uint32_t, 2>, v), r, (int)voff, (int)soff, aux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(vec_t<uint32_t, 4>, v), r, (int)voff, (int)soff, aux);
+}
+
 template <typename V>
 __device__ __forceinline__ V buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -304,7 +330,8 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
     const int ii = find_inst(A.cell_prefix, A.ninst, gc);
     const Inst &I = A.inst[ii];
     const real *fc = f + I.f0 + (long long)(gc - I.cell0) * g.nv;
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const int ngrp = g.npl / VEC;
     double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = threadIdx.x; q < ngrp; q += blockDim.x) {
@@ -923,16 +950,18 @@ __device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp,
     return make_tap_at<real, VEC>(g, sp + slot * g.pe, SI.cell[slot], p0, jx0, jy);
 }
 
-// Second-order upwind value at the downwind face of cell u0 (upwind
-// neighbour um1, downwind neighbour u1) with slope factor k = (1 - C)/2.
-template <typename real>
-__device__ __forceinline__ real face_value(real um1, real u0, real u1, real k)
-{
-    return u0 + k * minmod3(u1 - u0, u0 - um1);
-}
-
 // Upwind flux difference along one direction, values in upwind order
 // (u_{-2}, u_{-1}, u_0, u_1), Courant magnitudes C and slope factors k = (1 - C)/2.
+// With d0 = u_0 - u_{-1} and the limited slopes m1 = minmod(u_1 - u_0, d0),
+// m0 = minmod(d0, u_{-1} - u_{-2}), the two face values differ by
+// face(u_0) - face(u_{-1}) = d0 + k (m1 - m0).
+template <typename real>
+__device__ __forceinline__ real fmadd(real a, real b, real c)
+{
+    if constexpr (sizeof(real) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 template <typename real, int VEC>
 __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_t<real, VEC> um1, vec_t<real, VEC> u0,
                                                       vec_t<real, VEC> u1, vec_t<real, VEC> C, vec_t<real, VEC> k)
@@ -940,9 +969,9 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
     vec_t<real, VEC> r;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-        const real fp = face_value(um1[e], u0[e], u1[e], k[e]);
-        const real fm = face_value(um2[e], um1[e], u0[e], k[e]);
-        r[e] = C[e] * (fp - fm);
+        const real d0 = u0[e] - um1[e];
+        const real m1 = minmod3(u1[e] - u0[e], d0), m0 = minmod3(d0, um1[e] - um2[e]);
+        r[e] = C[e] * fmadd(k[e], m1 - m0, d0);
     }
     return r;
 }
@@ -961,8 +990,13 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // the z-tables of the taps are re-laid out in LDS as [sign combination][jz]
 // [tap role][2] so that one vector address per plane reaches every tap's
 // pair through immediate offsets.
+// Waves per SIMD the compiler is held to: four for the one-residue 2D float
+// kernels with one jx per lane (their registers then stay at 128).
+template <typename real, int DIM, int VEC, bool ZU>
+constexpr int stream_waves() { return (sizeof(real) == 4 && DIM == 2 && VEC == 1 && ZU) ? 4 : 1; }
+
 template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_waves<real, DIM, VEC, ZU>())))
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
 {
@@ -1034,10 +1068,14 @@ __global__ void __launch_bounds__(256)
 
     const real *base = src + I.f0;
     real *outb = dst + I.f0;
-    // the instance's f as a buffer (its byte size is below 2^32, checked at init)
-    const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, (uint32_t)((long long)I.ncell * g.nv * sizeof(real)));
+    // the instance's f (input and output) as buffers (its byte size is below
+    // 2^32, checked at init)
+    const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));
+    const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, ibytes);
+    const __amdgpu_buffer_rsrc_t ors = make_rsrc(outb, ibytes);
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const bool lim = I.minmod != 0;
     const int ngx = g.nvx / VEC, ngroups = ngx * g.nvy, ntask = ngroups * A.zr;
     const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
@@ -1090,7 +1128,11 @@ __global__ void __launch_bounds__(256)
         // hp: the hashes of this plane pair when the caller computed them
         // (have), for two consecutive planes of one stage.
         using U = vec_t<uint32_t, VEC>;
-        auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo, U hp, bool have) {
+        // have_c: std::true_type when the caller passes the plane pair's hash
+        // in hp (one-residue float forms, whose chunks start on even planes),
+        // std::false_type when each element hashes its own index
+        auto finish = [&](const V (&hv)[NT], int jz, uint32_t zo, U hp, auto have_c) {
+            constexpr bool HAVE = decltype(have_c)::value;
             real ta[NT], tb[NT];  // the taps' z-table values at plane jz
             if constexpr (ZU) {
                 const real *row = tzl + jz * (NROLE * 2);
@@ -1125,12 +1167,18 @@ __global__ void __launch_bounds__(256)
                 // one velocity column, keyed by the even member's index), low
                 // half for the even plane
                 const bool odd = (jz & 1) != 0;
-                const uint32_t ieven = ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real) - (odd ? (uint32_t)g.npl : 0u);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const real M = tc.l1[e] * a + tc.l2[e] * b;
                     const real d = __builtin_fmaf(c0m1_hi, hv[0][e], __builtin_fmaf(c0m1_lo, hv[0][e], M)) - (dx[e] + dy[e]);
-                    const uint32_t hb = have ? hp[e] : hash32((ieven + (uint32_t)e) ^ key);
+                    uint32_t hb;
+                    if constexpr (HAVE) {
+                        hb = hp[e];
+                    } else {
+                        const uint32_t ieven =
+                            ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real) - (odd ? (uint32_t)g.npl : 0u);
+                        hb = hash32((ieven + (uint32_t)e) ^ key);
+                    }
                     // bits 0-15 for the even plane, 16-31 for the odd one
                     r[e] = round_stochastic16((double)hv[0][e] + (double)d,
                                               __builtin_amdgcn_ubfe(hb, odd ? 16u : 0u, 16u));
@@ -1138,12 +1186,18 @@ __global__ void __launch_bounds__(256)
             } else {
                 r = u0 - dx - dy;
             }
-            V *op = reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo + (uint32_t)(p0 * sizeof(real)));
-            if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
-            else *op = r;
-            double s = 0.0;
+            if constexpr (ZU) {
+                // buffer store: lane offset of the group, wave-uniform offset of the plane
+                buf_st<V, NTSTORE>(r, ors, (uint32_t)(p0 * sizeof(real)), __builtin_amdgcn_readfirstlane(out0 + zo));
+            } else {
+                V *op = reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo + (uint32_t)(p0 * sizeof(real)));
+                if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
+                else *op = r;
+            }
+            double s = (double)r[0];
+            A0[0] += s;
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) {
+            for (int k = 1; k < VEC; ++k) {
                 const double hk = (double)r[k];
                 A0[k] += hk;
                 s += hk;
@@ -1184,17 +1238,21 @@ __global__ void __launch_bounds__(256)
                 }
             };
             auto compute_stage = [&](const V (&h)[UNR][NT], int j, uint32_t off) {
-                // two consecutive planes (one residue, even j): one hash per pair
-                U hp = 0;
-                const bool have = sizeof(real) == 4 && UNR == 2 && ZU && (j & 1) == 0 && j + 1 < z1;
-                if (have) {
+                if constexpr (sizeof(real) == 4 && UNR == 2 && ZU) {
+                    // one residue, chunks starting on even planes, two planes per
+                    // stage: j is even, and one hash serves the pair (j, j + 1)
+                    U hp;
                     const uint32_t ieven = ecell + (uint32_t)p0 + off / (uint32_t)sizeof(real);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) hp[e] = hash32((ieven + (uint32_t)e) ^ key);
-                }
+                    finish(h[0], j, off, hp, std::true_type{});
+                    if (j + 1 < z1) finish(h[1], j + 1, off + zr_off, hp, std::true_type{});
+                } else {
 #pragma unroll
-                for (int u = 0; u < UNR; ++u)
-                    if (j + u * A.zr < z1) finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off, hp, have);
+                    for (int u = 0; u < UNR; ++u)
+                        if (j + u * A.zr < z1)
+                            finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off, U(0), std::false_type{});
+                }
             };
             if constexpr (UNR == 2) {
                 V ha[UNR][NT], hb[UNR][NT];
@@ -1213,22 +1271,19 @@ __global__ void __launch_bounds__(256)
                 }
             } else {
                 // One plane per stage.  With one residue a lane's planes are
-                // consecutive, and the random bits of an even plane are kept
-                // for its odd partner.
+                // consecutive from an even first plane, and the random bits of
+                // an even plane are kept for its odd partner.
                 U hcar = 0;
-                const int jfirst = jz;
                 auto stage1 = [&](const V (&h)[1][NT], int j, uint32_t off) {
                     if constexpr (sizeof(real) == 4 && ZU) {
                         if ((j & 1) == 0) {
                             const uint32_t ieven = ecell + (uint32_t)p0 + off / (uint32_t)sizeof(real);
 #pragma unroll
                             for (int e = 0; e < VEC; ++e) hcar[e] = hash32((ieven + (uint32_t)e) ^ key);
-                            finish(h[0], j, off, hcar, true);
-                        } else {
-                            finish(h[0], j, off, hcar, j > jfirst);
                         }
+                        finish(h[0], j, off, hcar, std::true_type{});
                     } else {
-                        finish(h[0], j, off, hcar, false);
+                        finish(h[0], j, off, hcar, std::false_type{});
                     }
                 };
                 if constexpr (PD == 1) {
@@ -1338,7 +1393,8 @@ __global__ void __launch_bounds__(256)
         real *outb = dst + I.f0;
         const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, (uint32_t)((long long)I.ncell * g.nv * sizeof(real)));
         const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
-        const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+        int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
         const int ntask = g.npl * A.zr;
         const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
         const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;
@@ -1462,7 +1518,8 @@ __global__ void __launch_bounds__(256) k_final(Args A, const real *src, real *ds
     const real *sc = src + off;
     real *dc = dst + off;
     const real *E = params + (long long)gc * g.pe;
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const real c0 = E[0];
     const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 1) : 0u;
     const double c0d = sizeof(real) == 4 ? *reinterpret_cast<const double *>(E + 2) : 0.0;
@@ -1519,7 +1576,8 @@ __global__ void __launch_bounds__(256) k_init(Args A, real *__restrict__ f)
     }
     const double P = n * pi_t_m32(T);
     const long long off = I.f0 + (long long)c * g.nv;
-    const int z0 = split * g.nvz / A.vsplit, z1 = (split + 1) * g.nvz / A.vsplit;
+    int z0, z1;
+    chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
         const double dx = vnode(g, 0, jx) - V, vy = vnode(g, 1, jy);
