@@ -133,6 +133,14 @@ static Args make_args(const bgk_ctx *c)
     return a;
 }
 
+// LDS of the streaming kernel after its tables: 8 bytes of alignment, the
+// per-thread moment sums (NQ doubles per thread) and the node tables (v_z
+// and v_z^2 per plane, v_x, v_y).
+static size_t stream_acc_bytes(const Geo &g, int block)
+{
+    return 8 + ((size_t)NQ * block + 2 * g.nvz + g.nvx + g.nvy) * sizeof(double);
+}
+
 static void drop_graphs(bgk_ctx *c);
 
 static void release(bgk_ctx *c)
@@ -393,7 +401,7 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
             lds_max <= 0)
             lds_max = 65536;
         const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
-        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack;
+        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack + stream_acc_bytes(g, 256);
         const size_t adj = (c->dim == 2 ? 17 : 9) * entry + slack;
         c->lds_max = lds_max;
         if (fwd > (size_t)lds_max) {
@@ -617,10 +625,12 @@ static size_t role_table_bytes(const bgk_ctx *c, bool adjoint)
 }
 
 // The one-residue form needs every lane of a wave on one plane (zr = 1) and
-// its role tables to fit in LDS next to the slot entries.
-static bool use_roles(const bgk_ctx *c, int zr, size_t lds, bool adjoint)
+// its role tables to fit in LDS next to the slot entries (and, for the
+// streaming kernel, the moment sums).
+static bool use_roles(const bgk_ctx *c, int zr, size_t lds, bool adjoint, int block = 0)
 {
-    return zr == 1 && lds + role_table_bytes(c, adjoint) + 4096 <= (size_t)c->lds_max;
+    return zr == 1 && lds + role_table_bytes(c, adjoint) + (adjoint ? 0 : stream_acc_bytes(c->geo, block)) + 4096 <=
+                          (size_t)c->lds_max;
 }
 
 static bool stream_nt(const bgk_ctx *c)
@@ -636,12 +646,13 @@ template <typename real, int DIM, int VEC, int UNR, int PD, bool NTS>
 static void stream_kernel_z(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
     const real *p = (const real *)params_buf<real>(c, c->pass_parity);
-    if (use_roles(c, c->zr, lds, false))  // one plane per wave: role-ordered z-tables after the slots
+    const size_t acc = stream_acc_bytes(c->geo, c->sblock);
+    if (use_roles(c, c->zr, lds, false, c->sblock))  // one plane per wave: role-ordered z-tables after the slots
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, PD, NTS, true>), dim3(nb), dim3(c->sblock),
-                           lds + role_table_bytes(c, false), s, make_args(c), (const real *)src, (real *)dst, p,
-                           c->partial);
+                           lds + role_table_bytes(c, false) + acc, s, make_args(c), (const real *)src, (real *)dst,
+                           p, c->partial);
     else
-        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, 1, NTS, false>), dim3(nb), dim3(c->sblock), lds, s,
+        hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, 1, NTS, false>), dim3(nb), dim3(c->sblock), lds + acc, s,
                            make_args(c), (const real *)src, (real *)dst, p, c->partial);
 }
 

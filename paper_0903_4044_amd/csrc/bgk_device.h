@@ -261,6 +261,21 @@ __device__ __forceinline__ void fold_column(double (&acc)[NQ], double vx, double
     acc[8] += vy > 0.0 ? vy * A0 : 0.0;
 }
 
+// The same fold into this thread's slots of the workgroup's LDS accumulators
+// (acc[q * stride]): the nine sums do not occupy registers across a task.
+// The sums pass through fold_column itself, so the arithmetic (and its
+// rounding) is that of the register form.
+__device__ __forceinline__ void fold_column_lds(double *acc, int stride, double vx, double vy, double A0, double Az,
+                                                double Azz)
+{
+    double t[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) t[q] = acc[q * stride];
+    fold_column(t, vx, vy, A0, Az, Azz);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q * stride] = t[q];
+}
+
 template <typename T, int N>
 using vec_t = T __attribute__((ext_vector_type(N)));
 
@@ -288,20 +303,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
     void *p = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), BUF_WORD3);
-}
-
-// Buffer store of V (4, 8 or 16 bytes); NT marks it non-temporal (the slc
-// bit of the cache policy operand on this ISA family).
-template <typename V, bool NT>
-__device__ __forceinline__ void buf_st(V v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    constexpr int aux = NT ? 2 : 0;
-    if constexpr (sizeof(V) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, aux);
-    else if constexpr (sizeof(V) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vec_t<uint32_t, 2>, v), r, (int)voff, (int)soff, aux);
-    else
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(vec_t<uint32_t, 4>, v), r, (int)voff, (int)soff, aux);
 }
 
 template <typename V>
@@ -882,7 +883,7 @@ __global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__
 // Slots: 0 centre; 1 + 3*si + m (x direction), 7 + 3*si + m (y direction),
 // si = 0 for s = +1, 1 for s = -1; m = 0, 1, 2 for k = -2, -1, +1.
 
-struct SlotInfo { int cell[13]; int par[13]; };
+struct SlotInfo { int cell[13]; int par[13]; uint32_t off[13]; };  // off: byte offset of the slot cell's h
 
 __device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int pos, int other, int sgn, int own, int *cell, int *par)
 {
@@ -950,6 +951,26 @@ __device__ __forceinline__ Tap<real, VEC> make_tap(const Geo &g, const real *sp,
     return make_tap_at<real, VEC>(g, sp + slot * g.pe, SI.cell[slot], p0, jx0, jy);
 }
 
+// The same with the slot cell's byte offset from the workgroup's slot table
+// (computed once per work item instead of a 32-bit product per lane and tap).
+template <typename real, int VEC>
+__device__ __forceinline__ Tap<real, VEC> make_tap_slot(const Geo &g, const real *sp, const SlotInfo &SI, int slot,
+                                                        int p0, int jx0, int jy)
+{
+    const real *E = sp + slot * g.pe;
+    Tap<real, VEC> t;
+    t.off = SI.off[slot] + (uint32_t)(p0 * (int)sizeof(real));
+    t.tz = E + g.tz;
+    t.c0 = E[0];
+    const real y1 = E[g.ty1 + jy], y2 = E[g.ty2 + jy];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        t.l1[k] = E[g.tx1 + jx0 + k] * y1;
+        t.l2[k] = E[g.tx2 + jx0 + k] * y2;
+    }
+    return t;
+}
+
 // Upwind flux difference along one direction, values in upwind order
 // (u_{-2}, u_{-1}, u_0, u_1), Courant magnitudes C and slope factors k = (1 - C)/2.
 // With d0 = u_0 - u_{-1} and the limited slopes m1 = minmod(u_1 - u_0, d0),
@@ -990,13 +1011,13 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 // the z-tables of the taps are re-laid out in LDS as [sign combination][jz]
 // [tap role][2] so that one vector address per plane reaches every tap's
 // pair through immediate offsets.
-// Waves per SIMD the compiler is held to: four for the one-residue 2D float
-// kernels with one jx per lane (their registers then stay at 128).
-template <typename real, int DIM, int VEC, bool ZU>
-constexpr int stream_waves() { return (sizeof(real) == 4 && DIM == 2 && VEC == 1 && ZU) ? 4 : 1; }
+// Byte offset of the per-thread moment sums in the streaming kernel's dynamic
+// LDS: after `elems` table values, 8-byte aligned.
+template <typename real>
+__host__ __device__ constexpr size_t stream_acc_offset(size_t elems) { return (elems * sizeof(real) + 7) & ~(size_t)7; }
 
 template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream_waves<real, DIM, VEC, ZU>())))
+__global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
 {
@@ -1005,17 +1026,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
     constexpr int NSLOT = DIM == 1 ? 7 : 13;
     real *sp = reinterpret_cast<real *>(smem);
     __shared__ SlotInfo SI;
-    // v_z and v_z^2 of every plane (wave-uniform per plane: one LDS broadcast
-    // instead of recomputing them per lane); in reduced velocity space the
-    // planes' mass shares and energy terms (the column fold takes the mass
-    // from the first sum there; reduced contexts run with VEC = 1)
-    __shared__ double vzt[NVMAX][2];
     const Geo &g = A.g;
+    constexpr int NROLE = DIM == 1 ? 4 : 7;   // centre, x (-2, -1, +1), y (-2, -1, +1)
+    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
+    // Dynamic LDS: the slot entries (NSLOT table entries), the role-ordered
+    // z-tables (one-residue form), then 8-byte aligned: this thread's moment
+    // sums (acc[q * blockDim.x]) and the node tables, v_z and v_z^2 of every
+    // plane (vzt[2 jz], vzt[2 jz + 1]; wave-uniform per plane: one LDS
+    // broadcast instead of recomputing them per lane; in reduced velocity
+    // space the planes' mass shares and energy terms -- the column fold takes
+    // the mass from the first sum there, reduced contexts run with VEC = 1),
+    // v_x and v_y of every node (the lane constants of a task and the column
+    // fold read them instead of recomputing the nodes in double).
+    double *const acc_base = reinterpret_cast<double *>(
+        smem + stream_acc_offset<real>(NSLOT * g.pe + (ZU ? NCOMBO * g.nvz * NROLE * 2 : 0)));
+    double *const vzt = acc_base + NQ * blockDim.x;
+    double *const vxt = vzt + 2 * g.nvz;
+    double *const vyt = vxt + g.nvx;
     for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
         const ZW w = zweights(g, k);
-        vzt[k][0] = g.red ? w.m : w.z;
-        vzt[k][1] = w.zz;
+        vzt[2 * k] = g.red ? w.m : w.z;
+        vzt[2 * k + 1] = w.zz;
     }
+    for (int k = threadIdx.x; k < g.nvx; k += blockDim.x) vxt[k] = vnode(g, 0, k);
+    for (int k = threadIdx.x; k < g.nvy; k += blockDim.x) vyt[k] = vnode(g, 1, k);
     // (the first barrier of the item loop orders these writes before any read)
     // Work items (cell, jz chunk).  A grid smaller than the item count makes
     // the kernel persistent: each workgroup walks items gridDim.x apart (a
@@ -1043,6 +1077,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
         }
         SI.cell[s] = cell;
         SI.par[s] = par;
+        SI.off[s] = (uint32_t)cell * (uint32_t)g.nv * (uint32_t)sizeof(real);  // instance bytes < 2^32 (init)
     }
     __syncthreads();
     for (int t = threadIdx.x; t < NSLOT * g.pe; t += blockDim.x) {
@@ -1050,8 +1085,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
         sp[t] = params[(long long)SI.par[s] * g.pe + o];
     }
     __syncthreads();
-    constexpr int NROLE = DIM == 1 ? 4 : 7;   // centre, x (-2, -1, +1), y (-2, -1, +1)
-    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
     real *tzr = sp + NSLOT * g.pe;           // [combo][jz][role][2]
     if constexpr (ZU) {
         const int n = NCOMBO * g.nvz * NROLE;
@@ -1068,11 +1101,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
 
     const real *base = src + I.f0;
     real *outb = dst + I.f0;
-    // the instance's f (input and output) as buffers (its byte size is below
-    // 2^32, checked at init)
-    const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));
-    const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, ibytes);
-    const __amdgpu_buffer_rsrc_t ors = make_rsrc(outb, ibytes);
+    // the instance's f as a buffer (its byte size is below 2^32, checked at init)
+    const __amdgpu_buffer_rsrc_t frs = make_rsrc(base, (uint32_t)((long long)I.ncell * g.nv * sizeof(real)));
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
     int z0, z1;
     chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
@@ -1084,24 +1114,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
     // the centre entry's c0 - 1 as a two-float sum (float path)
     const double c0m1 = sizeof(real) == 4 ? *reinterpret_cast<const double *>(sp + 2) - 1.0 : 0.0;
     const float c0m1_hi = (float)c0m1, c0m1_lo = (float)(c0m1 - (double)c0m1_hi);
-    double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double *acc = acc_base + threadIdx.x;  // this thread's moment sums, zeroed per work item
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q * blockDim.x] = 0.0;
 
+    // (jx group, jy) of a one-residue task by a float reciprocal: task <
+    // 2^14 and ngx <= 128, so (task + 1/2) / ngx stays at least 1/256 away
+    // from an integer, far beyond the product's rounding error
+    const float inv_ngx = 1.0f / (float)ngx;
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
-        const int pg = task % ngroups, zr = ZU ? 0 : task / ngroups;
-        const int jy = pg / ngx, jx0 = (pg - jy * ngx) * VEC;
+        int pg, zr, jy;
+        if constexpr (ZU) {
+            pg = task;
+            zr = 0;
+            jy = (int)(((float)task + 0.5f) * inv_ngx);
+        } else {
+            pg = task % ngroups;
+            zr = task / ngroups;
+            jy = pg / ngx;
+        }
+        const int jx0 = (pg - jy * ngx) * VEC;
         const int p0 = jy * g.nvx + jx0;
         V Cx, kx;
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
-            Cx[k] = (real)(fabs(vnode(g, 0, jx0 + k)) * I.cx);
+            Cx[k] = (real)(fabs(vxt[jx0 + k]) * I.cx);
             kx[k] = lim ? (real)0.5 * ((real)1 - Cx[k]) : (real)0;
         }
-        const double vy = vnode(g, 1, jy);
-        const int sx = vnode(g, 0, jx0) > 0.0 ? 0 : 1;
-        const Tap<real, VEC> tc = make_tap<real, VEC>(g, sp, SI, 0, p0, jx0, jy);
-        const Tap<real, VEC> xa = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 0, p0, jx0, jy);
-        const Tap<real, VEC> xb = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 1, p0, jx0, jy);
-        const Tap<real, VEC> xd = make_tap<real, VEC>(g, sp, SI, 1 + 3 * sx + 2, p0, jx0, jy);
+        const double vy = vyt[jy];
+        const int sx = vxt[jx0] > 0.0 ? 0 : 1;
+        const Tap<real, VEC> tc = make_tap_slot<real, VEC>(g, sp, SI, 0, p0, jx0, jy);
+        const Tap<real, VEC> xa = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 0, p0, jx0, jy);
+        const Tap<real, VEC> xb = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 1, p0, jx0, jy);
+        const Tap<real, VEC> xd = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 2, p0, jx0, jy);
         Tap<real, VEC> ya, yb, yd;
         V Cy = 0, ky = 0;
         if constexpr (DIM == 2) {
@@ -1109,9 +1154,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
             const real cy = (real)(fabs(vy) * I.cy);
             Cy = cy;
             ky = lim ? (real)0.5 * ((real)1 - cy) : (real)0;
-            ya = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 0, p0, jx0, jy);
-            yb = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 1, p0, jx0, jy);
-            yd = make_tap<real, VEC>(g, sp, SI, 7 + 3 * sy + 2, p0, jx0, jy);
+            ya = make_tap_slot<real, VEC>(g, sp, SI, 7 + 3 * sy + 0, p0, jx0, jy);
+            yb = make_tap_slot<real, VEC>(g, sp, SI, 7 + 3 * sy + 1, p0, jx0, jy);
+            yd = make_tap_slot<real, VEC>(g, sp, SI, 7 + 3 * sy + 2, p0, jx0, jy);
         }
         double A0[VEC];
 #pragma unroll
@@ -1186,14 +1231,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
             } else {
                 r = u0 - dx - dy;
             }
-            if constexpr (ZU) {
-                // buffer store: lane offset of the group, wave-uniform offset of the plane
-                buf_st<V, NTSTORE>(r, ors, (uint32_t)(p0 * sizeof(real)), __builtin_amdgcn_readfirstlane(out0 + zo));
-            } else {
-                V *op = reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo + (uint32_t)(p0 * sizeof(real)));
-                if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
-                else *op = r;
-            }
+            V *op = reinterpret_cast<V *>(reinterpret_cast<char *>(outb) + out0 + zo + (uint32_t)(p0 * sizeof(real)));
+            if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
+            else *op = r;
             double s = (double)r[0];
             A0[0] += s;
 #pragma unroll
@@ -1202,8 +1242,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
                 A0[k] += hk;
                 s += hk;
             }
-            Az += vzt[jz][0] * s;
-            Azz += vzt[jz][1] * s;
+            Az += vzt[2 * jz] * s;
+            Azz += vzt[2 * jz + 1] * s;
         };
         // Software pipeline: the loads of the next UNR jz planes are issued
         // before the current ones are relaxed and streamed, so every wave keeps
@@ -1218,7 +1258,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
         const int zs = UNR * A.zr;
         int jz = z0 + zr;
         if (jz < z1) {
-            const int zlast = z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);  // last jz of this lane's residue
+            const int zlast = ZU ? z1 - 1 : z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);  // last jz of this lane's residue
             const uint32_t zlast_off = (uint32_t)zlast * zstep, zr_off = (uint32_t)A.zr * zstep;
             const uint32_t zs_off = (uint32_t)zs * zstep;
             uint32_t zoff = (uint32_t)jz * zstep;
@@ -1320,10 +1360,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stream
         }
 #pragma unroll
         for (int k = 0; k < VEC; ++k)
-            if (g.red) fold_column(acc, vnode(g, 0, jx0 + k), vy, k == 0 ? Az : 0.0, 0.0, k == 0 ? Azz : 0.0);
-            else fold_column(acc, vnode(g, 0, jx0 + k), vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
+            if (g.red) fold_column_lds(acc, blockDim.x, vxt[jx0 + k], vy, k == 0 ? Az : 0.0, 0.0, k == 0 ? Azz : 0.0);
+            else fold_column_lds(acc, blockDim.x, vxt[jx0 + k], vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
     }
-    block_sum_store<NQ>(acc, partial + (long long)L * NQ);
+    {
+        double sums[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sums[q] = acc[q * blockDim.x];
+        block_sum_store<NQ>(sums, partial + (long long)L * NQ);
+    }
     __syncthreads();  // LDS (slots, tables, reduction) is reused by the next item
     }
 }

@@ -529,3 +529,31 @@ def test_batch_64_cavities_golden(B):
     torch.cuda.synchronize()
     assert any(m == 1000 for _, m in seen), "no stored instance reached 1000 steps"
     print("batch moment errors:", {k: tuple(f"{x:.2e}" for x in e) for k, e in sorted(seen.items())})
+
+
+@pytest.mark.parametrize("name", ["shock_m3_fp32", "cavity_128_fp32"])
+def test_every_shape_full_size(B, oracle_mod, name):
+    """Every launch shape on the full Mach-3 shock (1024 x 48^3) and the full
+    128^2 x 24^3 cavity, FP32, two steps from the initial state: every element
+    written (the step's output starts as NaN) and the moments within 1e-5 of
+    the oracle.  The register-heaviest kernels (four jx per lane, deep jz
+    pipelines) exist only at such sizes in the tuned shapes."""
+    cfg = inputs.config(name)
+    O = oracle_mod.Oracle(cfg)
+    ref = O.moments(O.step(O.initial_state(), 2))
+    C = B.Context(cfg, "fp32", tune="off")
+    x = C.initial_state()
+    ran = 0
+    for vec in (1, 2, 4):
+        for unroll in (1, 2, 3, 4):
+            for vsplit in (1, 2):
+                for persist in (0, 2):
+                    try:
+                        C.set_launch(vec, unroll, vsplit, persist)
+                    except B.BGKError:
+                        continue
+                    y = C.step(x, n=2)
+                    e = moment_errors(C.moments(y).cpu().numpy(), ref, cfg)
+                    assert max(e) <= 1e-5, (vec, unroll, vsplit, persist, e)
+                    ran += 1
+    assert ran >= 16
