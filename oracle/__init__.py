@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bgk_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3}
+KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3, "cavity3d": 4, "periodic3d": 5}
 
 
 class Problem(ctypes.Structure):
@@ -41,6 +41,8 @@ class Problem(ctypes.Structure):
         ("strang", ctypes.c_int), ("minmod", ctypes.c_int),
         ("conservative", ctypes.c_int),
         ("reduced", ctypes.c_int),
+        ("nz", ctypes.c_int),
+        ("z0", ctypes.c_double), ("z1", ctypes.c_double),
     ]
 
 
@@ -118,6 +120,10 @@ def make_problem(cfg: dict) -> Problem:
     p.minmod = {"minmod": 1, "none": 0, "shift": 2}[cfg.get("limiter", "minmod")]
     p.conservative = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
     p.reduced = 1 if cfg.get("reduced", False) else 0
+    p.nz = int(cfg.get("nz", 1))
+    p.z0, p.z1 = float(cfg.get("z0", 0.0)), float(cfg.get("z1", 1.0))
+    if cfg["kind"] in ("cavity3d", "periodic3d") and p.reduced:
+        raise ValueError("the reduced velocity space is defined for one- and two-dimensional kinds")
     two = cfg["kind"] in ("cavity", "periodic2d")
     if p.reduced and (int(cfg["nv"][2]) != 2 or (not two and int(cfg["nv"][1]) != 1)):
         raise ValueError("the reduced velocity space takes nv[2] = 2 (and nv[1] = 1 for one-dimensional kinds)")
@@ -131,10 +137,12 @@ class Oracle:
         self.cfg = dict(cfg)
         self.p = make_problem(cfg)
         self.L = lib()
+        self.three_d = cfg["kind"] in ("cavity3d", "periodic3d")
         self.two_d = cfg["kind"] in ("cavity", "periodic2d")
         self.nx = self.p.nx
-        self.ny = self.p.ny if self.two_d else 1
-        self.ncell = self.nx * self.ny
+        self.ny = self.p.ny if (self.two_d or self.three_d) else 1
+        self.nz = self.p.nz if self.three_d else 1
+        self.ncell = self.nx * self.ny * self.nz
         self.nv = tuple(int(v) for v in cfg["nv"])
         self.nvel = self.nv[0] * self.nv[1] * self.nv[2]
         self.shape = (self.ncell, self.nvel)
@@ -228,8 +236,9 @@ class Oracle:
 
     # -- reverse sweep (hand-derived adjoint) -----------------------------
     def _no_conservative(self):
-        if self.p.conservative or self.p.reduced:
-            raise NotImplementedError("the reverse sweep covers the point-value Maxwellian in full velocity space only")
+        if self.p.conservative or self.p.reduced or self.three_d:
+            raise NotImplementedError("the reverse sweep covers the point-value Maxwellian in full velocity space, "
+                                      "one- and two-dimensional kinds")
 
     def relax_adjoint(self, x, mu, tau):
         """(dR_tau/dx)^T mu at x, and dL/dKn."""

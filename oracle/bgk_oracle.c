@@ -45,7 +45,11 @@
  *     values (their densities already come from Eq. (RH) and from the
  *     zero-mass-flux rule).
  *
- * Storage: f[cell][jz][jy][jx] (velocity fastest), cell = iy * nx + ix.
+ *   - the three-dimensional extension (Sec. 2.1: the method carries over to
+ *     two and three spatial dimensions, one upwind stencil per direction):
+ *     a cube with six diffuse walls, the lid (y = y1) moving along x.
+ *
+ * Storage: f[cell][jz][jy][jx] (velocity fastest), cell = (iz * ny + iy) * nx + ix.
  * Everything is double precision.  Loops are plain; OpenMP only splits the
  * loop over spatial cells.
  */
@@ -57,6 +61,8 @@
 #define ORC_CAVITY 1
 #define ORC_PERIODIC1 2
 #define ORC_PERIODIC2 3
+#define ORC_CAVITY3 4
+#define ORC_PERIODIC3 5
 
 typedef struct {
     int kind;
@@ -77,14 +83,22 @@ typedef struct {
                     holds g = int f dv_z, plane 1 h = int v_z^2 f dv_z), v_y and v_z for
                     one-dimensional kinds (nv[1] = 1, nv[2] = 2; g = int f dv_y dv_z,
                     h = int (v_y^2 + v_z^2) f dv_y dv_z) */
+    int nz;         /* three-dimensional kinds: cells along z */
+    double z0, z1;  /* and the box along z */
 } orc_problem;
 
 static const double GAMMA = 5.0 / 3.0;
 
 /* ------------------------------------------------------------------ grid */
 
+static int is3d(const orc_problem *p) { return p->kind == ORC_CAVITY3 || p->kind == ORC_PERIODIC3; }
 static int is2d(const orc_problem *p) { return p->kind == ORC_CAVITY || p->kind == ORC_PERIODIC2; }
-static long ncell(const orc_problem *p) { return (long)p->nx * (is2d(p) ? p->ny : 1); }
+/* streaming directions of the problem */
+static int ndim(const orc_problem *p) { return is3d(p) ? 3 : is2d(p) ? 2 : 1; }
+static long ncell(const orc_problem *p)
+{
+    return (long)p->nx * (ndim(p) >= 2 ? p->ny : 1) * (ndim(p) == 3 ? p->nz : 1);
+}
 static long nvel(const orc_problem *p) { return (long)p->nv[0] * p->nv[1] * p->nv[2]; }
 /* number of velocity components integrated out (0: full velocity space) */
 static int nred(const orc_problem *p) { return p->reduced ? (is2d(p) ? 1 : 2) : 0; }
@@ -98,6 +112,7 @@ static double dvel(const orc_problem *p, int a)
 static double dvol(const orc_problem *p) { return dvel(p, 0) * dvel(p, 1) * dvel(p, 2); }
 static double dxs(const orc_problem *p) { return (p->x1 - p->x0) / p->nx; }
 static double dys(const orc_problem *p) { return (p->y1 - p->y0) / p->ny; }
+static double dzs(const orc_problem *p) { return (p->z1 - p->z0) / p->nz; }
 
 /* Velocity of every node, Sec. 2.1: cell centres of a box cut into equal
  * cells, v_a(k) = lo_a + (k + 1/2) dv_a.  Returned as three arrays of Nv,
@@ -157,10 +172,14 @@ double orc_dt(const orc_problem *p)
     double m = 0.0;
     for (int jx = 0; jx < p->nv[0]; ++jx) {
         double ax = fabs(p->vlo[0] + (jx + 0.5) * dvel(p, 0)) / dxs(p);
-        if (!is2d(p)) { if (ax > m) m = ax; continue; }
+        if (ndim(p) == 1) { if (ax > m) m = ax; continue; }
         for (int jy = 0; jy < p->nv[1]; ++jy) {
             double ay = fabs(p->vlo[1] + (jy + 0.5) * dvel(p, 1)) / dys(p);
-            if (ax + ay > m) m = ax + ay;
+            if (ndim(p) == 2) { if (ax + ay > m) m = ax + ay; continue; }
+            for (int jz = 0; jz < p->nv[2]; ++jz) {
+                double az = fabs(p->vlo[2] + (jz + 0.5) * dvel(p, 2)) / dzs(p);
+                if (ax + ay + az > m) m = ax + ay + az;
+            }
         }
     }
     return p->cfl / m;
@@ -425,11 +444,13 @@ static void wall_maxwellian(const orc_problem *p, const velgrid *g, double uw, d
 }
 
 /* Walls are numbered 0 left (x = x0, inward normal +x), 1 right (-x),
- * 2 bottom (y = y0, +y), 3 top / lid (-y, moving with speed U_W along x). */
+ * 2 bottom (y = y0, +y), 3 top / lid (-y, moving with speed U_W along x),
+ * and in three dimensions 4 back (z = z0, +z) and 5 front (-z): wall w lies
+ * across axis w / 2, on the low side for even w. */
 static void wall_normal(int w, int *axis, double *sign)
 {
-    *axis = (w < 2) ? 0 : 1;
-    *sign = (w == 0 || w == 2) ? 1.0 : -1.0;
+    *axis = w / 2;
+    *sign = (w % 2 == 0) ? 1.0 : -1.0;
 }
 
 /* Wall density of Eq. (bc_cavity): the emitted Maxwellian carries the mass
@@ -439,7 +460,7 @@ static void wall_normal(int w, int *axis, double *sign)
  * g0 being the wall-adjacent cell. */
 static double wall_density(const velgrid *g, int axis, double sign, const double *g0, const double *phiw)
 {
-    const double *va = axis == 0 ? g->vx : g->vy;
+    const double *va = axis == 0 ? g->vx : axis == 1 ? g->vy : g->vz;
     double num = 0.0, den = 0.0;
     for (long j = 0; j < g->nv; ++j) {
         double vn = sign * va[j];
@@ -555,41 +576,56 @@ void orc_stream(const orc_problem *p, const double *gs, double *out, double dt)
         return;
     }
     velgrid g = make_velgrid(p);
-    const int two = is2d(p);
-    const int nx = p->nx, ny = two ? p->ny : 1;
+    const int dim = ndim(p);
+    const int nx = p->nx, ny = dim >= 2 ? p->ny : 1, nz = dim == 3 ? p->nz : 1;
     const long nv = nvel(p);
-    const int px = nx + 4, py = two ? ny + 4 : 1, oy = two ? 2 : 0;
-    double *G = malloc(sizeof(double) * (long)px * py * nv);
-#define PAD(ix, iy) (G + ((long)((iy) + oy) * px + (ix) + 2) * nv)
-#define SRC(ix, iy) (gs + ((long)(iy) * nx + (ix)) * nv)
+    /* two ghost layers on each side of each streaming direction */
+    const int px = nx + 4, py = dim >= 2 ? ny + 4 : 1, pz = dim == 3 ? nz + 4 : 1;
+    const int oy = dim >= 2 ? 2 : 0, oz = dim == 3 ? 2 : 0;
+    double *G = malloc(sizeof(double) * (long)px * py * pz * nv);
+#define PAD(ix, iy, iz) (G + ((((long)(iz) + oz) * py + (iy) + oy) * px + (ix) + 2) * nv)
+#define SRC(ix, iy, iz) (gs + (((long)(iz) * ny + (iy)) * nx + (ix)) * nv)
 
-    for (int iy = 0; iy < ny; ++iy)
-        for (int ix = 0; ix < nx; ++ix)
-            memcpy(PAD(ix, iy), SRC(ix, iy), sizeof(double) * nv);
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix)
+                memcpy(PAD(ix, iy, iz), SRC(ix, iy, iz), sizeof(double) * nv);
 
     if (p->kind == ORC_SHOCK) {
         /* Far-field states of Eq. (bc_shock) fill both ghost layers. */
         double up[3], dn[3];
         orc_rankine_hugoniot(p->mach, up, dn);
         double Vu[3] = {up[1], 0, 0}, Vd[3] = {dn[1], 0, 0};
-        maxwellian_on(&g, up[0], Vu, up[2], PAD(-2, 0));
-        maxwellian_on(&g, up[0], Vu, up[2], PAD(-1, 0));
-        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx, 0));
-        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx + 1, 0));
-    } else if (p->kind == ORC_PERIODIC1 || p->kind == ORC_PERIODIC2) {
-        for (int iy = 0; iy < ny; ++iy) {
-            memcpy(PAD(-2, iy), SRC(nx - 2, iy), sizeof(double) * nv);
-            memcpy(PAD(-1, iy), SRC(nx - 1, iy), sizeof(double) * nv);
-            memcpy(PAD(nx, iy), SRC(0, iy), sizeof(double) * nv);
-            memcpy(PAD(nx + 1, iy), SRC(1, iy), sizeof(double) * nv);
-        }
-        if (two)
-            for (int ix = 0; ix < nx; ++ix) {
-                memcpy(PAD(ix, -2), SRC(ix, ny - 2), sizeof(double) * nv);
-                memcpy(PAD(ix, -1), SRC(ix, ny - 1), sizeof(double) * nv);
-                memcpy(PAD(ix, ny), SRC(ix, 0), sizeof(double) * nv);
-                memcpy(PAD(ix, ny + 1), SRC(ix, 1), sizeof(double) * nv);
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(-2, 0, 0));
+        maxwellian_on(&g, up[0], Vu, up[2], PAD(-1, 0, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx, 0, 0));
+        maxwellian_on(&g, dn[0], Vd, dn[2], PAD(nx + 1, 0, 0));
+    } else if (p->kind == ORC_PERIODIC1 || p->kind == ORC_PERIODIC2 || p->kind == ORC_PERIODIC3) {
+        /* periodic images; each direction's stencil only reaches the ghosts
+         * along that direction, so no edge or corner ghosts are needed */
+        for (int iz = 0; iz < nz; ++iz)
+            for (int iy = 0; iy < ny; ++iy) {
+                memcpy(PAD(-2, iy, iz), SRC(nx - 2, iy, iz), sizeof(double) * nv);
+                memcpy(PAD(-1, iy, iz), SRC(nx - 1, iy, iz), sizeof(double) * nv);
+                memcpy(PAD(nx, iy, iz), SRC(0, iy, iz), sizeof(double) * nv);
+                memcpy(PAD(nx + 1, iy, iz), SRC(1, iy, iz), sizeof(double) * nv);
             }
+        if (dim >= 2)
+            for (int iz = 0; iz < nz; ++iz)
+                for (int ix = 0; ix < nx; ++ix) {
+                    memcpy(PAD(ix, -2, iz), SRC(ix, ny - 2, iz), sizeof(double) * nv);
+                    memcpy(PAD(ix, -1, iz), SRC(ix, ny - 1, iz), sizeof(double) * nv);
+                    memcpy(PAD(ix, ny, iz), SRC(ix, 0, iz), sizeof(double) * nv);
+                    memcpy(PAD(ix, ny + 1, iz), SRC(ix, 1, iz), sizeof(double) * nv);
+                }
+        if (dim == 3)
+            for (int iy = 0; iy < ny; ++iy)
+                for (int ix = 0; ix < nx; ++ix) {
+                    memcpy(PAD(ix, iy, -2), SRC(ix, iy, nz - 2), sizeof(double) * nv);
+                    memcpy(PAD(ix, iy, -1), SRC(ix, iy, nz - 1), sizeof(double) * nv);
+                    memcpy(PAD(ix, iy, nz), SRC(ix, iy, 0), sizeof(double) * nv);
+                    memcpy(PAD(ix, iy, nz + 1), SRC(ix, iy, 1), sizeof(double) * nv);
+                }
     } else {
         /* Diffuse walls, Eq. (bc_cavity).  For velocities leaving the wall
          * (v.n > 0) both ghosts hold n_W Phi_W; for velocities arriving at it
@@ -598,53 +634,65 @@ void orc_stream(const orc_problem *p, const double *gs, double *out, double dt)
         double *rest = malloc(sizeof(double) * nv), *lid = malloc(sizeof(double) * nv);
         wall_maxwellian(p, &g, 0.0, rest);
         wall_maxwellian(p, &g, lid_speed(p), lid);
-        for (int w = 0; w < 4; ++w) {
+        const int N[3] = {nx, ny, nz};
+        for (int w = 0; w < 2 * dim; ++w) {
             int axis; double sign;
             wall_normal(w, &axis, &sign);
-            const double *va = axis == 0 ? g.vx : g.vy;
+            const double *va = axis == 0 ? g.vx : axis == 1 ? g.vy : g.vz;
             const double *phiw = w == 3 ? lid : rest;
-            int len = axis == 0 ? ny : nx;
-            for (int k = 0; k < len; ++k) {
-                int ax, ay, gx1, gy1, gx2, gy2;
-                if (w == 0) { ax = 0; ay = k; gx1 = -1; gx2 = -2; gy1 = gy2 = k; }
-                else if (w == 1) { ax = nx - 1; ay = k; gx1 = nx; gx2 = nx + 1; gy1 = gy2 = k; }
-                else if (w == 2) { ax = k; ay = 0; gy1 = -1; gy2 = -2; gx1 = gx2 = k; }
-                else { ax = k; ay = ny - 1; gy1 = ny; gy2 = ny + 1; gx1 = gx2 = k; }
-                const double *g0 = SRC(ax, ay);
-                double nW = wall_density(&g, axis, sign, g0, phiw);
-                double *d1 = PAD(gx1, gy1), *d2 = PAD(gx2, gy2);
-                for (long j = 0; j < nv; ++j) {
-                    double v = sign * va[j] > 0.0 ? nW * phiw[j] : g0[j];
-                    d1[j] = v;
-                    d2[j] = v;
+            /* the face's cells run over the two other coordinates */
+            const int b1 = axis == 0 ? 1 : 0, b2 = axis == 2 ? 1 : 2;
+            for (int k2 = 0; k2 < N[b2]; ++k2)
+                for (int k1 = 0; k1 < N[b1]; ++k1) {
+                    int a[3], d1[3], d2[3];
+                    a[b1] = d1[b1] = d2[b1] = k1;
+                    a[b2] = d1[b2] = d2[b2] = k2;
+                    a[axis] = sign > 0.0 ? 0 : N[axis] - 1;
+                    d1[axis] = sign > 0.0 ? -1 : N[axis];
+                    d2[axis] = sign > 0.0 ? -2 : N[axis] + 1;
+                    const double *g0 = SRC(a[0], a[1], a[2]);
+                    double nW = wall_density(&g, axis, sign, g0, phiw);
+                    double *q1 = PAD(d1[0], d1[1], d1[2]), *q2 = PAD(d2[0], d2[1], d2[2]);
+                    for (long j = 0; j < nv; ++j) {
+                        double v = sign * va[j] > 0.0 ? nW * phiw[j] : g0[j];
+                        q1[j] = v;
+                        q2[j] = v;
+                    }
                 }
-            }
         }
         free(rest); free(lid);
     }
 
-    const double dx = dxs(p), dy = two ? dys(p) : 1.0;
+    const double dx = dxs(p), dy = dim >= 2 ? dys(p) : 1.0, dz = dim == 3 ? dzs(p) : 1.0;
     const int limit = p->minmod;
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int iy = 0; iy < ny; ++iy)
-        for (int ix = 0; ix < nx; ++ix) {
-            const double *xm2 = PAD(ix - 2, iy), *xm1 = PAD(ix - 1, iy), *c0 = PAD(ix, iy),
-                         *xp1 = PAD(ix + 1, iy), *xp2 = PAD(ix + 2, iy);
-            const double *ym2 = two ? PAD(ix, iy - 2) : 0, *ym1 = two ? PAD(ix, iy - 1) : 0,
-                         *yp1 = two ? PAD(ix, iy + 1) : 0, *yp2 = two ? PAD(ix, iy + 2) : 0;
-            double *o = out + ((long)iy * nx + ix) * nv;
-            for (long j = 0; j < nv; ++j) {
-                double Cx = g.vx[j] * dt / dx;
-                double r = c0[j] - Cx * (face_value(xm1[j], c0[j], xp1[j], xp2[j], Cx, limit) -
-                                         face_value(xm2[j], xm1[j], c0[j], xp1[j], Cx, limit));
-                if (two) {
-                    double Cy = g.vy[j] * dt / dy;
-                    r -= Cy * (face_value(ym1[j], c0[j], yp1[j], yp2[j], Cy, limit) -
-                               face_value(ym2[j], ym1[j], c0[j], yp1[j], Cy, limit));
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix) {
+                const double *xm2 = PAD(ix - 2, iy, iz), *xm1 = PAD(ix - 1, iy, iz), *c0 = PAD(ix, iy, iz),
+                             *xp1 = PAD(ix + 1, iy, iz), *xp2 = PAD(ix + 2, iy, iz);
+                double *o = out + (((long)iz * ny + iy) * nx + ix) * nv;
+                for (long j = 0; j < nv; ++j) {
+                    double Cx = g.vx[j] * dt / dx;
+                    double r = c0[j] - Cx * (face_value(xm1[j], c0[j], xp1[j], xp2[j], Cx, limit) -
+                                             face_value(xm2[j], xm1[j], c0[j], xp1[j], Cx, limit));
+                    if (dim >= 2) {
+                        const double *ym2 = PAD(ix, iy - 2, iz), *ym1 = PAD(ix, iy - 1, iz),
+                                     *yp1 = PAD(ix, iy + 1, iz), *yp2 = PAD(ix, iy + 2, iz);
+                        double Cy = g.vy[j] * dt / dy;
+                        r -= Cy * (face_value(ym1[j], c0[j], yp1[j], yp2[j], Cy, limit) -
+                                   face_value(ym2[j], ym1[j], c0[j], yp1[j], Cy, limit));
+                    }
+                    if (dim == 3) {
+                        const double *zm2 = PAD(ix, iy, iz - 2), *zm1 = PAD(ix, iy, iz - 1),
+                                     *zp1 = PAD(ix, iy, iz + 1), *zp2 = PAD(ix, iy, iz + 2);
+                        double Cz = g.vz[j] * dt / dz;
+                        r -= Cz * (face_value(zm1[j], c0[j], zp1[j], zp2[j], Cz, limit) -
+                                   face_value(zm2[j], zm1[j], c0[j], zp1[j], Cz, limit));
+                    }
+                    o[j] = r;
                 }
-                o[j] = r;
             }
-        }
 #undef PAD
 #undef SRC
     free(G);
@@ -715,7 +763,7 @@ void orc_totals(const orc_problem *p, const double *f, double *tot /* [6] */)
 {
     velgrid g = make_velgrid(p);
     const long nc = ncell(p), nv = nvel(p);
-    const double w = dvol(p) * dxs(p) * (is2d(p) ? dys(p) : 1.0);
+    const double w = dvol(p) * dxs(p) * (ndim(p) >= 2 ? dys(p) : 1.0) * (ndim(p) == 3 ? dzs(p) : 1.0);
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (long c = 0; c < nc; ++c)
         for (long j = 0; j < nv; ++j) {
@@ -737,6 +785,7 @@ void orc_totals(const orc_problem *p, const double *f, double *tot /* [6] */)
  * the lid: L = sum_i dx [sum_{vy>0} vx vy f dV + n_W,i sum_{vy<0} vx vy Phi_W dV]. */
 double orc_lid_shear(const orc_problem *p, const double *f)
 {
+    if (ndim(p) == 3) return NAN; /* defined for the two-dimensional cavity */
     velgrid g = make_velgrid(p);
     const int nx = p->nx, ny = p->ny;
     const long nv = nvel(p);

@@ -762,3 +762,117 @@ def test_steady_shock_connects_rankine_hugoniot_states(oracle_mod):
     m = O.moments(f)
     np.testing.assert_allclose(m[0, [0, 1, 4]], up, rtol=2e-3)
     np.testing.assert_allclose(m[-1, [0, 1, 4]], dn, rtol=2e-3)
+
+
+# ------------------------------------------------- three spatial dimensions
+# The extension of Sec. 2.1 to three directions: a cube with six diffuse
+# walls (lid at y = y1 moving along x) and a periodic box.
+
+
+def cube(**kw):
+    d = prob(kind="cavity3d", nx=4, ny=3, nz=4, z0=0.0, z1=1.0, nv=(8, 6, 8), vlo=(-4.0,) * 3,
+             vhi=(4.0,) * 3, kn=0.3, lid_mach=0.3, t_wall=1.1, cfl=0.45)
+    d.update(kw)
+    return d
+
+
+def as6(O, f):
+    """f[cell][v] as f[iz][iy][ix][jz][jy][jx]."""
+    nvx, nvy, nvz = O.nv
+    return np.asarray(f).reshape(O.nz, O.ny, O.nx, nvz, nvy, nvx)
+
+
+def swap_xz(O, f):
+    """The state mirrored through the plane x = z: f'(x, y, z; v_x, v_y, v_z) =
+    f(z, y, x; v_z, v_y, v_x) (needs nx = nz and equal x and z velocity axes)."""
+    return np.ascontiguousarray(as6(O, f).transpose(2, 1, 0, 5, 4, 3)).reshape(O.shape)
+
+
+def perturbed3(O, seed, amp=0.3):
+    return O.initial_state() * (1 + amp * inputs.uniform(O.shape, seed=seed, lo=-1, hi=1))
+
+
+def test_z_uniform_box_reduces_to_the_2d_step(oracle_mod):
+    """A periodic box whose state does not depend on z: the z fluxes vanish
+    term by term, so four steps equal the two-dimensional periodic steps bit
+    for bit (same dt)."""
+    c2 = prob(kind="periodic2d", nx=5, ny=4, nv=(8, 6, 6), vlo=(-4.0,) * 3, vhi=(4.0,) * 3, kn=0.3, dt=0.01)
+    c3 = dict(c2, kind="periodic3d", nz=3, z0=0.0, z1=1.0)
+    O2, O3 = oracle_mod.Oracle(c2), oracle_mod.Oracle(c3)
+    f2 = perturbed3(O2, 201)
+    f3 = np.tile(f2, (3, 1))
+    got = O3.step(f3, 4).reshape(3, O2.ncell, O2.nvel)
+    want = O2.step(f2, 4)
+    for iz in range(3):
+        assert np.array_equal(got[iz], want)
+
+
+@pytest.mark.parametrize("limiter", ["minmod", "none"])
+def test_periodic_cube_commutes_with_swapping_x_and_z(oracle_mod, limiter):
+    """On a cubic periodic box with equal x and z velocity axes, stepping the
+    state mirrored through x = z gives the mirrored step: the z stencil
+    computes what the x stencil does (a dropped, mis-signed or mis-indexed z
+    term fails this)."""
+    cfg = prob(kind="periodic3d", nx=5, ny=3, nz=5, z0=0.0, z1=1.0, nv=(8, 6, 8), vlo=(-4.0,) * 3,
+               vhi=(4.0,) * 3, kn=0.3, cfl=0.4, limiter=limiter)
+    O = oracle_mod.Oracle(cfg)
+    f = perturbed3(O, 202)
+    a = O.step(swap_xz(O, f), 3)
+    b = swap_xz(O, O.step(f, 3))
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
+
+
+def test_cube_with_resting_lid_commutes_with_swapping_x_and_z(oracle_mod):
+    """All six walls at rest: the cube is symmetric under x <-> z, so the
+    z walls (numbers 4, 5) must act as the x walls do."""
+    cfg = cube(nz=4, lid_mach=0.0)
+    O = oracle_mod.Oracle(cfg)
+    f = perturbed3(O, 203)
+    a = O.step(swap_xz(O, f), 3)
+    b = swap_xz(O, O.step(f, 3))
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
+
+
+def test_driven_cube_mirror_in_z(oracle_mod):
+    """The lid moves along x, so z -> z1 - z, v_z -> -v_z maps solutions to
+    solutions on a symmetric v_z axis."""
+    cfg = cube()
+    O = oracle_mod.Oracle(cfg)
+    f = perturbed3(O, 204)
+
+    def mirror(x):
+        return np.ascontiguousarray(as6(O, x)[::-1, :, :, ::-1, :, :]).reshape(O.shape)
+
+    a = O.step(mirror(f), 3)
+    b = mirror(O.step(f, 3))
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
+
+
+def test_cube_at_rest_is_stationary_under_streaming(oracle_mod):
+    """A gas at rest at the wall temperature with the lid at rest: every wall
+    density is 1 (equal incident and emitted fluxes of the same Maxwellian)
+    and streaming leaves the state unchanged."""
+    cfg = cube(lid_mach=0.0, t_wall=1.0)
+    O = oracle_mod.Oracle(cfg)
+    f = O.initial_state()
+    g = O.stream(f)
+    assert np.max(np.abs(g - f)) <= 1e-14 * np.max(f)
+
+
+def test_cube_streaming_conserves_mass(oracle_mod):
+    """Six diffuse walls with zero net mass flux each: one streaming pass of
+    a perturbed state keeps the total mass to rounding, while momentum and
+    energy change at the walls."""
+    cfg = cube()
+    O = oracle_mod.Oracle(cfg)
+    f = perturbed3(O, 205)
+    t0, t1 = O.totals(f), O.totals(O.stream(f))
+    assert abs(t1[0] - t0[0]) <= 1e-14 * t0[0]
+    assert abs(t1[4] - t0[4]) > 1e-9 * t0[4]
+
+
+def test_cube_time_step_sums_three_courant_numbers(oracle_mod):
+    cfg = cube(nx=4, ny=5, nz=2, nv=(8, 6, 10), vlo=(-4.0, -3.0, -5.0), vhi=(4.0, 3.0, 5.0), cfl=0.5)
+    O = oracle_mod.Oracle(cfg)
+    vx, vy, vz = 4.0 - 0.5, 3.0 - 0.5, 5.0 - 0.5
+    assert O.dt == pytest.approx(0.5 / (vx * 4 + vy * 5 + vz * 2), rel=1e-15)
