@@ -6,7 +6,9 @@
  * Equations on GPUs I: Model Kinetic Equations", arXiv:0903.4044, Sec. 2,
  * Eq. (BGKW)) on a spatial grid times a uniform 3D velocity grid (Sec. 2.1),
  * for the paper's two problems: the 1D normal shock (Sec. 4.1) and the 2D
- * lid-driven cavity with diffuse walls (Sec. 5.1), plus periodic test boxes.
+ * lid-driven cavity with diffuse walls (Sec. 5.1), its extension to a
+ * lid-driven cube (Sec. 2.1: one upwind stencil per spatial direction), plus
+ * periodic test boxes.
  *
  * One time step is R_{dt/2} S_dt R_{dt/2} (Strang) or R_dt S_dt (Lie, the
  * order of Sec. 2.1), where R_tau is the exact homogeneous relaxation of
@@ -23,7 +25,7 @@
  * the caller (typically torch tensors).  f holds every instance of the
  * context back to back; instance k starts at element f_offset(k) and is
  * laid out f[cell][jz][jy][jx] (velocity fastest, jx fastest of all;
- * cell = iy * nx + ix).  Elements are double for BGK_FP64 and float for
+ * cell = (iz * ny + iy) * nx + ix).  Elements are double for BGK_FP64 and float for
  * BGK_FP32.  Every buffer the size of f is the caller's: besides f and its
  * output, bgk_step takes a workspace of ws_step_bytes (its ping-pong
  * buffer) and bgk_step_adjoint one of ws_adjoint_bytes (two f-sized
@@ -66,6 +68,9 @@ extern "C" {
 #define BGK_CAVITY_2D 1     /* Sec. 5.1: four diffuse walls of Eq. (bc_cavity), moving lid on top */
 #define BGK_PERIODIC_1D 2   /* periodic test box */
 #define BGK_PERIODIC_2D 3   /* periodic test box */
+#define BGK_CAVITY_3D 4     /* lid-driven cube: six diffuse walls of Eq. (bc_cavity) (walls 4, 5 across z),
+                               the lid at y = y1 moving along x */
+#define BGK_PERIODIC_3D 5   /* periodic test box */
 
 #define BGK_STRANG 0        /* R_{dt/2} S_dt R_{dt/2} */
 #define BGK_LIE 1           /* R_dt S_dt (Sec. 2.1) */
@@ -92,7 +97,7 @@ extern "C" {
 
 /* One problem instance (Sec. 2.1 grid, Sec. 4.1 / 5.1 boundary data). */
 typedef struct bgk_problem {
-    int kind;               /* BGK_SHOCK_1D, BGK_CAVITY_2D, BGK_PERIODIC_1D/2D */
+    int kind;               /* BGK_SHOCK_1D, BGK_CAVITY_2D, BGK_PERIODIC_1D/2D, BGK_CAVITY_3D, BGK_PERIODIC_3D */
     int nx, ny;             /* spatial cells (ny ignored for 1D kinds) */
     double x0, x1, y0, y1;  /* spatial box */
     int nv[3];              /* velocity cells per component (even, 2..128) */
@@ -118,14 +123,19 @@ typedef struct bgk_problem {
                                the components out and the integrals of Eq. (Maxw) are exact;
                                their vlo, vhi are ignored; the minmod limiter acts on g and h
                                separately.  0: full velocity space.  The same for all instances
-                               of a context.  No reverse sweep. */
+                               of a context.  No reverse sweep.  Not for 3D kinds. */
+    int nz;                 /* 3D kinds: spatial cells along z (ignored otherwise).  The v_z nodes
+                               must change sign between two planes jz - 1, jz with jz even (an even
+                               count of nodes on either side: nv[2] divisible by 4 on a box
+                               symmetric about 0), else BGK_E_UNSUPPORTED */
+    double z0, z1;          /* 3D kinds: spatial box along z */
 } bgk_problem;
 
 typedef struct bgk_ctx bgk_ctx;
 
 /* Create a context for n_probs instances stepped together (one launch per
  * kernel for all of them).  All instances must share the velocity grid and
- * the dimension (1D kinds or 2D kinds).  Validates every field, computes each
+ * the dimension (1D, 2D or 3D kinds).  Validates every field, computes each
  * instance's dt, and allocates the context's small device data (per-cell
  * table entries and moment partial sums, no f-sized buffer) on the current
  * device.  precision: BGK_FP64 or BGK_FP32.
@@ -296,8 +306,8 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * (1D) table entries per
  * workgroup exceed the device's LDS, for BGK_SHIFT contexts (no reverse
  * sweep of the translation form) and for contexts with a BGK_CONSERVATIVE
- * instance (no reverse sweep of the effective parameters' solve).
- * Asynchronous on `stream`. */
+ * instance (no reverse sweep of the effective parameters' solve) and for
+ * 3D kinds.  Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *ws, void *stream);
 
@@ -308,7 +318,8 @@ int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *
  * with Phi_W the unit-density wall Maxwellian at (U_W, 0, 0) and T_w and n_W
  * the per-cell wall density that balances the incident flux
  * sum_{v_y>0} v_y f.  Written to L[k] (device, n_probs doubles); 0 for
- * non-cavity instances.  f: device, f_elems elements. */
+ * non-cavity instances.  f: device, f_elems elements.  BGK_E_UNSUPPORTED
+ * for 3D kinds (as is the gradient below). */
 int bgk_lid_shear(bgk_ctx *ctx, const void *f, double *L, void *stream);
 
 /* Gradient of bgk_lid_shear: lam = dL/df (device, f_elems elements in the
@@ -327,7 +338,7 @@ int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double *grad_para
  * zero below the lid (the vortex centre; linear between cell centres) up to
  * the lid (linear extrapolation over the top half cell), or from the bottom
  * wall if there is no zero, divided by the height (y1 - y0).  NaN for
- * non-cavity instances and for a lid at rest.  f: device, f_elems elements; out: host, 2 n_probs doubles.
+ * non-cavity instances (3D kinds included) and for a lid at rest.  f: device, f_elems elements; out: host, 2 n_probs doubles.
  * Synchronises `stream`; errors: BGK_E_INVALID, BGK_E_HIP. */
 int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void *stream);
 

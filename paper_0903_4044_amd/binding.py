@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbgk.so")
 
 OK, E_INVALID, E_CFL, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_NEGATIVE, E_ALIAS = range(8)
-KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3}
+KINDS = {"shock": 0, "cavity": 1, "periodic1d": 2, "periodic2d": 3, "cavity3d": 4, "periodic3d": 5}
 FP64, FP32 = 0, 1
 
 
@@ -44,6 +44,8 @@ class Problem(ctypes.Structure):
         ("splitting", ctypes.c_int), ("limiter", ctypes.c_int),
         ("maxwellian", ctypes.c_int),
         ("reduced", ctypes.c_int),
+        ("nz", ctypes.c_int),
+        ("z0", ctypes.c_double), ("z1", ctypes.c_double),
     ]
 
 
@@ -118,6 +120,8 @@ def to_struct(cfg: dict) -> Problem:
     p.limiter = {"minmod": 0, "none": 1, "shift": 2}[cfg.get("limiter", "minmod")]
     p.maxwellian = {"point": 0, "conservative": 1}[cfg.get("maxwellian", "point")]
     p.reduced = 1 if cfg.get("reduced", False) else 0
+    p.nz = int(cfg.get("nz", 1))
+    p.z0, p.z1 = float(cfg.get("z0", 0.0)), float(cfg.get("z1", 1.0))
     return p
 
 
@@ -129,7 +133,7 @@ def size_class(problems, precision: str) -> str:
     cells = sum(inputs.ncells(p) for p in problems)
     bucket = 1 << max(0, math.ceil(math.log2(max(cells, 1))))
     nv = "x".join(str(int(v)) for v in p0["nv"])
-    return f"{2 if inputs.is_2d(p0) else 1}d/{precision}/nv{nv}/cells<={bucket}"
+    return f"{inputs.ndim(p0)}d/{precision}/nv{nv}/cells<={bucket}"
 
 
 def load_tuned() -> dict:

@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(256)
             const int sgn = si == 0 ? 1 : -1, k = m == 0 ? -2 : m == 1 ? -1 : m == 2 ? 1 : 2;
             const int N = d == 0 ? I.nx : I.ny;
             const int pos = (d == 0 ? ix : iy) + sgn * k;
-            resolve_slot(I, d, pos, d == 0 ? iy : ix, sgn, c, &cell, &par);
+            resolve_slot(I, d, ix, iy, 0, sgn * k, sgn, c, &cell, &par);
             mc = ((pos >= 0 && pos < N) || per) ? cell : -1;
         }
         S.cell[sl] = cell;

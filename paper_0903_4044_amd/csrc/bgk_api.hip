@@ -114,7 +114,13 @@ static int fail(bgk_ctx *ctx, int code, const std::string &msg)
 
 static const double kGamma = 5.0 / 3.0;
 
-static bool is2d_kind(int k) { return k == BGK_CAVITY_2D || k == BGK_PERIODIC_2D; }
+// Spatial dimension of a problem kind.
+static int kind_dim(int k)
+{
+    if (k == BGK_CAVITY_3D || k == BGK_PERIODIC_3D) return 3;
+    if (k == BGK_CAVITY_2D || k == BGK_PERIODIC_2D) return 2;
+    return 1;
+}
 
 static Args make_args(const bgk_ctx *c)
 {
@@ -134,11 +140,12 @@ static Args make_args(const bgk_ctx *c)
 }
 
 // LDS of the streaming kernel after its tables: 8 bytes of alignment, the
-// per-thread moment sums (NQ doubles per thread) and the node tables (v_z
-// and v_z^2 per plane, v_x, v_y).
-static size_t stream_acc_bytes(const Geo &g, int block)
+// per-thread moment sums (NQ doubles per thread in 3D, 9 without the z half
+// fluxes otherwise) and the node tables (v_z and v_z^2 per plane, v_x, v_y).
+static size_t stream_acc_bytes(const Geo &g, int dim, int block)
 {
-    return 8 + ((size_t)NQ * block + 2 * g.nvz + g.nvx + g.nvy) * sizeof(double);
+    const size_t nacc = dim == 3 ? NQ : 9;
+    return 8 + (nacc * block + 2 * g.nvz + g.nvx + g.nvy) * sizeof(double);
 }
 
 static void drop_graphs(bgk_ctx *c);
@@ -166,16 +173,29 @@ static void release(bgk_ctx *c)
     delete c;
 }
 
-// Time step from the Courant rule: dt = cfl / max_j sum_d |v_d(j)| / dx_d.
-static double courant_rate(const bgk_problem &p, bool two)
+// Time step from the Courant rule: dt = cfl / max_j sum_d |v_d(j)| / dx_d
+// over the streaming directions.
+static double courant_rate(const bgk_problem &p, int dim)
 {
-    const double dx = (p.x1 - p.x0) / p.nx, dy = two ? (p.y1 - p.y0) / p.ny : 1.0;
-    double mx = 0.0, my = 0.0;
-    for (int k = 0; k < p.nv[0]; ++k)
-        mx = std::max(mx, std::fabs(p.vlo[0] + (k + 0.5) * (p.vhi[0] - p.vlo[0]) / p.nv[0]));
-    for (int k = 0; k < p.nv[1]; ++k)
-        my = std::max(my, std::fabs(p.vlo[1] + (k + 0.5) * (p.vhi[1] - p.vlo[1]) / p.nv[1]));
-    return mx / dx + (two ? my / dy : 0.0);
+    const double len[3] = {p.x1 - p.x0, dim >= 2 ? p.y1 - p.y0 : 1.0, dim == 3 ? p.z1 - p.z0 : 1.0};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    double r = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        double m = 0.0;
+        for (int k = 0; k < p.nv[a]; ++k)
+            m = std::max(m, std::fabs(p.vlo[a] + (k + 0.5) * (p.vhi[a] - p.vlo[a]) / p.nv[a]));
+        r += m / (len[a] / n[a]);
+    }
+    return r;
+}
+
+// Planes of the velocity grid with v_z < 0 (they come first).
+static int negative_planes(const bgk_problem &p)
+{
+    int n = 0;
+    for (int k = 0; k < p.nv[2]; ++k)
+        if (p.vlo[2] + (k + 0.5) * (p.vhi[2] - p.vlo[2]) / p.nv[2] < 0.0) ++n;
+    return n;
 }
 
 static int validate(const bgk_problem &p, int idx, std::string &msg)
@@ -186,14 +206,17 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
         msg = b;
         return BGK_E_INVALID;
     };
-    if (p.kind < 0 || p.kind > 3) return bad("unknown kind");
-    const bool two = is2d_kind(p.kind);
-    if (p.nx < 1 || (two && p.ny < 1)) return bad("nx, ny must be >= 1");
+    if (p.kind < 0 || p.kind > 5) return bad("unknown kind");
+    const int dim = kind_dim(p.kind);
+    if (p.nx < 1 || (dim >= 2 && p.ny < 1) || (dim == 3 && p.nz < 1)) return bad("nx, ny, nz must be >= 1");
     if (p.kind == BGK_PERIODIC_1D && p.nx < 2) return bad("periodic boxes need nx >= 2");
     if (p.kind == BGK_PERIODIC_2D && (p.nx < 2 || p.ny < 2)) return bad("periodic boxes need nx, ny >= 2");
-    if (!(p.x1 > p.x0) || (two && !(p.y1 > p.y0))) return bad("empty spatial box");
+    if (p.kind == BGK_PERIODIC_3D && (p.nx < 2 || p.ny < 2 || p.nz < 2))
+        return bad("periodic boxes need nx, ny, nz >= 2");
+    if (!(p.x1 > p.x0) || (dim >= 2 && !(p.y1 > p.y0)) || (dim == 3 && !(p.z1 > p.z0)))
+        return bad("empty spatial box");
     for (int a = 0; a < 3; ++a) {
-        if (a == 1 && p.reduced && !two && p.nv[1] == 1) continue;  // the single node v_y = 0
+        if (a == 1 && p.reduced && dim == 1 && p.nv[1] == 1) continue;  // the single node v_y = 0
         if (p.nv[a] < 2 || p.nv[a] > NVMAX) {
             msg = "velocity cells per component must be in [2, 128]";
             return BGK_E_UNSUPPORTED;
@@ -206,21 +229,33 @@ static int validate(const bgk_problem &p, int idx, std::string &msg)
     if (p.limiter != BGK_MINMOD && p.limiter != BGK_NOLIMIT && p.limiter != BGK_SHIFT) return bad("unknown limiter");
     if (p.maxwellian != BGK_POINT && p.maxwellian != BGK_CONSERVATIVE) return bad("unknown Maxwellian form");
     if (p.reduced != 0 && p.reduced != 1) return bad("reduced must be 0 or 1");
-    if (p.reduced && (p.nv[2] != 2 || (!two && p.nv[1] != 1))) {
+    if (p.reduced && (p.nv[2] != 2 || (dim == 1 && p.nv[1] != 1))) {
         snprintf(b, sizeof b, "problem %d: the reduced velocity space takes nv[2] = 2 (and nv[1] = 1 for "
                               "one-dimensional kinds)", idx);
         msg = b;
         return BGK_E_UNSUPPORTED;
     }
-    if (p.limiter == BGK_SHIFT && two) {
+    if (dim == 3 && p.reduced) {
+        snprintf(b, sizeof b, "problem %d: three-dimensional kinds stream along v_z (no reduced space)", idx);
+        msg = b;
+        return BGK_E_UNSUPPORTED;
+    }
+    if (dim == 3 && negative_planes(p) % 2) {
+        snprintf(b, sizeof b, "problem %d: v_z must change sign at an even plane (nv[2] divisible by 4 on a "
+                              "symmetric box)", idx);
+        msg = b;
+        return BGK_E_UNSUPPORTED;
+    }
+    if (p.limiter == BGK_SHIFT && dim >= 2) {
         snprintf(b, sizeof b, "problem %d: shift streaming is one-dimensional", idx);
         msg = b;
         return BGK_E_UNSUPPORTED;
     }
     if (p.kind == BGK_SHOCK_1D && !(p.mach > 1.0)) return bad("shock needs Mach > 1");
-    if (p.kind == BGK_CAVITY_2D && !(p.t_wall > 0.0)) return bad("wall temperature must be > 0");
+    if ((p.kind == BGK_CAVITY_2D || p.kind == BGK_CAVITY_3D) && !(p.t_wall > 0.0))
+        return bad("wall temperature must be > 0");
     if (!(p.dt > 0.0) && !(p.cfl > 0.0)) return bad("need dt > 0 or cfl > 0");
-    const double rate = courant_rate(p, two);
+    const double rate = courant_rate(p, dim);
     const double dt = p.dt > 0.0 ? p.dt : p.cfl / rate;
     if (p.limiter != BGK_SHIFT && dt * rate > 2.0 / 3.0 * (1.0 + 1e-12)) {
         snprintf(b, sizeof b, "problem %d: Courant sum %.6g exceeds 2/3", idx, dt * rate);
@@ -245,6 +280,7 @@ static bool vec_valid(const bgk_ctx *c, int v)
     if (c->shift) return false;  // the translation-form kernel takes one jx per lane task
     if (g.red) return false;     // reduced: the column fold needs one jx per lane task
     if (v == 4 && c->precision == BGK_FP64) return false;
+    if (c->dim == 3) return false;  // ten taps per lane: one jx per lane task
     if (g.nvx % v) return false;
     for (int k = 0; k < g.nvx; k += v) {
         const double a = g.lo[0] + (k + 0.5) * g.dv[0], b = g.lo[0] + (k + v - 0.5) * g.dv[0];
@@ -315,7 +351,7 @@ static void choose_launch(bgk_ctx *c)
     int vec = 1;
     for (int v : {4, 2})
         if (vec_valid(c, v)) { vec = v; break; }
-    if (c->dim == 2) vec = 1;
+    if (c->dim >= 2) vec = 1;
     const int unroll = (c->dim == 1 && c->precision == BGK_FP32 && !c->shift) ? 2 : 1;
     const int target = c->dim == 1 ? (c->precision == BGK_FP32 ? 1024 : 512) : 2048;
     set_shape(c, vec, unroll, vsplit_for(c, target));
@@ -340,7 +376,7 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
         if (rc) return rc;
         const bgk_problem &p = probs[i], &q = probs[0];
         const char *why = nullptr;
-        if (is2d_kind(p.kind) != is2d_kind(q.kind)) why = "all instances must have the same dimension";
+        if (kind_dim(p.kind) != kind_dim(q.kind)) why = "all instances must have the same dimension";
         else if (p.reduced != q.reduced) why = "all instances must share the velocity space (reduced or not)";
         else if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
             why = "shift streaming cannot share a context with other limiters";
@@ -355,7 +391,7 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     c->precision = precision;
     c->esize = precision == BGK_FP64 ? 8 : 4;
     c->ninst = n_probs;
-    c->dim = is2d_kind(probs[0].kind) ? 2 : 1;
+    c->dim = kind_dim(probs[0].kind);
     c->shift = probs[0].limiter == BGK_SHIFT;
     c->probs.assign(probs, probs + n_probs);
     (void)hipGetDevice(&c->device);
@@ -372,7 +408,8 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     g.npl = g.nvx * g.nvy;
     g.nv = (long long)g.npl * g.nvz;
     g.dV = 1.0;
-    g.red = probs[0].reduced ? (is2d_kind(probs[0].kind) ? 1 : 2) : 0;
+    g.red = probs[0].reduced ? (c->dim == 2 ? 1 : 2) : 0;
+    g.zneg = g.red ? 0 : negative_planes(probs[0]);
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = probs[0].vlo[a];
         g.dv[a] = (probs[0].vhi[a] - probs[0].vlo[a]) / probs[0].nv[a];
@@ -393,15 +430,15 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     g.tz = (g.ty2 + g.nvy + 1) & ~1;
     g.pe = (g.tz + 2 * g.nvz + 3) & ~3;
     {
-        // LDS per workgroup: the table entries of every stencil slot (13 in
-        // 2D, 7 in 1D for the step; 17 and 9 for the reverse sweep) plus a
-        // few KB of static buffers
+        // LDS per workgroup: the table entries of every stencil slot (1 + 6
+        // dim for the step; 17 and 9 for the reverse sweep of 2D and 1D
+        // kinds) plus a few KB of static buffers
         int lds_max = 0;
         if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
             lds_max <= 0)
             lds_max = 65536;
         const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
-        const size_t fwd = (c->dim == 2 ? 13 : 7) * entry + slack + stream_acc_bytes(g, 256);
+        const size_t fwd = (size_t)(1 + 6 * c->dim) * entry + slack + stream_acc_bytes(g, c->dim, 256);
         const size_t adj = (c->dim == 2 ? 17 : 9) * entry + slack;
         c->lds_max = lds_max;
         if (fwd > (size_t)lds_max) {
@@ -419,12 +456,17 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     long long f_off = 0;
     for (int i = 0; i < n_probs; ++i) {
         const bgk_problem &p = probs[i];
-        const bool two = is2d_kind(p.kind);
+        const int dim = kind_dim(p.kind);
         Inst I{};
         I.kind = p.kind;
         I.nx = p.nx;
-        I.ny = two ? p.ny : 1;
-        I.ncell = I.nx * I.ny;
+        I.ny = dim >= 2 ? p.ny : 1;
+        I.nz = dim == 3 ? p.nz : 1;
+        if ((long long)I.nx * I.ny * I.nz >= (1LL << 30)) {
+            msg = "one instance must have fewer than 2^30 cells";
+            return BGK_E_UNSUPPORTED;
+        }
+        I.ncell = I.nx * I.ny * I.nz;
         I.cell0 = c->h_cell_prefix.back();
         I.strang = p.splitting == BGK_STRANG;
         I.minmod = p.limiter == BGK_MINMOD;
@@ -432,10 +474,12 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
         I.conservative = p.maxwellian == BGK_CONSERVATIVE;
         if (I.conservative) c->conservative = true;
         I.f0 = f_off;
-        const double dx = (p.x1 - p.x0) / p.nx, dy = two ? (p.y1 - p.y0) / p.ny : 1.0;
-        I.dt = p.dt > 0.0 ? p.dt : p.cfl / courant_rate(p, two);
+        const double dx = (p.x1 - p.x0) / p.nx, dy = dim >= 2 ? (p.y1 - p.y0) / p.ny : 1.0,
+                     dz = dim == 3 ? (p.z1 - p.z0) / p.nz : 1.0;
+        I.dt = p.dt > 0.0 ? p.dt : p.cfl / courant_rate(p, dim);
         I.cx = I.dt / dx;
-        I.cy = two ? I.dt / dy : 0.0;
+        I.cy = dim >= 2 ? I.dt / dy : 0.0;
+        I.cz = dim == 3 ? I.dt / dz : 0.0;
         I.kn = p.kn;
         I.omega = p.omega;
         I.tw = p.t_wall;
@@ -452,7 +496,11 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
             I.dn[1] = I.up[1] / r;
             I.dn[2] = (5.0 * m2 - 1.0) * (m2 + 3.0) / (16.0 * m2);
         }
-        const int np = p.kind == BGK_SHOCK_1D ? 2 : p.kind == BGK_CAVITY_2D ? 2 * I.nx + 2 * I.ny : 0;
+        // ghost entries: the two far fields, or one per face cell of each wall
+        const int np = p.kind == BGK_SHOCK_1D    ? 2
+                       : p.kind == BGK_CAVITY_2D ? 2 * I.nx + 2 * I.ny
+                       : p.kind == BGK_CAVITY_3D ? 2 * (I.ny * I.nz + I.nx * I.nz + I.nx * I.ny)
+                                                 : 0;
         if ((long long)I.ncell * g.nv * (long long)c->esize >= (1LL << 31) * 2LL) {
             msg = "one instance must hold fewer than 2^32 bytes of f";
             return BGK_E_UNSUPPORTED;
@@ -619,8 +667,8 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
 // streaming kernel, 9 or 5 for the reverse sweep's gather kernel.
 static size_t role_table_bytes(const bgk_ctx *c, bool adjoint)
 {
-    const int combos = c->dim == 2 ? 4 : 2;
-    const int roles = adjoint ? (c->dim == 2 ? 9 : 5) : (c->dim == 2 ? 7 : 4);
+    const int combos = c->dim >= 2 ? 4 : 2;
+    const int roles = adjoint ? (c->dim == 2 ? 9 : 5) : 1 + 3 * c->dim;
     return (size_t)combos * c->geo.nvz * roles * 2 * c->esize;
 }
 
@@ -629,7 +677,7 @@ static size_t role_table_bytes(const bgk_ctx *c, bool adjoint)
 // streaming kernel, the moment sums).
 static bool use_roles(const bgk_ctx *c, int zr, size_t lds, bool adjoint, int block = 0)
 {
-    return zr == 1 && lds + role_table_bytes(c, adjoint) + (adjoint ? 0 : stream_acc_bytes(c->geo, block)) + 4096 <=
+    return zr == 1 && lds + role_table_bytes(c, adjoint) + (adjoint ? 0 : stream_acc_bytes(c->geo, c->dim, block)) + 4096 <=
                           (size_t)c->lds_max;
 }
 
@@ -646,7 +694,7 @@ template <typename real, int DIM, int VEC, int UNR, int PD, bool NTS>
 static void stream_kernel_z(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
     const real *p = (const real *)params_buf<real>(c, c->pass_parity);
-    const size_t acc = stream_acc_bytes(c->geo, c->sblock);
+    const size_t acc = stream_acc_bytes(c->geo, DIM, c->sblock);
     if (use_roles(c, c->zr, lds, false, c->sblock))  // one plane per wave: role-ordered z-tables after the slots
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, PD, NTS, true>), dim3(nb), dim3(c->sblock),
                            lds + role_table_bytes(c, false) + acc, s, make_args(c), (const real *)src, (real *)dst,
@@ -666,25 +714,34 @@ static void stream_kernel_u(bgk_ctx *c, int nb, size_t lds, const void *src, voi
 template <typename real, int DIM, int VEC>
 static void stream_kernel(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
-    switch (c->unroll) {
-    case 2: stream_kernel_u<real, DIM, VEC, 2, 1>(c, nb, lds, src, dst, s); break;
-    case 3: stream_kernel_u<real, DIM, VEC, 1, 2>(c, nb, lds, src, dst, s); break;
-    case 4: stream_kernel_u<real, DIM, VEC, 1, 3>(c, nb, lds, src, dst, s); break;
-    default: stream_kernel_u<real, DIM, VEC, 1, 1>(c, nb, lds, src, dst, s); break;
+    if constexpr (DIM == 3) {  // 3D: one or two planes per stage, one stage in flight
+        if (c->unroll == 2) stream_kernel_u<real, DIM, VEC, 2, 1>(c, nb, lds, src, dst, s);
+        else stream_kernel_u<real, DIM, VEC, 1, 1>(c, nb, lds, src, dst, s);
+    } else {
+        switch (c->unroll) {
+        case 2: stream_kernel_u<real, DIM, VEC, 2, 1>(c, nb, lds, src, dst, s); break;
+        case 3: stream_kernel_u<real, DIM, VEC, 1, 2>(c, nb, lds, src, dst, s); break;
+        case 4: stream_kernel_u<real, DIM, VEC, 1, 3>(c, nb, lds, src, dst, s); break;
+        default: stream_kernel_u<real, DIM, VEC, 1, 1>(c, nb, lds, src, dst, s); break;
+        }
     }
 }
 
 template <typename real, int DIM>
 static void stream_dispatch(bgk_ctx *c, int nb, size_t lds, const void *src, void *dst, hipStream_t s)
 {
-    if constexpr (sizeof(real) == 4) {
-        if (c->vec == 4) {
-            stream_kernel<real, DIM, 4>(c, nb, lds, src, dst, s);
-            return;
+    if constexpr (DIM == 3) {  // one jx per lane task
+        stream_kernel<real, DIM, 1>(c, nb, lds, src, dst, s);
+    } else {
+        if constexpr (sizeof(real) == 4) {
+            if (c->vec == 4) {
+                stream_kernel<real, DIM, 4>(c, nb, lds, src, dst, s);
+                return;
+            }
         }
+        if (c->vec == 2) stream_kernel<real, DIM, 2>(c, nb, lds, src, dst, s);
+        else stream_kernel<real, DIM, 1>(c, nb, lds, src, dst, s);
     }
-    if (c->vec == 2) stream_kernel<real, DIM, 2>(c, nb, lds, src, dst, s);
-    else stream_kernel<real, DIM, 1>(c, nb, lds, src, dst, s);
 }
 
 template <typename real>
@@ -692,7 +749,7 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
 {
     const int items = c->ncells * c->vsplit;
     const int nb = c->persist ? std::min(items, c->persist * c->ncu) : items;
-    const int nslot = c->dim == 1 ? 7 : 13;
+    const int nslot = 1 + 6 * c->dim;
     const size_t lds = (size_t)nslot * c->geo.pe * sizeof(real);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -726,7 +783,8 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         else
             hipLaunchKernelGGL((k_shift<real, false, false>), dim3(nb), dim3(c->sblock), 0, s, a, (const real *)src,
                                (real *)dst, p, c->partial);
-    } else if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
+    } else if (c->dim == 3) stream_dispatch<real, 3>(c, nb, lds, src, dst, s);
+    else if (c->dim == 2) stream_dispatch<real, 2>(c, nb, lds, src, dst, s);
     else stream_dispatch<real, 1>(c, nb, lds, src, dst, s);
     HIP_TRY(c, hipGetLastError());
     if (c->timing) HIP_TRY(c, hipEventRecord(e1, s));
@@ -1009,6 +1067,7 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     for (const void *q : {f_n, lam_next, (const void *)lam_n})
         if (overlaps(ws, 2 * fb, q, fb))
             return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: the workspace must not overlap f_n, lam_next or lam_n");
+    if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: one- and two-dimensional kinds only");
     if (!ctx->adjoint_fits)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
@@ -1044,6 +1103,7 @@ extern "C" int bgk_lid_shear(bgk_ctx *ctx, const void *f, double *L, void *strea
 {
     if (!ctx) return BGK_E_INVALID;
     if (!f || !L) return fail(ctx, BGK_E_INVALID, "bgk_lid_shear: NULL buffer");
+    if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_lid_shear: two-dimensional cavities only");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, L, nullptr, nullptr, s)
                                       : lid<float>(ctx, f, L, nullptr, nullptr, s);
@@ -1055,6 +1115,7 @@ extern "C" int bgk_lid_shear_grad(bgk_ctx *ctx, const void *f, void *lam, double
     if (!f || !lam || !grad_params) return fail(ctx, BGK_E_INVALID, "bgk_lid_shear_grad: NULL buffer");
     if (lam == f) return fail(ctx, BGK_E_ALIAS, "bgk_lid_shear_grad: lam must not alias f");
     if (ctx->geo.red) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_lid_shear_grad: not in the reduced velocity space");
+    if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_lid_shear_grad: two-dimensional cavities only");
     hipStream_t s = (hipStream_t)stream;
     return ctx->precision == BGK_FP64 ? lid<double>(ctx, f, nullptr, lam, grad_params, s)
                                       : lid<float>(ctx, f, nullptr, lam, grad_params, s);
@@ -1192,6 +1253,7 @@ static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
                 for (int ps : {0, 2, 4}) {
                     if (rc) break;
                     if (c->shift && unroll != 1) continue;  // k_shift has one pipeline form
+                    if (c->dim == 3 && unroll > 2) continue;  // 3D: modes 1 and 2 only
                     if (ps && c->ncells * vs <= ps * c->ncu) continue;  // grid already resident
                     Cand k{0.0, vec, unroll, vs, ps};
                     rc = measure(k, &k.us);
@@ -1249,7 +1311,8 @@ extern "C" int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int
 {
     if (!ctx) return BGK_E_INVALID;
     if (!(vec == 1 || vec == 2 || vec == 4) || !vec_valid(ctx, vec) || unroll < 1 || unroll > 4 ||
-        (ctx->shift && unroll != 1) || vsplit < 1 || vsplit > ctx->vsplit_max || persist < 0 || persist > 64)
+        (ctx->shift && unroll != 1) || (ctx->dim == 3 && unroll > 2) || vsplit < 1 || vsplit > ctx->vsplit_max ||
+        persist < 0 || persist > 64)
         return fail(ctx, BGK_E_INVALID, "bgk_set_launch: shape not valid for this context");
     set_shape(ctx, vec, unroll, vsplit, persist);
     return BGK_OK;

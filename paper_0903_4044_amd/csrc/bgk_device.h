@@ -36,19 +36,21 @@
 namespace bgk {
 
 constexpr int NVMAX = 128;        // per velocity component
-constexpr int KIND_SHOCK = 0, KIND_CAVITY = 1, KIND_PER1 = 2, KIND_PER2 = 3;
+constexpr int KIND_SHOCK = 0, KIND_CAVITY = 1, KIND_PER1 = 2, KIND_PER2 = 3, KIND_CAV3 = 4, KIND_PER3 = 5;
 constexpr int MODE_FIRST = 0, MODE_MID = 1, MODE_FINAL = 2;
-constexpr int NQ = 9;             // moment sums per cell: 1, vx, vy, vz, |v|^2, 4 half fluxes
+// moment sums per cell: 1, vx, vy, vz, |v|^2, and the half-range fluxes
+// sum_{v_a < 0} |v_a| f, sum_{v_a > 0} v_a f of x (5, 6), y (7, 8), z (9, 10)
+constexpr int NQ = 11;
 
 struct Inst {
-    int kind, nx, ny, ncell;
+    int kind, nx, ny, nz, ncell;
     int cell0;      // first global cell index of the instance
     int pseudo0;    // first global params entry of its ghost sources
     int strang, minmod;
     int shift;      // translation form of the streaming step (k_shift)
     int conservative;  // relaxations use the effective Maxwellian parameters
     long long f0;   // element offset of the instance in f
-    double cx, cy;  // dt / dx, dt / dy
+    double cx, cy, cz;  // dt / dx, dt / dy, dt / dz
     double dt, kn, omega;
     double tw, uw;  // wall temperature, lid speed
     double x0, dx;  // spatial origin and cell size along x
@@ -62,6 +64,7 @@ struct Geo {
     double lo[3], dv[3];
     double dV;
     int red;                    // components integrated out: 1 v_z (2D kinds), 2 v_y and v_z (1D kinds)
+    int zneg;                   // planes with v_z < 0 (they come first)
     int pe;                     // params entry stride (elements)
     int tx1, ty1, tx2, ty2, tz; // entry offsets
 };
@@ -112,18 +115,21 @@ constexpr int STRIP = 16;
 
 __device__ __forceinline__ int strip_cell(const Inst &I, int q)
 {
+    // 3D instances: the planes iz one after the other, each walked in strips
+    const int pl = I.nx * I.ny, iz = q / pl;
+    q -= iz * pl;
     const int W = I.nx < STRIP ? I.nx : STRIP;
     const int span = W * I.ny;
     const int nfull = I.nx / W;
     if (q < nfull * span) {
         const int k = q / span, r = q - k * span;
         const int iy = r / W;
-        return iy * I.nx + k * W + (r - iy * W);
+        return iz * pl + iy * I.nx + k * W + (r - iy * W);
     }
     const int rem = I.nx - nfull * W;
     const int r = q - nfull * span;
     const int iy = r / rem;
-    return iy * I.nx + nfull * W + (r - iy * rem);
+    return iz * pl + iy * I.nx + nfull * W + (r - iy * rem);
 }
 
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
@@ -247,8 +253,10 @@ __device__ __forceinline__ void block_sum_store(double (&acc)[N], double *out)
 }
 
 // Per-p (one (jx, jy) column, summed over its jz range) contribution to the
-// nine moment sums: A0 = sum h, Az = sum vz h, Azz = sum vz^2 h.
-__device__ __forceinline__ void fold_column(double (&acc)[NQ], double vx, double vy, double A0, double Az, double Azz)
+// moment sums: A0 = sum h, Az = sum vz h, Azz = sum vz^2 h, and the z
+// half-range fluxes Azm = sum_{vz<0} |vz| h, Azp = sum_{vz>0} vz h.
+__device__ __forceinline__ void fold_column(double (&acc)[NQ], double vx, double vy, double A0, double Az, double Azz,
+                                            double Azm = 0.0, double Azp = 0.0)
 {
     acc[0] += A0;
     acc[1] += vx * A0;
@@ -259,21 +267,25 @@ __device__ __forceinline__ void fold_column(double (&acc)[NQ], double vx, double
     acc[6] += vx > 0.0 ? vx * A0 : 0.0;
     acc[7] += vy < 0.0 ? -vy * A0 : 0.0;
     acc[8] += vy > 0.0 ? vy * A0 : 0.0;
+    acc[9] += Azm;
+    acc[10] += Azp;
 }
 
 // The same fold into this thread's slots of the workgroup's LDS accumulators
 // (acc[q * stride]): the nine sums do not occupy registers across a task.
 // The sums pass through fold_column itself, so the arithmetic (and its
 // rounding) is that of the register form.
+// NS: the sums kept (9 without the z half fluxes, 11 with them).
+template <int NS = NQ>
 __device__ __forceinline__ void fold_column_lds(double *acc, int stride, double vx, double vy, double A0, double Az,
-                                                double Azz)
+                                                double Azz, double Azm = 0.0, double Azp = 0.0)
 {
     double t[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) t[q] = acc[q * stride];
-    fold_column(t, vx, vy, A0, Az, Azz);
+    for (int q = 0; q < NQ; ++q) t[q] = q < NS ? acc[q * stride] : 0.0;
+    fold_column(t, vx, vy, A0, Az, Azz, Azm, Azp);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q * stride] = t[q];
+    for (int q = 0; q < NS; ++q) acc[q * stride] = t[q];
 }
 
 template <typename T, int N>
@@ -334,13 +346,13 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
     int z0, z1;
     chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const int ngrp = g.npl / VEC;
-    double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = threadIdx.x; q < ngrp; q += blockDim.x) {
         const int p0 = q * VEC, jx0 = p0 % g.nvx, jy = p0 / g.nvx;
         double A0[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) A0[e] = 0.0;
-        double Az = 0, Azz = 0;
+        double Az = 0, Azz = 0, Azm = 0, Azp = 0;
 #pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
             const V h = ld<V>(fc, (uint32_t)((jz * g.npl + p0) * (int)sizeof(real)));
@@ -354,10 +366,13 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
             }
             Az += w.z * sh;
             Azz += w.zz * sh;
+            if (w.z < 0.0) Azm -= w.z * sh;
+            else Azp += w.z * sh;
         }
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-            fold_column(acc, vnode(g, 0, jx0 + e), vnode(g, 1, jy), A0[e], e == 0 ? Az : 0.0, e == 0 ? Azz : 0.0);
+            fold_column(acc, vnode(g, 0, jx0 + e), vnode(g, 1, jy), A0[e], e == 0 ? Az : 0.0, e == 0 ? Azz : 0.0,
+                        e == 0 ? Azm : 0.0, e == 0 ? Azp : 0.0);
     }
     block_sum_store<NQ>(acc, partial + (long long)L * NQ);
 }
@@ -539,6 +554,8 @@ __device__ __forceinline__ void wave_table_sums(const Geo &g, const Tables &t, d
                 s0 += w.m * x;
                 s1 += w.z * x;
                 s2 += w.zz * x;
+                if (w.z < 0.0) sm += -w.z * x;
+                else sp += w.z * x;
                 continue;
             }
             const double v = vnode(g, a, lane + W * q);
@@ -775,16 +792,48 @@ __device__ __forceinline__ void write_entry(const Geo &g, real *E, double c0, do
     }
 }
 
-// Wall geometry: wall w = 0 left (+x inward), 1 right (-x), 2 bottom (+y), 3 top (-y).
+// Wall geometry: wall w = 0 left (+x inward), 1 right (-x), 2 bottom (+y),
+// 3 top (-y), and for 3D instances 4 back (+z), 5 front (-z): wall w lies
+// across axis w / 2, on the low side for even w.  The wall entries of an
+// instance come wall by wall; within wall w the face cells are numbered by
+// the other two coordinates, the lower axis fastest: (iy, iz) for x walls,
+// (ix, iz) for y walls, (ix, iy) for z walls.
+__device__ __forceinline__ int wall_size(const Inst &I, int w)
+{
+    return w < 2 ? I.ny * I.nz : w < 4 ? I.nx * I.nz : I.nx * I.ny;
+}
+
 __device__ __forceinline__ int wall_of_entry(const Inst &I, int k, int *pos)
 {
-    if (k < I.ny) { *pos = k; return 0; }
-    k -= I.ny;
-    if (k < I.ny) { *pos = k; return 1; }
-    k -= I.ny;
-    if (k < I.nx) { *pos = k; return 2; }
-    *pos = k - I.nx;
-    return 3;
+    int w = 0;
+    while (w < 5 && k >= wall_size(I, w)) k -= wall_size(I, w++);
+    *pos = k;
+    return w;
+}
+
+// First entry of wall w within the instance's wall entries.
+__device__ __forceinline__ int wall_offset(const Inst &I, int w)
+{
+    int o = 0;
+    for (int v = 0; v < w; ++v) o += wall_size(I, v);
+    return o;
+}
+
+// Instance-local cell next to position pos of wall w.
+__device__ __forceinline__ int wall_cell(const Inst &I, int w, int pos)
+{
+    const int axis = w >> 1;
+    const bool low = (w & 1) == 0;
+    if (axis == 0) {
+        const int iy = pos % I.ny, iz = pos / I.ny;
+        return (iz * I.ny + iy) * I.nx + (low ? 0 : I.nx - 1);
+    }
+    if (axis == 1) {
+        const int ix = pos % I.nx, iz = pos / I.nx;
+        return (iz * I.ny + (low ? 0 : I.ny - 1)) * I.nx + ix;
+    }
+    const int ix = pos % I.nx, iy = pos / I.nx;
+    return ((low ? 0 : I.nz - 1) * I.ny + iy) * I.nx + ix;
 }
 
 // Table entry e (a cell, or a ghost source after the ncells cells), computed by
@@ -823,29 +872,27 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     // g0 being the wall-adjacent cell of the streaming input, g0 = c0 h + cA e1 + cB e2.
     int pos;
     const int w = wall_of_entry(I, k, &pos);
-    const int axis = w < 2 ? 0 : 1;
-    const int adj = w == 0 ? pos * I.nx : w == 1 ? pos * I.nx + I.nx - 1 : w == 2 ? pos : (I.ny - 1) * I.nx + pos;
+    const int axis = w >> 1;
+    const int adj = wall_cell(I, w, pos);
     cell_coefficients<W>(A, I, I.cell0 + adj, mode, partial, C, true);
     const double VW[3] = {w == 3 ? I.uw : 0.0, 0.0, 0.0};
     Tables tw;
     lane_tables<W>(g, VW, I.tw, tw);
     double sw[3][5];
     wave_table_sums<W>(g, tw, sw, true);
-    const int b1 = axis == 0 ? 1 : 0, b2 = 2;  // the two other components
-    // incident: v_axis < 0 for walls 0, 2 (sum index 3), v_axis > 0 for walls 1, 3 (index 4)
-    const bool lowwall = (w == 0 || w == 2);
-    const double hin1 = axis == 0 ? (lowwall ? C.s1[0][3] : C.s1[0][4]) : (lowwall ? C.s1[1][3] : C.s1[1][4]);
-    const double hin2 = axis == 0 ? (lowwall ? C.s2[0][3] : C.s2[0][4]) : (lowwall ? C.s2[1][3] : C.s2[1][4]);
-    const double out_w = axis == 0 ? (lowwall ? sw[0][4] : sw[0][3]) : (lowwall ? sw[1][4] : sw[1][3]);
-    const double o1 = axis == 0 ? C.s1[1][0] : C.s1[0][0], o2 = axis == 0 ? C.s2[1][0] : C.s2[0][0];
-    const double ow = axis == 0 ? sw[1][0] : sw[0][0];
-    const double hraw = w == 0 ? C.raw[5] : w == 1 ? C.raw[6] : w == 2 ? C.raw[7] : C.raw[8];
+    const int b1 = axis == 0 ? 1 : 0, b2 = axis == 2 ? 1 : 2;  // the two other components
+    // incident: v_axis < 0 for the low walls (sum index 3), v_axis > 0 for the high ones (index 4)
+    const bool lowwall = (w & 1) == 0;
+    const double hin1 = lowwall ? C.s1[axis][3] : C.s1[axis][4];
+    const double hin2 = lowwall ? C.s2[axis][3] : C.s2[axis][4];
+    const double out_w = lowwall ? sw[axis][4] : sw[axis][3];
+    const double o1 = C.s1[b1][0], o2 = C.s2[b1][0], ow = sw[b1][0];
+    const double hraw = C.raw[5 + w];
     double flux = C.c0 * hraw;
     if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * C.s1[b2][0];
     if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * C.s2[b2][0];
     const double pw = pi_t_m32(I.tw);
     const double den = pw * g.dV * out_w * ow * sw[b2][0];
-    (void)b1;
     write_entry<real, W>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
     if ((threadIdx.x & (W - 1)) == 1) E[1] = (real)(flux / den);  // n_W, read by the reverse sweep
 }
@@ -878,19 +925,34 @@ __global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__
 // in each direction is {i - 2s, i - s, i, i + s} with s = sign(v_d); a slot
 // table resolves every stencil position (interior cell, periodic image,
 // far-field Maxwellian, wall-adjacent cell or emitted wall Maxwellian) once
-// per workgroup, so the inner loop is branch-free.
+// per workgroup, so the inner loop is branch-free.  In three dimensions the
+// sign of v_z, and with it the z stencil, changes along a lane's jz loop:
+// the loop runs in two sweeps, the planes with v_z < 0 and then those with
+// v_z > 0, each with the z taps of its sign.
 //
-// Slots: 0 centre; 1 + 3*si + m (x direction), 7 + 3*si + m (y direction),
-// si = 0 for s = +1, 1 for s = -1; m = 0, 1, 2 for k = -2, -1, +1.
+// Slots: 0 centre; 1 + 6 d + 3 si + m for direction d (x, y, z), si = 0
+// for s = +1, 1 for s = -1; m = 0, 1, 2 for k = -2, -1, +1.
+constexpr int MAXSLOT = 19;
+struct SlotInfo { int cell[MAXSLOT]; int par[MAXSLOT]; uint32_t off[MAXSLOT]; };  // off: byte offset of the slot cell's h
 
-struct SlotInfo { int cell[13]; int par[13]; uint32_t off[13]; };  // off: byte offset of the slot cell's h
-
-__device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int pos, int other, int sgn, int own, int *cell, int *par)
+// The stencil position `delta` cells from cell (ix, iy, iz) along `axis`,
+// for velocities whose component along it has sign sgn: the cell whose h is
+// read and the table entry that relaxes it.  Inside the instance: that cell.
+// Periodic kinds: its image.  Shock: the far-field entry (c0 = 0, so the
+// cell read is irrelevant; the own cell).  Walls: for velocities leaving the
+// wall, the wall's emitted-Maxwellian entry of the face cell; for velocities
+// arriving at it, the wall-adjacent cell itself.
+__device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int ix, int iy, int iz, int delta, int sgn,
+                                             int own, int *cell, int *par)
 {
-    const int N = axis == 0 ? I.nx : I.ny;
-    auto at = [&](int q) { return axis == 0 ? other * I.nx + q : q * I.nx + other; };
+    const int N = axis == 0 ? I.nx : axis == 1 ? I.ny : I.nz;
+    const int pos = (axis == 0 ? ix : axis == 1 ? iy : iz) + delta;
+    auto at = [&](int q) {
+        const int x = axis == 0 ? q : ix, y = axis == 1 ? q : iy, z = axis == 2 ? q : iz;
+        return (z * I.ny + y) * I.nx + x;
+    };
     if (pos >= 0 && pos < N) { *cell = at(pos); *par = I.cell0 + *cell; return; }
-    if (I.kind == KIND_PER1 || I.kind == KIND_PER2) {
+    if (I.kind == KIND_PER1 || I.kind == KIND_PER2 || I.kind == KIND_PER3) {
         const int q = ((pos % N) + N) % N;
         *cell = at(q); *par = I.cell0 + *cell; return;
     }
@@ -898,10 +960,10 @@ __device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int pos, i
     const bool low = pos < 0;
     const bool emitted = low ? (sgn > 0) : (sgn < 0);
     if (emitted) {
-        const int w = axis == 0 ? (low ? 0 : 1) : (low ? 2 : 3);
-        const int off = w == 0 ? 0 : w == 1 ? I.ny : w == 2 ? 2 * I.ny : 2 * I.ny + I.nx;
+        const int w = 2 * axis + (low ? 0 : 1);
+        const int face = axis == 0 ? iz * I.ny + iy : axis == 1 ? iz * I.nx + ix : iy * I.nx + ix;
         *cell = own;
-        *par = I.pseudo0 + off + other;
+        *par = I.pseudo0 + wall_offset(I, w) + face;
     } else {
         *cell = at(low ? 0 : N - 1);
         *par = I.cell0 + *cell;
@@ -1023,12 +1085,15 @@ __global__ void __launch_bounds__(256)
 {
     using V = vec_t<real, VEC>;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NSLOT = DIM == 1 ? 7 : 13;
+    constexpr int NSLOT = 1 + 6 * DIM;
     real *sp = reinterpret_cast<real *>(smem);
     __shared__ SlotInfo SI;
     const Geo &g = A.g;
-    constexpr int NROLE = DIM == 1 ? 4 : 7;   // centre, x (-2, -1, +1), y (-2, -1, +1)
-    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
+    constexpr int NROLE = 1 + 3 * DIM;        // centre, x (-2, -1, +1), y (-2, -1, +1), z (-2, -1, +1)
+    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y; the z roles follow the plane)
+    // moment sums kept per thread: without z streaming the z half fluxes are
+    // zero and stay out of LDS
+    constexpr int NACC = DIM == 3 ? NQ : 9;
     // Dynamic LDS: the slot entries (NSLOT table entries), the role-ordered
     // z-tables (one-residue form), then 8-byte aligned: this thread's moment
     // sums (acc[q * blockDim.x]) and the node tables, v_z and v_z^2 of every
@@ -1040,7 +1105,7 @@ __global__ void __launch_bounds__(256)
     // fold read them instead of recomputing the nodes in double).
     double *const acc_base = reinterpret_cast<double *>(
         smem + stream_acc_offset<real>(NSLOT * g.pe + (ZU ? NCOMBO * g.nvz * NROLE * 2 : 0)));
-    double *const vzt = acc_base + NQ * blockDim.x;
+    double *const vzt = acc_base + NACC * blockDim.x;
     double *const vxt = vzt + 2 * g.nvz;
     double *const vyt = vxt + g.nvx;
     for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) {
@@ -1063,7 +1128,7 @@ __global__ void __launch_bounds__(256)
     const int c = strip_cell(I, gq - I.cell0);
     const int gc = I.cell0 + c;
     const int L = gc * A.vsplit + split;  // (cell, chunk) index of the partial sums
-    const int ix = c % I.nx, iy = c / I.nx;
+    const int pl = I.nx * I.ny, iz = c / pl, ix = c % I.nx, iy = (c - iz * pl) / I.nx;
 
     if (threadIdx.x < NSLOT) {
         const int s = threadIdx.x;
@@ -1072,8 +1137,7 @@ __global__ void __launch_bounds__(256)
         else {
             const int d = (s - 1) / 6, r = (s - 1) % 6, si = r / 3, m = r % 3;
             const int sgn = si == 0 ? 1 : -1, k = m == 0 ? -2 : (m == 1 ? -1 : 1);
-            if (d == 0) resolve_slot(I, 0, ix + sgn * k, iy, sgn, c, &cell, &par);
-            else resolve_slot(I, 1, iy + sgn * k, ix, sgn, c, &cell, &par);
+            resolve_slot(I, d, ix, iy, iz, sgn * k, sgn, c, &cell, &par);
         }
         SI.cell[s] = cell;
         SI.par[s] = par;
@@ -1090,8 +1154,11 @@ __global__ void __launch_bounds__(256)
         const int n = NCOMBO * g.nvz * NROLE;
         for (int t = threadIdx.x; t < n; t += blockDim.x) {
             const int role = t % NROLE, jz = (t / NROLE) % g.nvz, combo = t / (NROLE * g.nvz);
-            const int sx = combo & 1, sy = combo >> 1;
-            const int slot = role == 0 ? 0 : role <= 3 ? 1 + 3 * sx + (role - 1) : 7 + 3 * sy + (role - 4);
+            const int sx = combo & 1, sy = combo >> 1, sz = jz < g.zneg ? 1 : 0;
+            const int slot = role == 0   ? 0
+                             : role <= 3 ? 1 + 3 * sx + (role - 1)
+                             : role <= 6 ? 7 + 3 * sy + (role - 4)
+                                         : 13 + 3 * sz + (role - 7);
             const real *E = sp + slot * g.pe + g.tz + 2 * jz;
             tzr[2 * t] = E[0];
             tzr[2 * t + 1] = E[1];
@@ -1116,7 +1183,7 @@ __global__ void __launch_bounds__(256)
     const float c0m1_hi = (float)c0m1, c0m1_lo = (float)(c0m1 - (double)c0m1_hi);
     double *acc = acc_base + threadIdx.x;  // this thread's moment sums, zeroed per work item
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q * blockDim.x] = 0.0;
+    for (int q = 0; q < NACC; ++q) acc[q * blockDim.x] = 0.0;
 
     // (jx group, jy) of a one-residue task by a float reciprocal: task <
     // 2^14 and ngx <= 128, so (task + 1/2) / ngx stays at least 1/256 away
@@ -1147,9 +1214,9 @@ __global__ void __launch_bounds__(256)
         const Tap<real, VEC> xa = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 0, p0, jx0, jy);
         const Tap<real, VEC> xb = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 1, p0, jx0, jy);
         const Tap<real, VEC> xd = make_tap_slot<real, VEC>(g, sp, SI, 1 + 3 * sx + 2, p0, jx0, jy);
-        Tap<real, VEC> ya, yb, yd;
+        Tap<real, VEC> ya, yb, yd, za, zb, zd;
         V Cy = 0, ky = 0;
-        if constexpr (DIM == 2) {
+        if constexpr (DIM >= 2) {
             const int sy = vy > 0.0 ? 0 : 1;
             const real cy = (real)(fabs(vy) * I.cy);
             Cy = cy;
@@ -1162,8 +1229,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int k = 0; k < VEC; ++k) A0[k] = 0.0;
         double Az = 0.0, Azz = 0.0;
-        constexpr int NT = DIM == 1 ? 4 : 7;
-        const Tap<real, VEC> *taps[7] = {&tc, &xa, &xb, &xd, &ya, &yb, &yd};
+        constexpr int NT = NROLE;
+        const Tap<real, VEC> *taps[10] = {&tc, &xa, &xb, &xd, &ya, &yb, &yd, &za, &zb, &zd};
         // this lane's z-table rows (ZU): combination of the signs of v_x, v_y
         const int combo = DIM == 1 ? sx : sx + 2 * (vy > 0.0 ? 0 : 1);
         const real *tzl = tzr + combo * g.nvz * NROLE * 2;
@@ -1197,9 +1264,16 @@ __global__ void __launch_bounds__(256)
             V dx = flux_diff<real, VEC>(xa.relax_ab(hv[1], ta[1], tb[1]), xb.relax_ab(hv[2], ta[2], tb[2]), u0,
                                         xd.relax_ab(hv[3], ta[3], tb[3]), Cx, kx);
             V dy = 0;
-            if constexpr (DIM == 2)
+            if constexpr (DIM >= 2)
                 dy = flux_diff<real, VEC>(ya.relax_ab(hv[4], ta[4], tb[4]), yb.relax_ab(hv[5], ta[5], tb[5]), u0,
                                           yd.relax_ab(hv[6], ta[6], tb[6]), Cy, ky);
+            if constexpr (DIM == 3) {
+                // the plane's Courant number along z (v_z of the plane from LDS)
+                const real cz = (real)(fabs(vzt[2 * jz]) * I.cz);
+                const V Cz = cz, kz = lim ? (real)0.5 * ((real)1 - cz) : (real)0;
+                dy += flux_diff<real, VEC>(za.relax_ab(hv[7], ta[7], tb[7]), zb.relax_ab(hv[8], ta[8], tb[8]), u0,
+                                           zd.relax_ab(hv[9], ta[9], tb[9]), Cz, kz);
+            }
             V r;
             if constexpr (sizeof(real) == 4) {
                 // New value h + d with the increment d = (c0 - 1) h + M - fluxes
@@ -1256,9 +1330,12 @@ __global__ void __launch_bounds__(256)
         // flight per register than two-plane stages, where half the buffers
         // are being computed on).
         const int zs = UNR * A.zr;
-        int jz = z0 + zr;
-        if (jz < z1) {
-            const int zlast = ZU ? z1 - 1 : z1 - 1 - ((z1 - 1 - (z0 + zr)) % A.zr);  // last jz of this lane's residue
+        // One sweep over the planes [zb0, zb1) of the chunk: the lane's first
+        // plane there is the first of its residue class (chunk start + zr).
+        auto sweep = [&](int zb0, int zb1) {
+        int jz = zb0 + ((z0 + zr - zb0) % A.zr + A.zr) % A.zr;
+        if (jz < zb1) {
+            const int zlast = ZU ? zb1 - 1 : zb1 - 1 - ((zb1 - 1 - jz) % A.zr);  // last jz of this lane's residue
             const uint32_t zlast_off = (uint32_t)zlast * zstep, zr_off = (uint32_t)A.zr * zstep;
             const uint32_t zs_off = (uint32_t)zs * zstep;
             uint32_t zoff = (uint32_t)jz * zstep;
@@ -1286,11 +1363,11 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) hp[e] = hash32((ieven + (uint32_t)e) ^ key);
                     finish(h[0], j, off, hp, std::true_type{});
-                    if (j + 1 < z1) finish(h[1], j + 1, off + zr_off, hp, std::true_type{});
+                    if (j + 1 < zb1) finish(h[1], j + 1, off + zr_off, hp, std::true_type{});
                 } else {
 #pragma unroll
                     for (int u = 0; u < UNR; ++u)
-                        if (j + u * A.zr < z1)
+                        if (j + u * A.zr < zb1)
                             finish(h[u], j + u * A.zr, off + (uint32_t)u * zr_off, U(0), std::false_type{});
                 }
             };
@@ -1302,12 +1379,12 @@ __global__ void __launch_bounds__(256)
                     compute_stage(ha, jz, zoff);
                     jz += zs;
                     zoff += zs_off;
-                    if (jz >= z1) break;
+                    if (jz >= zb1) break;
                     load_stage(ha, zoff + zs_off);
                     compute_stage(hb, jz, zoff);
                     jz += zs;
                     zoff += zs_off;
-                    if (jz >= z1) break;
+                    if (jz >= zb1) break;
                 }
             } else {
                 // One plane per stage.  With one residue a lane's planes are
@@ -1331,7 +1408,7 @@ __global__ void __launch_bounds__(256)
                     // renames the copies)
                     V ha[1][NT];
                     load_stage(ha, zoff);
-                    for (; jz < z1; jz += zs, zoff += zs_off) {
+                    for (; jz < zb1; jz += zs, zoff += zs_off) {
                         V hn[1][NT];
                         load_stage(hn, zoff + zs_off);
                         stage1(ha, jz, zoff);
@@ -1351,23 +1428,47 @@ __global__ void __launch_bounds__(256)
                             stage1(hr[r], jz, zoff);
                             jz += zs;
                             zoff += zs_off;
-                            if (jz >= z1) goto ring_done;
+                            if (jz >= zb1) goto ring_done;
                         }
                     }
                 ring_done:;
                 }
             }
         }
+        };
+        double Azm = 0.0, Azp = 0.0;
+        if constexpr (DIM == 3) {
+            // planes with v_z < 0 (upwind neighbours on the +z side, s = -1),
+            // then those with v_z > 0 (s = +1); Az splits into the two half
+            // fluxes on the way
+            za = make_tap_slot<real, VEC>(g, sp, SI, 16, p0, jx0, jy);
+            zb = make_tap_slot<real, VEC>(g, sp, SI, 17, p0, jx0, jy);
+            zd = make_tap_slot<real, VEC>(g, sp, SI, 18, p0, jx0, jy);
+            sweep(z0, min(z1, g.zneg));
+            const double Aneg = Az;
+            Az = 0.0;
+            za = make_tap_slot<real, VEC>(g, sp, SI, 13, p0, jx0, jy);
+            zb = make_tap_slot<real, VEC>(g, sp, SI, 14, p0, jx0, jy);
+            zd = make_tap_slot<real, VEC>(g, sp, SI, 15, p0, jx0, jy);
+            sweep(max(z0, g.zneg), z1);
+            Azm = -Aneg;
+            Azp = Az;
+            Az = Aneg + Az;
+        } else {
+            sweep(z0, z1);
+        }
 #pragma unroll
         for (int k = 0; k < VEC; ++k)
-            if (g.red) fold_column_lds(acc, blockDim.x, vxt[jx0 + k], vy, k == 0 ? Az : 0.0, 0.0, k == 0 ? Azz : 0.0);
-            else fold_column_lds(acc, blockDim.x, vxt[jx0 + k], vy, A0[k], k == 0 ? Az : 0.0, k == 0 ? Azz : 0.0);
+            if (g.red) fold_column_lds<NACC>(acc, blockDim.x, vxt[jx0 + k], vy, k == 0 ? Az : 0.0, 0.0, k == 0 ? Azz : 0.0);
+            else fold_column_lds<NACC>(acc, blockDim.x, vxt[jx0 + k], vy, A0[k], k == 0 ? Az : 0.0,
+                                       k == 0 ? Azz : 0.0, k == 0 ? Azm : 0.0, k == 0 ? Azp : 0.0);
     }
     {
-        double sums[NQ];
+        double sums[NACC];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sums[q] = acc[q * blockDim.x];
-        block_sum_store<NQ>(sums, partial + (long long)L * NQ);
+        for (int q = 0; q < NACC; ++q) sums[q] = acc[q * blockDim.x];
+        block_sum_store<NACC>(sums, partial + (long long)L * NQ);
+        if (threadIdx.x >= NACC && threadIdx.x < NQ) partial[(long long)L * NQ + threadIdx.x] = 0.0;
     }
     __syncthreads();  // LDS (slots, tables, reduction) is reused by the next item
     }
@@ -1444,7 +1545,7 @@ __global__ void __launch_bounds__(256)
         const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
         const uint32_t ecell = (uint32_t)c * (uint32_t)g.nv;
         const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
-        double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[NQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if constexpr (STAGE) {
             // the previous item's reads of stz ended at its closing barrier
             const int nst = 2 * g.nvx * (z1 - z0);

@@ -11,9 +11,11 @@ density in n_r, length in the domain unit, time in length / sqrt(2 R T_r)):
 
     kind       'shock' (1D, far-field Maxwellian ghosts, Sec. 4.1),
                'cavity' (2D, diffuse walls, Sec. 5.1),
-               'periodic1d' / 'periodic2d' (test problems)
-    nx, ny     spatial cells (ny = 1 for 1D kinds)
-    x0, x1, y0, y1   spatial box
+               'cavity3d' (3D: six diffuse walls, the lid at y = y1 moving along x;
+               Sec. 2.1 carries the method over to three directions),
+               'periodic1d' / 'periodic2d' / 'periodic3d' (test problems)
+    nx, ny, nz spatial cells (ny = 1 for 1D kinds, nz = 1 for 1D and 2D kinds)
+    x0, x1, y0, y1, z0, z1   spatial box
     nv         (Nvx, Nvy, Nvz) velocity cells (Sec. 2.1)
     vlo, vhi   velocity box per component
     kn, omega  collision frequency nu = n T^(1-omega) / Kn
@@ -44,7 +46,7 @@ NOISE_SEED = 9034045
 
 
 def _base(**kw):
-    d = dict(kind="shock", nx=1, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+    d = dict(kind="shock", nx=1, ny=1, nz=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0,
              nv=(8, 8, 8), vlo=(-4.0, -4.0, -4.0), vhi=(4.0, 4.0, 4.0),
              kn=1.0, omega=0.5, cfl=0.5, dt=0.0, mach=0.0, lid_mach=0.0,
              t_wall=1.0, splitting="strang", limiter="minmod", maxwellian="point",
@@ -164,8 +166,14 @@ def uniform(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(lo, hi, shape)
 
 
+def ndim(p: dict) -> int:
+    """Streaming directions of a problem."""
+    return 3 if p["kind"] in ("cavity3d", "periodic3d") else 2 if p["kind"] in ("cavity", "periodic2d") else 1
+
+
 def ncells(p: dict) -> int:
-    return int(p["nx"]) * (int(p["ny"]) if p["kind"] in ("cavity", "periodic2d") else 1)
+    d = ndim(p)
+    return int(p["nx"]) * (int(p["ny"]) if d >= 2 else 1) * (int(p.get("nz", 1)) if d == 3 else 1)
 
 
 def nvel(p: dict) -> int:
@@ -175,3 +183,7 @@ def nvel(p: dict) -> int:
 
 def is_2d(p: dict) -> bool:
     return p["kind"] in ("cavity", "periodic2d")
+
+
+def is_3d(p: dict) -> bool:
+    return p["kind"] in ("cavity3d", "periodic3d")

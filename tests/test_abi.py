@@ -120,3 +120,32 @@ def test_reduced_velocity_space_rules(B):
     mixed = (B.Problem * 2)(B.to_struct(cav), B.to_struct(dict(cav, reduced=False)))
     assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED
     assert not h.value
+
+
+def cube(**kw):
+    d = dict(kind="cavity3d", nx=4, ny=3, nz=4, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0,
+             nv=(8, 8, 8), vlo=(-4.0,) * 3, vhi=(4.0,) * 3, kn=0.3, omega=0.5, cfl=0.5, dt=0.0, mach=1.5,
+             lid_mach=0.2, t_wall=1.0, splitting="strang", limiter="minmod")
+    d.update(kw)
+    return d
+
+
+def test_three_dimensional_rules(B):
+    """3D kinds: nz >= 1 (2 for periodic boxes), a non-empty z box, the
+    Courant sum over three directions, v_z changing sign at an even plane,
+    full velocity space, no shift streaming, no mixing with 2D kinds."""
+    assert init_code(B, cube(nz=0))[0] == B.E_INVALID
+    assert init_code(B, cube(z1=0.0))[0] == B.E_INVALID
+    assert init_code(B, cube(kind="periodic3d", nz=1))[0] == B.E_INVALID
+    assert init_code(B, cube(t_wall=0.0))[0] == B.E_INVALID
+    # max |v| = 3.5 on cells of 1/4, 1/3, 1/4: at dt = 0.02 the x and y terms sum to
+    # 0.49, with the z term 0.77 > 2/3
+    assert init_code(B, cube(cfl=0.0, dt=0.02))[0] == B.E_CFL
+    rc, msg = init_code(B, cube(nv=(8, 8, 10)))  # five planes with v_z < 0
+    assert rc == B.E_UNSUPPORTED and "even plane" in msg
+    assert init_code(B, cube(nv=(8, 8, 2), reduced=True))[0] == B.E_UNSUPPORTED
+    assert init_code(B, cube(limiter="shift", splitting="lie"))[0] == B.E_UNSUPPORTED
+    h = ctypes.c_void_p()
+    mixed = (B.Problem * 2)(B.to_struct(cube()), B.to_struct(dict(cube(), kind="cavity")))
+    assert B.load().bgk_init(mixed, 2, 0, ctypes.byref(h)) == B.E_UNSUPPORTED
+    assert not h.value
