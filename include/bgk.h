@@ -134,8 +134,12 @@ typedef struct bgk_problem {
 typedef struct bgk_ctx bgk_ctx;
 
 /* Create a context for n_probs instances stepped together (one launch per
- * kernel for all of them).  All instances must share the velocity grid and
- * the dimension (1D, 2D or 3D kinds).  Validates every field, computes each
+ * kernel for all of them).  All instances must share the velocity grid;
+ * their dimensions may differ (a shock batched with cavities): the kernels
+ * run at the highest dimension of the batch, and an instance streams along
+ * its own directions only, with the same values as alone (contexts in the
+ * reduced velocity space, whose layout depends on the dimension, hold one
+ * dimension only; mixed contexts have no reverse sweep).  Validates every field, computes each
  * instance's dt, and allocates the context's small device data (per-cell
  * table entries and moment partial sums, no f-sized buffer) on the current
  * device.  precision: BGK_FP64 or BGK_FP32.

@@ -126,14 +126,16 @@ def to_struct(cfg: dict) -> Problem:
 
 
 def size_class(problems, precision: str) -> str:
-    """Key of the tuned-shape table: dimension, precision, velocity grid and
-    the power-of-two bucket of the total cell count."""
+    """Key of the tuned-shape table: dimension (the highest of a batch that
+    mixes them), precision, velocity grid and the power-of-two bucket of the
+    total cell count."""
     import math
     p0 = problems[0]
     cells = sum(inputs.ncells(p) for p in problems)
     bucket = 1 << max(0, math.ceil(math.log2(max(cells, 1))))
     nv = "x".join(str(int(v)) for v in p0["nv"])
-    return f"{inputs.ndim(p0)}d/{precision}/nv{nv}/cells<={bucket}"
+    dim = max(inputs.ndim(p) for p in problems)
+    return f"{dim}d/{precision}/nv{nv}/cells<={bucket}"
 
 
 def load_tuned() -> dict:

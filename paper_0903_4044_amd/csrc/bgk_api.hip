@@ -73,6 +73,7 @@ struct bgk_ctx {
     // reverse sweep (allocated at the first bgk_step_adjoint / bgk_lid_shear call)
     bool adj_ready = false;
     bool adjoint_fits = true;  // reverse-sweep tables fit the device's LDS
+    bool mixed = false;        // instances of different dimensions
     int lds_max = 65536;       // device LDS per workgroup (bytes)
     void *adj_h = nullptr, *adj_hb = nullptr;                     // during a reverse step: h = S(R_a f), abar
                                                                   // (the two halves of the caller's workspace)
@@ -376,8 +377,9 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
         if (rc) return rc;
         const bgk_problem &p = probs[i], &q = probs[0];
         const char *why = nullptr;
-        if (kind_dim(p.kind) != kind_dim(q.kind)) why = "all instances must have the same dimension";
-        else if (p.reduced != q.reduced) why = "all instances must share the velocity space (reduced or not)";
+        if (p.reduced != q.reduced) why = "all instances must share the velocity space (reduced or not)";
+        else if (p.reduced && kind_dim(p.kind) != kind_dim(q.kind))
+            why = "the reduced velocity space differs by dimension: no mixed-dimension batch";
         else if ((p.limiter == BGK_SHIFT) != (q.limiter == BGK_SHIFT))
             why = "shift streaming cannot share a context with other limiters";
         for (int a = 0; a < 3 && !why; ++a)
@@ -391,7 +393,12 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     c->precision = precision;
     c->esize = precision == BGK_FP64 ? 8 : 4;
     c->ninst = n_probs;
-    c->dim = kind_dim(probs[0].kind);
+    // a batch mixing dimensions runs the kernels of the highest one
+    c->dim = 1;
+    for (int i = 0; i < n_probs; ++i) {
+        c->dim = std::max(c->dim, kind_dim(probs[i].kind));
+        if (kind_dim(probs[i].kind) != kind_dim(probs[0].kind)) c->mixed = true;
+    }
     c->shift = probs[0].limiter == BGK_SHIFT;
     c->probs.assign(probs, probs + n_probs);
     (void)hipGetDevice(&c->device);
@@ -1068,6 +1075,7 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
         if (overlaps(ws, 2 * fb, q, fb))
             return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: the workspace must not overlap f_n, lam_next or lam_n");
     if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: one- and two-dimensional kinds only");
+    if (ctx->mixed) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: instances of one dimension only");
     if (!ctx->adjoint_fits)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");

@@ -57,6 +57,12 @@ struct Inst {
     double up[3], dn[3];  // shock far-field (n, V, T)
 };
 
+// Streaming directions of an instance.
+__device__ __forceinline__ int inst_dim(const Inst &I)
+{
+    return I.kind == KIND_CAV3 || I.kind == KIND_PER3 ? 3 : I.kind == KIND_CAVITY || I.kind == KIND_PER2 ? 2 : 1;
+}
+
 struct Geo {
     int nvx, nvy, nvz;
     int npl;                    // nvx * nvy
@@ -945,6 +951,9 @@ struct SlotInfo { int cell[MAXSLOT]; int par[MAXSLOT]; uint32_t off[MAXSLOT]; };
 __device__ __forceinline__ void resolve_slot(const Inst &I, int axis, int ix, int iy, int iz, int delta, int sgn,
                                              int own, int *cell, int *par)
 {
+    // An instance of lower dimension in a batch run at a higher one does not
+    // stream along this axis (its Courant number there is 0): its own cell.
+    if (axis >= inst_dim(I)) { *cell = own; *par = I.cell0 + own; return; }
     const int N = axis == 0 ? I.nx : axis == 1 ? I.ny : I.nz;
     const int pos = (axis == 0 ? ix : axis == 1 ? iy : iz) + delta;
     auto at = [&](int q) {
