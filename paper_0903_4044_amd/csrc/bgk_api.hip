@@ -45,6 +45,11 @@ struct bgk_ctx {
     int unroll = 1;            // streaming kernel: jz values whose loads are issued together
     int persist = 0;           // streaming kernel: 0 one workgroup per item, else resident workgroups per CU
     bool shift = false;        // every instance streams in the translation form (k_shift)
+    // translation form in row tiles (k_shift_rows, the shape's unroll = 2):
+    // cells per tile, log2 lanes per cell, window cells, tiles, LDS bytes
+    bool row_ok = false, row_pcache = false;
+    int row_tt = 0, row_lg = 0, row_wmax = 0, row_ntiles = 0;
+    size_t row_lds_bytes = 0;
     bool conservative = false; // some instance relaxes with the effective Maxwellian parameters
     // hipGraph replay of whole bgk_step calls (every launch after the one that
     // sets the rounding counter); key: (f_in, f_out, workspace, steps).
@@ -135,6 +140,7 @@ static Args make_args(const bgk_ctx *c)
     a.vsplit = c->vsplit;
     a.zr = c->zr;
     a.nparts = c->vsplit;
+    a.ntiles = c->row_ntiles;
     a.pass = c->pass;
     a.g = c->geo;
     return a;
@@ -335,6 +341,7 @@ static void set_shape(bgk_ctx *c, int vec, int unroll, int vsplit, int persist =
     c->unroll = unroll;
     c->persist = persist;
     c->vsplit = std::max(1, std::min(c->vsplit_max, vsplit));
+    if (c->shift && unroll == 2) c->vsplit = g.nvz;  // row tiles: one plane per work item
     task_shape(g, c->vec, g.nvz / c->vsplit, &c->zr, &c->sblock);
 }
 
@@ -343,17 +350,66 @@ static int vsplit_for(const bgk_ctx *c, int target_wg)
     return std::max(1, std::min(c->geo.nvz, (target_wg + c->ncells - 1) / c->ncells));
 }
 
+// Translation form in row tiles: lanes per cell G = 2^lg >= N_vx (at most
+// 64), 4 (cell, jx) pairs per lane of a 1024-lane workgroup, so TT = 4096 / G
+// cells per tile; per instance the first tile and the reach of its sources
+// below and above a tile (the largest shift m + 1 of each sign, plus one
+// cell of margin); the window (TT + both reaches) sets the LDS size, with
+// the v_x tables of the window cached when they fit too.
+static void plan_rows(bgk_ctx *c)
+{
+    const Geo &g = c->geo;
+    c->row_ok = false;
+    if (g.nvx > 64) return;
+    int lg = 0;
+    while ((1 << lg) < g.nvx) ++lg;
+    const int tt = 4096 >> lg;
+    int reach = 0, tiles = 0;
+    for (Inst &I : c->h_inst) {
+        int lo = 0, hi = 0;
+        for (int k = 0; k < g.nvx; ++k) {
+            const double vx = g.lo[0] + (k + 0.5) * g.dv[0];
+            const int m = (int)std::floor(std::fabs(vx) * I.cx);
+            if (vx > 0.0) lo = std::max(lo, m + 2);
+            else hi = std::max(hi, m + 2);
+        }
+        I.reach_lo = lo;
+        I.reach_hi = hi;
+        I.tile0 = tiles;
+        tiles += (I.nx + tt - 1) / tt;
+        reach = std::max(reach, lo + hi);
+    }
+    const int wmax = tt + reach;
+    size_t lds = c->esize == 4 ? row_lds<float>(g.nvx, tt, wmax, true).total : row_lds<double>(g.nvx, tt, wmax, true).total;
+    bool pc = true;
+    if (lds > (size_t)c->lds_max) {
+        pc = false;
+        lds = c->esize == 4 ? row_lds<float>(g.nvx, tt, wmax, false).total : row_lds<double>(g.nvx, tt, wmax, false).total;
+    }
+    if (lds > (size_t)c->lds_max) return;
+    c->row_ok = true;
+    c->row_pcache = pc;
+    c->row_tt = tt;
+    c->row_lg = lg;
+    c->row_wmax = wmax;
+    c->row_ntiles = tiles;
+    c->row_lds_bytes = lds;
+}
+
 // Default shape (measured on MI355X for the paper's grids; bgk_autotune refines it).
 static void choose_launch(bgk_ctx *c)
 {
     // up to 4 jz chunks per cell even on large grids: smaller work items keep
     // the y-neighbour rows of the cells in flight resident in each XCD's L2
     c->vsplit_max = std::max(vsplit_for(c, 8192), std::min(c->geo.nvz, 4));
+    if (c->row_ok) c->vsplit_max = std::max(c->vsplit_max, c->geo.nvz);
     int vec = 1;
     for (int v : {4, 2})
         if (vec_valid(c, v)) { vec = v; break; }
     if (c->dim >= 2) vec = 1;
-    const int unroll = (c->dim == 1 && c->precision == BGK_FP32 && !c->shift) ? 2 : 1;
+    int unroll = (c->dim == 1 && c->precision == BGK_FP32 && !c->shift) ? 2 : 1;
+    // translation form: row tiles when their plane-by-tile items fill the device
+    if (c->shift && c->row_ok && c->row_ntiles * c->geo.nvz >= c->ncu) unroll = 2;
     const int target = c->dim == 1 ? (c->precision == BGK_FP32 ? 1024 : 512) : 2048;
     set_shape(c, vec, unroll, vsplit_for(c, target));
     c->block = 256;
@@ -521,6 +577,7 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
     c->npseudo = c->h_pseudo_prefix.back();
     for (int i = 0; i < n_probs; ++i) c->h_inst[i].pseudo0 = c->ncells + c->h_pseudo_prefix[i];
     c->f_elems = (size_t)f_off;
+    if (c->shift) plan_rows(c);
 
     choose_launch(c);
     return BGK_OK;
@@ -771,7 +828,26 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         c->ev_used++;
         HIP_TRY(c, hipEventRecord(e0, s));
     }
-    if (c->shift) {
+    if (c->shift && c->unroll == 2) {
+        const real *p = (const real *)params_buf<real>(c, c->pass_parity);
+        const int items = c->row_ntiles * c->geo.nvz;
+        const int nbr = c->persist ? std::min(items, c->persist * c->ncu) : items;
+        const Args a = make_args(c);
+        const bool nt = stream_nt(c);
+        const size_t l = c->row_lds_bytes;
+        if (c->row_pcache && nt)
+            hipLaunchKernelGGL((k_shift_rows<real, 4, true, true>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
+                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
+        else if (c->row_pcache)
+            hipLaunchKernelGGL((k_shift_rows<real, 4, true, false>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
+                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
+        else if (nt)
+            hipLaunchKernelGGL((k_shift_rows<real, 4, false, true>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
+                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
+        else
+            hipLaunchKernelGGL((k_shift_rows<real, 4, false, false>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
+                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
+    } else if (c->shift) {
         const real *p = (const real *)params_buf<real>(c, c->pass_parity);
         // the v_z tables of a cell's 2 Nvx source entries, staged in LDS when they fit in 64 KB
         const size_t st = (size_t)4 * c->geo.nvx * c->geo.nvz * sizeof(real);
@@ -1260,7 +1336,7 @@ static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
             for (int vs : splits)
                 for (int ps : {0, 2, 4}) {
                     if (rc) break;
-                    if (c->shift && unroll != 1) continue;  // k_shift has one pipeline form
+                    if (c->shift && unroll > (c->row_ok ? 2 : 1)) continue;  // per-cell or row tiles
                     if (c->dim == 3 && unroll > 2) continue;  // 3D: modes 1 and 2 only
                     if (ps && c->ncells * vs <= ps * c->ncu) continue;  // grid already resident
                     Cand k{0.0, vec, unroll, vs, ps};
@@ -1319,7 +1395,7 @@ extern "C" int bgk_set_launch(bgk_ctx *ctx, int vec, int unroll, int vsplit, int
 {
     if (!ctx) return BGK_E_INVALID;
     if (!(vec == 1 || vec == 2 || vec == 4) || !vec_valid(ctx, vec) || unroll < 1 || unroll > 4 ||
-        (ctx->shift && unroll != 1) || (ctx->dim == 3 && unroll > 2) || vsplit < 1 || vsplit > ctx->vsplit_max ||
+        (ctx->shift && unroll > (ctx->row_ok ? 2 : 1)) || (ctx->dim == 3 && unroll > 2) || vsplit < 1 || vsplit > ctx->vsplit_max ||
         persist < 0 || persist > 64)
         return fail(ctx, BGK_E_INVALID, "bgk_set_launch: shape not valid for this context");
     set_shape(ctx, vec, unroll, vsplit, persist);

@@ -55,6 +55,9 @@ struct Inst {
     double tw, uw;  // wall temperature, lid speed
     double x0, dx;  // spatial origin and cell size along x
     double up[3], dn[3];  // shock far-field (n, V, T)
+    // translation-form streaming in row tiles: first tile of the instance,
+    // and the sources' reach below and above a tile (cells, with a margin)
+    int tile0, reach_lo, reach_hi;
 };
 
 // Streaming directions of an instance.
@@ -85,6 +88,7 @@ struct Args {
     int vsplit;                 // velocity chunks (along jz) per cell
     int zr;                     // jz residues per streaming workgroup (lane tasks)
     int nparts;                 // partial moment sums per cell that consumers add up
+    int ntiles;                 // row-tile translation streaming: tiles over all instances
     uint32_t *pass;             // rounding counter: advanced once per streaming pass
     Geo g;
 };
@@ -1654,6 +1658,257 @@ __global__ void __launch_bounds__(256)
         }
         block_sum_store<NQ>(acc, partial + (long long)L * NQ);
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- shift, row tiles
+// The translation form again, organised for coalesced access.  At a fixed
+// velocity the sources of consecutive cells are consecutive cells, but the
+// shift m depends on jx: the per-cell kernel above gathers, per lane, one
+// value from a different source cell, so every load touches its own cache
+// line, and the source rows that one cell's velocity grid reaches (2 m_max
+// cells of them) leave the L2 between their uses.  Here a work item is
+// (tile of TT consecutive cells of one instance, plane jz), and for each
+// velocity row jy of the plane the workgroup
+//   1. loads the row (N_vx contiguous values) of every source cell the tile
+//      reaches, relaxes it with that cell's table entry, and keeps per jx
+//      the TT + 1 consecutive sources of the tile in LDS ([jx][k]);
+//   2. lane (t, jx) blends its two sources from LDS and stores its value, the
+//      N_vx lanes of a cell storing one contiguous row.
+// Work items run plane-major, so the items in flight on one XCD are
+// consecutive tiles of one plane and share their source rows in its L2.
+// Moments: per (t, jx) a lane owns, the sums over the plane's rows of h,
+// v_y h, v_y^2 h and the v_y < 0 part of v_y h (v_x, v_z are fixed), folded
+// into the NQ sums of the cell at the end of the item and written to
+// partial[(cell * N_vz + jz) * NQ + q] (the launch runs with vsplit = N_vz).
+// Arithmetic: FP64 out = u_a - th (u_a - u_b) as in Eq. (upwind); FP32 keeps
+// h and the relaxation increment r = (c0 - 1) h + M of each source
+// (u = h + r), forms d = r_a - th (u_a - u_b) in float and rounds h_a + d
+// stochastically with the random bits of the element (as every streaming
+// kernel does).  Lane groups: G = 2^lg >= N_vx lanes per cell (N_vx <= 64),
+// PPL (t, jx) pairs per lane, TT = PPL * 1024 / G.
+
+struct RowJx { int wb, ka, kb, pad; double th; };  // window index of source k = 0; source offsets of a and b
+
+template <typename real>
+struct RowCell { int par, cell; real c0, cmh, cml, z1, z2, yz1, yz2; };
+
+// Byte offsets of the row kernel's dynamic LDS.
+struct RowLds { size_t stage, jx, cell, pc, total; };
+
+__host__ __device__ inline size_t row_align(size_t x) { return (x + 15) & ~(size_t)15; }
+
+template <typename real>
+__host__ __device__ inline RowLds row_lds(int nvx, int tt, int wmax, bool pcache)
+{
+    RowLds L;
+    L.stage = 0;
+    L.jx = row_align((size_t)nvx * (tt + 1) * 8);
+    L.cell = L.jx + row_align((size_t)nvx * sizeof(RowJx));
+    L.pc = L.cell + row_align((size_t)wmax * sizeof(RowCell<real>));
+    L.total = L.pc + (pcache ? row_align((size_t)wmax * nvx * 2 * sizeof(real)) : 0);
+    return L;
+}
+
+template <typename real, int PPL, bool PCACHE, bool NTSTORE>
+__global__ void __launch_bounds__(1024)
+    k_shift_rows(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
+                 double *__restrict__ partial, int tt, int wmax, int lg)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Geo &g = A.g;
+    const RowLds Lo = row_lds<real>(g.nvx, tt, wmax, PCACHE);
+    // stage[jx * (tt + 1) + k], 8 bytes: FP32 (h, r) of the source, FP64 u
+    using S2 = vec_t<real, sizeof(real) == 4 ? 2 : 1>;
+    using X2 = vec_t<real, 2>;
+    static_assert(sizeof(S2) == 8, "stage elements of 8 bytes");
+    S2 *stage = reinterpret_cast<S2 *>(smem + Lo.stage);
+    RowJx *JX = reinterpret_cast<RowJx *>(smem + Lo.jx);
+    RowCell<real> *CT = reinterpret_cast<RowCell<real> *>(smem + Lo.cell);
+    X2 *PC = reinterpret_cast<X2 *>(smem + Lo.pc);  // (TX1, TX2) of window cell w at jx: PC[w * nvx + jx]
+    const int G = 1 << lg, tid = threadIdx.x, nth = blockDim.x;
+    const int ntl = A.ntiles, nitems = ntl * g.nvz;
+    const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int Lq = xcd_remap(item, nitems);
+        const int jz = Lq / ntl, tile = Lq - jz * ntl;
+        int lo = 0, hi = A.ninst;  // inst[lo].tile0 <= tile < inst[hi].tile0
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (A.inst[mid].tile0 <= tile) lo = mid; else hi = mid;
+        }
+        const Inst &I = A.inst[lo];
+        const int i0 = (tile - I.tile0) * tt;
+        const int te = min(tt, I.nx - i0);
+        const int wlo = i0 - I.reach_lo;
+        const int W = min(te + I.reach_lo + I.reach_hi, wmax);
+        // per jx: shift, fraction and the window index of its first source
+        for (int jx = tid; jx < g.nvx; jx += nth) {
+            const double vx = vnode(g, 0, jx), ac = fabs(vx) * I.cx;
+            const int m = (int)floor(ac);
+            const bool pos = vx > 0.0;
+            RowJx r;
+            const int wb = (pos ? i0 - m - 1 : i0 + m) - wlo;
+            r.wb = max(0, min(wb, W - 1 - te));  // (inside the window by the host's reach margins)
+            r.ka = pos ? 1 : 0;
+            r.kb = pos ? 0 : 1;
+            r.pad = 0;
+            r.th = ac - (double)m;
+            JX[jx] = r;
+        }
+        // per window cell: its table entry and the plane's factors
+        for (int w = tid; w < W; w += nth) {
+            const int q = wlo + w;
+            RowCell<real> c;
+            if (q >= 0 && q < I.nx) { c.cell = q; c.par = I.cell0 + q; }
+            else if (I.kind == KIND_PER1) { c.cell = ((q % I.nx) + I.nx) % I.nx; c.par = I.cell0 + c.cell; }
+            else { c.cell = -1; c.par = I.pseudo0 + (q < 0 ? 0 : 1); }
+            const real *E = params + (long long)c.par * g.pe;
+            double c0;
+            if constexpr (sizeof(real) == 4) c0 = *reinterpret_cast<const double *>(E + 2);
+            else c0 = E[0];
+            c.c0 = (real)c0;
+            const double cm = c0 - 1.0;
+            c.cmh = (real)cm;
+            c.cml = (real)(cm - (double)c.cmh);
+            c.z1 = E[g.tz + 2 * jz];
+            c.z2 = E[g.tz + 2 * jz + 1];
+            c.yz1 = c.yz2 = 0;
+            CT[w] = c;
+        }
+        __syncthreads();
+        if constexpr (PCACHE) {
+            for (int s = tid; s < (W << lg); s += nth) {
+                const int w = s >> lg, jx = s & (G - 1);
+                if (jx < g.nvx) {
+                    const real *E = params + (long long)CT[w].par * g.pe;
+                    X2 v;
+                    v[0] = E[g.tx1 + jx];
+                    v[1] = E[g.tx2 + jx];
+                    PC[w * g.nvx + jx] = v;
+                }
+            }
+        }
+        // this lane's (t, jx) pairs
+        int ia[PPL], ib[PPL], tj[PPL];
+        real th[PPL];
+        uint32_t ooff[PPL];  // byte offset of the pair's value at jy = 0 in the instance
+        double S0[PPL], Sy[PPL], Syy[PPL], Syn[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int q = tid + p * nth, t = q >> lg, jx = q & (G - 1);
+            tj[p] = (jx < g.nvx && t < te) ? t : -1;
+            const int jj = jx < g.nvx ? jx : 0;
+            const RowJx r = JX[jj];
+            // stage index k = window index - wb: the sources of cell i0 + t sit at k = t + ka, t + kb
+            ia[p] = jj * (tt + 1) + t + r.ka;
+            ib[p] = jj * (tt + 1) + t + r.kb;
+            th[p] = (real)r.th;
+            ooff[p] = (uint32_t)(((long long)(i0 + t) * g.nv + (long long)jz * g.npl + jj) * sizeof(real));
+            S0[p] = Sy[p] = Syy[p] = Syn[p] = 0.0;
+        }
+        const real *base = src + I.f0;
+        real *outb = dst + I.f0;
+        const uint32_t zoff = (uint32_t)jz * (uint32_t)g.npl;
+        for (int jy = 0; jy < g.nvy; ++jy) {
+            // the row's factors TY(jy) TZ(jz) of every window cell
+            for (int w = tid; w < W; w += nth) {
+                const real *E = params + (long long)CT[w].par * g.pe;
+                CT[w].yz1 = E[g.ty1 + jy] * CT[w].z1;
+                CT[w].yz2 = E[g.ty2 + jy] * CT[w].z2;
+            }
+            __syncthreads();
+            // stage the relaxed sources
+            for (int s = tid; s < (W << lg); s += nth) {
+                const int w = s >> lg, jx = s & (G - 1);
+                if (jx >= g.nvx) continue;
+                const int k = w - JX[jx].wb;
+                if ((unsigned)k > (unsigned)te) continue;
+                const RowCell<real> c = CT[w];
+                const real h = c.cell >= 0 ? base[(long long)c.cell * g.nv + zoff + jy * g.nvx + jx] : (real)0;
+                real x1, x2;
+                if constexpr (PCACHE) {
+                    const X2 v = PC[w * g.nvx + jx];
+                    x1 = v[0];
+                    x2 = v[1];
+                } else {
+                    const real *E = params + (long long)c.par * g.pe;
+                    x1 = E[g.tx1 + jx];
+                    x2 = E[g.tx2 + jx];
+                }
+                const real M = x1 * c.yz1 + x2 * c.yz2;
+                S2 v;
+                if constexpr (sizeof(real) == 4) {
+                    v[0] = h;
+                    v[1] = __builtin_fmaf(c.cmh, h, __builtin_fmaf(c.cml, h, M));
+                } else {
+                    v[0] = c.c0 * h + M;
+                }
+                stage[jx * (tt + 1) + k] = v;
+            }
+            __syncthreads();
+            // blend, store, accumulate
+            const double vy = vnode(g, 1, jy);
+            const uint32_t yoff = (uint32_t)(jy * g.nvx) * (uint32_t)sizeof(real);
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                if (tj[p] < 0) continue;
+                const S2 a = stage[ia[p]], b = stage[ib[p]];
+                real r;
+                if constexpr (sizeof(real) == 4) {
+                    const real ua = a[0] + a[1], ub = b[0] + b[1];
+                    const real d = a[1] - th[p] * (ua - ub);
+                    const uint32_t e = ooff[p] / (uint32_t)sizeof(real) + (uint32_t)(jy * g.nvx);  // element index
+                    const bool odd = (jz & 1) != 0;
+                    const uint32_t hb = hash32((e - (odd ? (uint32_t)g.npl : 0u)) ^ key);
+                    r = round_stochastic16((double)a[0] + (double)d, __builtin_amdgcn_ubfe(hb, odd ? 16u : 0u, 16u));
+                } else {
+                    r = a[0] - th[p] * (a[0] - b[0]);
+                }
+                real *op = reinterpret_cast<real *>(reinterpret_cast<char *>(outb) + ooff[p] + yoff);
+                if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
+                else *op = r;
+                const double rd = (double)r;
+                S0[p] += rd;
+                Sy[p] = __builtin_fma(vy, rd, Sy[p]);
+                Syy[p] = __builtin_fma(vy * vy, rd, Syy[p]);
+                if (vy < 0.0) Syn[p] = __builtin_fma(-vy, rd, Syn[p]);
+            }
+        }
+        // fold into the NQ sums of each cell: a cell's G lanes are consecutive
+        // lanes of one wave (G <= 64)
+        const ZW zw = zweights(g, jz);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int q = tid + p * nth, t = q >> lg, jx = q & (G - 1);
+            double v[9];
+            if (tj[p] >= 0) {
+                const double vx = vnode(g, 0, jx), ms = zw.m * S0[p];
+                v[0] = ms;
+                v[1] = vx * ms;
+                v[2] = zw.m * Sy[p];
+                v[3] = zw.z * S0[p];
+                v[4] = (vx * vx * ms + zw.m * Syy[p]) + zw.zz * S0[p];
+                v[5] = vx < 0.0 ? -vx * ms : 0.0;
+                v[6] = vx > 0.0 ? vx * ms : 0.0;
+                v[7] = zw.m * Syn[p];
+                v[8] = zw.m * (Sy[p] + Syn[p]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) v[k] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                for (int off = G >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+            if (jx == 0 && t < te) {
+                double *out = partial + ((long long)(I.cell0 + i0 + t) * A.vsplit + jz) * NQ;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) out[k] = v[k];
+                out[9] = 0.0;
+                out[10] = 0.0;
+            }
+        }
+        __syncthreads();  // LDS tables are rebuilt by the next item
     }
 }
 

@@ -32,10 +32,14 @@ def workloads():
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=binding.TUNED_PATH, help="where to write the table")
+    ap.add_argument("--only", default="", help="comma-separated workload names (default: all)")
     args = ap.parse_args()
+    only = {w for w in args.only.split(",") if w}
     torch.cuda.set_device(0)
     table = binding.load_tuned()
     for name, probs, prec in workloads():
+        if only and name not in only:
+            continue
         ctx = binding.Context(probs, prec, tune="off")
         f = ctx.initial_state()
         torch.cuda.synchronize()

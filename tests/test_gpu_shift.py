@@ -133,3 +133,97 @@ def test_staged_and_global_table_reads_agree_with_oracle(B, oracle_mod):
         y32 = C32.step(dev(f0, torch.float32), n=4)
         en, eV, eT = moment_rel(C32.moments(y32).cpu().numpy(), O.moments(ref))
         assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+# ------------------------------------------------------ row-tile kernel
+# The translation form in row tiles (launch shape unroll = 2): one plane of a
+# tile of consecutive cells per workgroup, coalesced row loads staged in LDS.
+
+@pytest.mark.parametrize("kind", ["shock", "periodic1d"])
+@pytest.mark.parametrize("cfl", [0.7, 3.6, 9.3])
+def test_row_tiles_match_oracle_fp64(B, oracle_mod, kind, cfl):
+    cfg = small(kind, cfl=cfl)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 91)
+    ref = O.step(f0, 5)
+    C = B.Context(cfg, "fp64", tune="off")
+    for persist in (0, 1):
+        C.set_launch(1, 2, 1, persist)
+        assert C.launch()["unroll"] == 2
+        y = C.step(dev(f0, torch.float64), n=5).cpu().numpy().reshape(O.shape)
+        np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind", ["shock", "periodic1d"])
+def test_row_tiles_match_oracle_fp32(B, oracle_mod, kind):
+    cfg = small(kind, cfl=3.6)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 92)
+    ref = O.step(f0, 20)
+    C = B.Context(cfg, "fp32", tune="off")
+    C.set_launch(1, 2, 1, 0)
+    y = C.step(dev(f0, torch.float32), n=20)
+    en, eV, eT = moment_rel(C.moments(y).cpu().numpy(), O.moments(ref))
+    assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+@pytest.mark.parametrize("nv", [(30, 6, 4), (16, 4, 6), (64, 2, 2), (5, 3, 2)])
+def test_row_tiles_several_tiles(B, oracle_mod, nv):
+    """Several tiles per instance (1024, 256 or 64 cells per tile with 4 pairs
+    per lane) and a ragged last tile, at Courant numbers up to ~12."""
+    lo, hi = (-10.0, -3.0, -3.0), (12.0, 3.0, 3.0)
+    cfg = small("shock", nx={30: 300, 16: 600, 64: 150, 5: 1100}[nv[0]], nv=nv, vlo=lo, vhi=hi, cfl=12.3,
+                x0=-20.0, x1=20.0)
+    O = oracle_mod.Oracle(cfg)
+    f0 = perturbed(O, 93)
+    ref = O.step(f0, 3)
+    C = B.Context(cfg, "fp64", tune="off")
+    C.set_launch(1, 2, 1, 0)
+    y = C.step(dev(f0, torch.float64), n=3).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    C32 = B.Context(cfg, "fp32", tune="off")
+    C32.set_launch(1, 2, 1, 2)
+    y32 = C32.step(dev(f0, torch.float32), n=3)
+    en, eV, eT = moment_rel(C32.moments(y32).cpu().numpy(), O.moments(ref))
+    assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+def test_row_tiles_batch_of_shocks(B, oracle_mod):
+    """Instances of different lengths and Courant numbers share the tile
+    sequence (each instance starts a tile)."""
+    probs = [small("shock", nx=300, nv=(30, 4, 4), vlo=(-10.0, -3.0, -3.0), vhi=(12.0, 3.0, 3.0), cfl=c,
+                   x0=-20.0, x1=20.0) for c in (2.2, 9.7)]
+    probs.append(small("periodic1d", nx=37, nv=(30, 4, 4), vlo=(-10.0, -3.0, -3.0), vhi=(12.0, 3.0, 3.0), cfl=5.1))
+    Os = [oracle_mod.Oracle(p) for p in probs]
+    f0s = [perturbed(O, 94 + i) for i, O in enumerate(Os)]
+    refs = [O.step(f, 4) for O, f in zip(Os, f0s)]
+    C = B.Context(probs, "fp64", tune="off")
+    C.set_launch(1, 2, 1, 0)
+    x = torch.tensor(np.concatenate([f.reshape(-1) for f in f0s]), dtype=torch.float64, device="cuda")
+    y = C.step(x, n=4)
+    for i, (O, ref) in enumerate(zip(Os, refs)):
+        got = C.instance_view(y, i).cpu().numpy().reshape(O.shape)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_row_tiles_paper_box(B, oracle_mod):
+    """The paper's Mach-3 box on 512 cells with row tiles: FP64 to 1e-12,
+    FP32 moments to 1e-5 after 10 steps."""
+    cfg = inputs.config("shock_m3_paper", nx=512)
+    O = oracle_mod.Oracle(cfg)
+    f0 = O.initial_state()
+    ref = O.step(f0, 10)
+    C = B.Context(cfg, "fp64", tune="off")
+    C.set_launch(1, 2, 1, 0)
+    y = C.step(dev(f0, torch.float64), n=10).cpu().numpy().reshape(O.shape)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    C32 = B.Context(cfg, "fp32", tune="off")
+    C32.set_launch(1, 2, 1, 0)
+    y32 = C32.step(dev(f0, torch.float32), n=10)
+    en, eV, eT = moment_rel(C32.moments(y32).cpu().numpy(), O.moments(ref))
+    assert max(en, eV, eT) <= 1e-5, (en, eV, eT)
+
+
+def test_paper_box_default_is_row_tiles(B):
+    C = B.Context(inputs.config("shock_m3_paper"), "fp32", tune="off")
+    assert C.launch()["unroll"] == 2
