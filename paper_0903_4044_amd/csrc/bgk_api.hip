@@ -47,7 +47,7 @@ struct bgk_ctx {
     bool shift = false;        // every instance streams in the translation form (k_shift)
     // translation form in row tiles (k_shift_rows, the shape's unroll = 2):
     // cells per tile, log2 lanes per cell, window cells, tiles, LDS bytes
-    bool row_ok = false, row_pcache = false;
+    bool row_ok = false, row_pcache = false;  // row_pcache: v_x table values in the source list
     int row_tt = 0, row_lg = 0, row_wmax = 0, row_ntiles = 0;
     size_t row_lds_bytes = 0;
     bool conservative = false; // some instance relaxes with the effective Maxwellian parameters
@@ -351,11 +351,12 @@ static int vsplit_for(const bgk_ctx *c, int target_wg)
 }
 
 // Translation form in row tiles: lanes per cell G = 2^lg >= N_vx (at most
-// 64), 4 (cell, jx) pairs per lane of a 1024-lane workgroup, so TT = 4096 / G
+// 64), 4 (cell, jx) pairs per lane of a ROW_THREADS-lane workgroup, TT = 4 ROW_THREADS / G - 1
 // cells per tile; per instance the first tile and the reach of its sources
 // below and above a tile (the largest shift m + 1 of each sign, plus one
-// cell of margin); the window (TT + both reaches) sets the LDS size, with
-// the v_x tables of the window cached when they fit too.
+// cell of margin); the window (TT + both reaches, at most ROW_THREADS
+// cells) and the list of its needed sources set the LDS size, the list
+// holding the sources' v_x table values too when they fit.
 static void plan_rows(bgk_ctx *c)
 {
     const Geo &g = c->geo;
@@ -363,7 +364,7 @@ static void plan_rows(bgk_ctx *c)
     if (g.nvx > 64) return;
     int lg = 0;
     while ((1 << lg) < g.nvx) ++lg;
-    const int tt = 4096 >> lg;
+    const int tt = ((4 * ROW_THREADS) >> lg) - 1;  // (tt + 1) N_vx sources fill ROW_EPL = 4 per lane
     int reach = 0, tiles = 0;
     for (Inst &I : c->h_inst) {
         int lo = 0, hi = 0;
@@ -380,11 +381,13 @@ static void plan_rows(bgk_ctx *c)
         reach = std::max(reach, lo + hi);
     }
     const int wmax = tt + reach;
-    size_t lds = c->esize == 4 ? row_lds<float>(g.nvx, tt, wmax, true).total : row_lds<double>(g.nvx, tt, wmax, true).total;
+    if (wmax > ROW_THREADS) return;  // one window cell per lane
+    // the v_x table values kept in the source list when they fit
+    size_t lds = c->esize == 4 ? row_lds<float, true>(g.nvx, tt, wmax).total : row_lds<double, true>(g.nvx, tt, wmax).total;
     bool pc = true;
     if (lds > (size_t)c->lds_max) {
         pc = false;
-        lds = c->esize == 4 ? row_lds<float>(g.nvx, tt, wmax, false).total : row_lds<double>(g.nvx, tt, wmax, false).total;
+        lds = c->esize == 4 ? row_lds<float, false>(g.nvx, tt, wmax).total : row_lds<double, false>(g.nvx, tt, wmax).total;
     }
     if (lds > (size_t)c->lds_max) return;
     c->row_ok = true;
@@ -833,20 +836,18 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         const int items = c->row_ntiles * c->geo.nvz;
         const int nbr = c->persist ? std::min(items, c->persist * c->ncu) : items;
         const Args a = make_args(c);
-        const bool nt = stream_nt(c);
         const size_t l = c->row_lds_bytes;
-        if (c->row_pcache && nt)
-            hipLaunchKernelGGL((k_shift_rows<real, 4, true, true>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
-                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
-        else if (c->row_pcache)
-            hipLaunchKernelGGL((k_shift_rows<real, 4, true, false>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
-                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
-        else if (nt)
-            hipLaunchKernelGGL((k_shift_rows<real, 4, false, true>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
-                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
-        else
-            hipLaunchKernelGGL((k_shift_rows<real, 4, false, false>), dim3(nbr), dim3(1024), l, s, a, (const real *)src,
-                               (real *)dst, p, c->partial, c->row_tt, c->row_wmax, c->row_lg);
+        const int sel = (c->row_pcache ? 2 : 0) + (stream_nt(c) ? 1 : 0);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nbr), dim3(ROW_THREADS), l, s, a, (const real *)src, (real *)dst, p, c->partial,
+                               c->row_tt, c->row_wmax, c->row_lg);
+        };
+        switch (sel) {
+        case 3: go(k_shift_rows<real, 4, true, true>); break;
+        case 2: go(k_shift_rows<real, 4, true, false>); break;
+        case 1: go(k_shift_rows<real, 4, false, true>); break;
+        default: go(k_shift_rows<real, 4, false, false>); break;
+        }
     } else if (c->shift) {
         const real *p = (const real *)params_buf<real>(c, c->pass_parity);
         // the v_z tables of a cell's 2 Nvx source entries, staged in LDS when they fit in 64 KB

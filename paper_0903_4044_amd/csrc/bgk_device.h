@@ -1686,46 +1686,75 @@ __global__ void __launch_bounds__(256)
 // (u = h + r), forms d = r_a - th (u_a - u_b) in float and rounds h_a + d
 // stochastically with the random bits of the element (as every streaming
 // kernel does).  Lane groups: G = 2^lg >= N_vx lanes per cell (N_vx <= 64),
-// PPL (t, jx) pairs per lane, TT = PPL * 1024 / G.
+// PPL (t, jx) pairs per lane, TT = PPL * ROW_THREADS / G - 1.
 
 struct RowJx { int wb, ka, kb, pad; double th; };  // window index of source k = 0; source offsets of a and b
 
 template <typename real>
-struct RowCell { int par, cell; real c0, cmh, cml, z1, z2, yz1, yz2; };
+struct RowCell { int par, cell; real c0, cmh, cml, z1, z2; real yz[4]; };  // yz: (TY1 TZ1, TY2 TZ2) of two rows
 
 // Byte offsets of the row kernel's dynamic LDS.
-struct RowLds { size_t stage, jx, cell, pc, total; };
+struct RowLds { size_t stage, jx, cell, ent, scan, total; };
 
 __host__ __device__ inline size_t row_align(size_t x) { return (x + 15) & ~(size_t)15; }
 
-template <typename real>
-__host__ __device__ inline RowLds row_lds(int nvx, int tt, int wmax, bool pcache)
+// Workgroups of ROW_THREADS lanes, two per CU (their barriers interleave);
+// the window holds at most ROW_THREADS cells (one per lane in the per-cell
+// passes).  ROW_EPL: staged sources per lane and row, (TT + 1) N_vx <=
+// 4 ROW_THREADS of them (TT = 4 ROW_THREADS / G - 1).
+constexpr int ROW_THREADS = 512;
+constexpr int ROW_EPL = 4;
+
+// Source list entry: element offset of the source at jy = 0 (-1: far field)
+// and (stage index | w << 13 | jx << 23); with XIN also its v_x table values.
+template <typename real, bool XIN>
+struct RowEnt { int off; uint32_t packed; real x[XIN ? 2 : 1]; };
+
+// Stage row stride (8-byte elements) of one jx: odd, so the 32 jx of a wave
+// at one cell fall on distinct LDS banks.
+__host__ __device__ inline int row_stride(int tt) { return (tt + 1) | 1; }
+
+template <typename real, bool XIN>
+__host__ __device__ inline RowLds row_lds(int nvx, int tt, int wmax)
 {
     RowLds L;
-    L.stage = 0;
-    L.jx = row_align((size_t)nvx * (tt + 1) * 8);
+    L.stage = 0;  // nvx rows of stride S holding tt + 1 sources, and one slot written by padding entries
+    L.jx = row_align(((size_t)nvx * row_stride(tt) + 1) * 8);
     L.cell = L.jx + row_align((size_t)nvx * sizeof(RowJx));
-    L.pc = L.cell + row_align((size_t)wmax * sizeof(RowCell<real>));
-    L.total = L.pc + (pcache ? row_align((size_t)wmax * nvx * 2 * sizeof(real)) : 0);
+    L.ent = L.cell + row_align((size_t)wmax * sizeof(RowCell<real>));
+    L.scan = L.ent + row_align((size_t)ROW_EPL * ROW_THREADS * sizeof(RowEnt<real, XIN>));
+    L.total = L.scan + row_align(32 * sizeof(int));
     return L;
 }
 
-template <typename real, int PPL, bool PCACHE, bool NTSTORE>
-__global__ void __launch_bounds__(1024)
+// Per work item the window's needed (cell, jx) sources, TT + 1 per jx, are
+// listed once in LDS (cell-major, so consecutive entries are consecutive jx
+// of one cell row and their loads coalesce; the list is padded to ROW_EPL
+// entries per lane with entries that load nothing useful and stage into a
+// spare slot); each row then loads and relaxes just those, the loads of row
+// jy + 1 (and the y-table values of row jy + 2) being issued before row jy
+// is blended, so they are in flight during the blend.  Every global load
+// and store is issued unconditionally (padding lanes repeat a valid lane's
+// address and value), so the waits on them are static counts and a row's
+// staging waits for its own loads only, not for the stores issued after.
+template <typename real, int PPL, bool XIN, bool NTSTORE>
+__global__ void __launch_bounds__(ROW_THREADS, 4)
     k_shift_rows(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
                  double *__restrict__ partial, int tt, int wmax, int lg)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Geo &g = A.g;
-    const RowLds Lo = row_lds<real>(g.nvx, tt, wmax, PCACHE);
-    // stage[jx * (tt + 1) + k], 8 bytes: FP32 (h, r) of the source, FP64 u
+    const RowLds Lo = row_lds<real, XIN>(g.nvx, tt, wmax);
+    // stage[jx * S + k], 8 bytes: FP32 (h, r) of the source, FP64 u
     using S2 = vec_t<real, sizeof(real) == 4 ? 2 : 1>;
-    using X2 = vec_t<real, 2>;
     static_assert(sizeof(S2) == 8, "stage elements of 8 bytes");
+    using Ent = RowEnt<real, XIN>;
+    const int S = row_stride(tt);
     S2 *stage = reinterpret_cast<S2 *>(smem + Lo.stage);
     RowJx *JX = reinterpret_cast<RowJx *>(smem + Lo.jx);
     RowCell<real> *CT = reinterpret_cast<RowCell<real> *>(smem + Lo.cell);
-    X2 *PC = reinterpret_cast<X2 *>(smem + Lo.pc);  // (TX1, TX2) of window cell w at jx: PC[w * nvx + jx]
+    Ent *EN = reinterpret_cast<Ent *>(smem + Lo.ent);
+    int *SC = reinterpret_cast<int *>(smem + Lo.scan);
     const int G = 1 << lg, tid = threadIdx.x, nth = blockDim.x;
     const int ntl = A.ntiles, nitems = ntl * g.nvz;
     const uint32_t key = sizeof(real) == 4 ? pass_key(A.pass, 0) : 0u;
@@ -1742,6 +1771,7 @@ __global__ void __launch_bounds__(1024)
         const int te = min(tt, I.nx - i0);
         const int wlo = i0 - I.reach_lo;
         const int W = min(te + I.reach_lo + I.reach_hi, wmax);
+        const uint32_t zoff = (uint32_t)jz * (uint32_t)g.npl;
         // per jx: shift, fraction and the window index of its first source
         for (int jx = tid; jx < g.nvx; jx += nth) {
             const double vx = vnode(g, 0, jx), ac = fabs(vx) * I.cx;
@@ -1756,13 +1786,16 @@ __global__ void __launch_bounds__(1024)
             r.th = ac - (double)m;
             JX[jx] = r;
         }
-        // per window cell: its table entry and the plane's factors
-        for (int w = tid; w < W; w += nth) {
+        // per window cell (one per lane): its table entry and the plane's factors
+        const int w = tid;
+        int cell = -1;
+        if (w < W) {
             const int q = wlo + w;
             RowCell<real> c;
             if (q >= 0 && q < I.nx) { c.cell = q; c.par = I.cell0 + q; }
             else if (I.kind == KIND_PER1) { c.cell = ((q % I.nx) + I.nx) % I.nx; c.par = I.cell0 + c.cell; }
             else { c.cell = -1; c.par = I.pseudo0 + (q < 0 ? 0 : 1); }
+            cell = c.cell;
             const real *E = params + (long long)c.par * g.pe;
             double c0;
             if constexpr (sizeof(real) == 4) c0 = *reinterpret_cast<const double *>(E + 2);
@@ -1773,116 +1806,213 @@ __global__ void __launch_bounds__(1024)
             c.cml = (real)(cm - (double)c.cmh);
             c.z1 = E[g.tz + 2 * jz];
             c.z2 = E[g.tz + 2 * jz + 1];
-            c.yz1 = c.yz2 = 0;
+            c.yz[0] = c.yz[1] = c.yz[2] = c.yz[3] = 0;
             CT[w] = c;
         }
         __syncthreads();
-        if constexpr (PCACHE) {
-            for (int s = tid; s < (W << lg); s += nth) {
-                const int w = s >> lg, jx = s & (G - 1);
-                if (jx < g.nvx) {
-                    const real *E = params + (long long)CT[w].par * g.pe;
-                    X2 v;
-                    v[0] = E[g.tx1 + jx];
-                    v[1] = E[g.tx2 + jx];
-                    PC[w * g.nvx + jx] = v;
-                }
+        // list the needed sources: count per cell, block-wide exclusive scan, fill
+        int cnt = 0;
+        if (w < W)
+            for (int jx = 0; jx < g.nvx; ++jx) cnt += (unsigned)(w - JX[jx].wb) <= (unsigned)te ? 1 : 0;
+        int inc = cnt;
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) SC[wave] = inc;
+        __syncthreads();
+        int pre = 0, nent = 0;
+        for (int k = 0; k < (nth >> 6); ++k) {
+            const int v = SC[k];
+            pre += k < wave ? v : 0;
+            nent += v;
+        }
+        if (w < W) {
+            int e = pre + inc - cnt;
+            for (int jx = 0; jx < g.nvx; ++jx) {
+                const int k = w - JX[jx].wb;
+                if ((unsigned)k > (unsigned)te) continue;
+                Ent en;
+                en.off = cell >= 0 ? (int)((uint32_t)cell * (uint32_t)g.nv + zoff + (uint32_t)jx) : -1;
+                en.packed = (uint32_t)(jx * S + k) | ((uint32_t)w << 13) | ((uint32_t)jx << 23);
+                EN[e++] = en;
             }
         }
-        // this lane's (t, jx) pairs
-        int ia[PPL], ib[PPL], tj[PPL];
+        // padding entries up to ROW_EPL per lane: no source, the spare stage slot
+        for (int e = nent + tid; e < ROW_EPL * nth; e += nth) {
+            Ent en;
+            en.off = -1;
+            en.packed = (uint32_t)(g.nvx * S);
+            EN[e] = en;
+        }
+        __syncthreads();
+        if constexpr (XIN) {
+            for (int e = tid; e < ROW_EPL * nth; e += nth) {
+                const uint32_t pk = EN[e].packed;
+                const int ww = (pk >> 13) & 1023, jx = pk >> 23;
+                const real *E = params + (long long)CT[ww].par * g.pe;
+                EN[e].x[0] = E[g.tx1 + jx];
+                EN[e].x[1] = E[g.tx2 + jx];
+            }
+        }
+        // this lane's (t, jx) pairs: stage index of the lower source, which
+        // of the two is a, fraction, output offset.  A padding lane (jx or t
+        // beyond the grid or the tile) takes the last valid jx and t, so it
+        // computes and stores that pair's value again; it adds no moments.
+        int i0s[PPL];
+        bool valid[PPL], apos[PPL];
         real th[PPL];
         uint32_t ooff[PPL];  // byte offset of the pair's value at jy = 0 in the instance
-        double S0[PPL], Sy[PPL], Syy[PPL], Syn[PPL];
+        double S0[PPL], Sy[PPL], Syy[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            const int q = tid + p * nth, t = q >> lg, jx = q & (G - 1);
-            tj[p] = (jx < g.nvx && t < te) ? t : -1;
-            const int jj = jx < g.nvx ? jx : 0;
+            const int q = tid + p * nth, tq = q >> lg, jq = q & (G - 1);
+            valid[p] = jq < g.nvx && tq < te;
+            const int t = min(tq, te - 1), jj = min(jq, g.nvx - 1);
             const RowJx r = JX[jj];
-            // stage index k = window index - wb: the sources of cell i0 + t sit at k = t + ka, t + kb
-            ia[p] = jj * (tt + 1) + t + r.ka;
-            ib[p] = jj * (tt + 1) + t + r.kb;
+            // stage index k = window index - wb: the sources of cell i0 + t sit at
+            // k = t, t + 1 (a the upper one for v_x > 0)
+            i0s[p] = jj * S + t;
+            apos[p] = r.ka != 0;
             th[p] = (real)r.th;
             ooff[p] = (uint32_t)(((long long)(i0 + t) * g.nv + (long long)jz * g.npl + jj) * sizeof(real));
-            S0[p] = Sy[p] = Syy[p] = Syn[p] = 0.0;
+            S0[p] = Sy[p] = Syy[p] = 0.0;
         }
         const real *base = src + I.f0;
         real *outb = dst + I.f0;
-        const uint32_t zoff = (uint32_t)jz * (uint32_t)g.npl;
-        for (int jy = 0; jy < g.nvy; ++jy) {
-            // the row's factors TY(jy) TZ(jz) of every window cell
-            for (int w = tid; w < W; w += nth) {
-                const real *E = params + (long long)CT[w].par * g.pe;
-                CT[w].yz1 = E[g.ty1 + jy] * CT[w].z1;
-                CT[w].yz2 = E[g.ty2 + jy] * CT[w].z2;
+        // this lane's list entries tid + u nth: h of the row being fetched (a
+        // far field or padding entry loads the instance's first row and keeps 0)
+        // (the loaded values are used raw; the staging zeroes those of far
+        // fields and padding, so no instruction consumes a load before its row)
+        auto fetch = [&](int jy, real (&hreg)[ROW_EPL]) {
+            int off[ROW_EPL];
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) off[u] = EN[tid + u * nth].off;
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) hreg[u] = base[(uint32_t)max(off[u], 0) + (uint32_t)(jy * g.nvx)];
+        };
+        real ty1 = 0, ty2 = 0;  // window cell tid (lanes past the window read the last one)
+        const int wq = min(w, W - 1);
+        auto fetch_ty = [&](int jy) {
+            const real *E = params + (long long)CT[wq].par * g.pe;
+            ty1 = E[g.ty1 + jy];
+            ty2 = E[g.ty2 + jy];
+        };
+        auto put_yz = [&](int b) {
+            if (w < W) {
+                CT[w].yz[2 * b] = ty1 * CT[w].z1;
+                CT[w].yz[2 * b + 1] = ty2 * CT[w].z2;
             }
-            __syncthreads();
-            // stage the relaxed sources
-            for (int s = tid; s < (W << lg); s += nth) {
-                const int w = s >> lg, jx = s & (G - 1);
-                if (jx >= g.nvx) continue;
-                const int k = w - JX[jx].wb;
-                if ((unsigned)k > (unsigned)te) continue;
-                const RowCell<real> c = CT[w];
-                const real h = c.cell >= 0 ? base[(long long)c.cell * g.nv + zoff + jy * g.nvx + jx] : (real)0;
-                real x1, x2;
-                if constexpr (PCACHE) {
-                    const X2 v = PC[w * g.nvx + jx];
-                    x1 = v[0];
-                    x2 = v[1];
+        };
+        // One row: stage from the loads in hreg, then reuse hreg for the loads
+        // of row jy + 2 (two rows of latency cover), blend.  Rows come in
+        // pairs with alternating buffers; with an odd row count the last pair
+        // repeats row N_vy - 1 (same values stored again, no moments added).
+        auto row = [&](int jyr, real (&hreg)[ROW_EPL]) {
+            const bool live = jyr < g.nvy;
+            const int jy = min(jyr, g.nvy - 1), b = jyr & 1;
+            // stage the relaxed sources of row jy: all LDS reads first, then
+            // the arithmetic, then the stage writes
+            Ent en[ROW_EPL];
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) en[u] = EN[tid + u * nth];
+            real y1[ROW_EPL], y2[ROW_EPL], ch[ROW_EPL], cl[ROW_EPL], x1[ROW_EPL], x2[ROW_EPL];
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) {
+                const int ww = (en[u].packed >> 13) & 1023, jx = en[u].packed >> 23;
+                const RowCell<real> &c = CT[ww];
+                y1[u] = c.yz[2 * b];
+                y2[u] = c.yz[2 * b + 1];
+                if constexpr (sizeof(real) == 4) {
+                    ch[u] = c.cmh;
+                    cl[u] = c.cml;
+                } else {
+                    ch[u] = c.c0;
+                    cl[u] = 0;
+                }
+                if constexpr (XIN) {
+                    x1[u] = en[u].x[0];
+                    x2[u] = en[u].x[1];
                 } else {
                     const real *E = params + (long long)c.par * g.pe;
-                    x1 = E[g.tx1 + jx];
-                    x2 = E[g.tx2 + jx];
+                    x1[u] = E[g.tx1 + jx];
+                    x2[u] = E[g.tx2 + jx];
                 }
-                const real M = x1 * c.yz1 + x2 * c.yz2;
-                S2 v;
-                if constexpr (sizeof(real) == 4) {
-                    v[0] = h;
-                    v[1] = __builtin_fmaf(c.cmh, h, __builtin_fmaf(c.cml, h, M));
-                } else {
-                    v[0] = c.c0 * h + M;
-                }
-                stage[jx * (tt + 1) + k] = v;
             }
+            S2 sv[ROW_EPL];
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) {
+                const real h = en[u].off >= 0 ? hreg[u] : (real)0;
+                const real M = x1[u] * y1[u] + x2[u] * y2[u];
+                if constexpr (sizeof(real) == 4) {
+                    sv[u][0] = h;
+                    sv[u][1] = __builtin_fmaf(ch[u], h, __builtin_fmaf(cl[u], h, M));
+                } else {
+                    sv[u][0] = ch[u] * h + M;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < ROW_EPL; ++u) stage[en[u].packed & 8191] = sv[u];
+            put_yz(b ^ 1);  // (the last row's write is never read)
             __syncthreads();
+            // loads of row jy + 2 in flight during this row's and the next row's
+            // blend (the last rows load row N_vy - 1 again)
+            fetch(min(jyr + 2, g.nvy - 1), hreg);
+            fetch_ty(min(jyr + 2, g.nvy - 1));
             // blend, store, accumulate
             const double vy = vnode(g, 1, jy);
             const uint32_t yoff = (uint32_t)(jy * g.nvx) * (uint32_t)sizeof(real);
+            S2 slo[PPL], shi[PPL];
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                if (tj[p] < 0) continue;
-                const S2 a = stage[ia[p]], b = stage[ib[p]];
+                slo[p] = stage[i0s[p]];
+                shi[p] = stage[i0s[p] + 1];
+            }
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                const S2 a = apos[p] ? shi[p] : slo[p], bb = apos[p] ? slo[p] : shi[p];
                 real r;
                 if constexpr (sizeof(real) == 4) {
-                    const real ua = a[0] + a[1], ub = b[0] + b[1];
+                    const real ua = a[0] + a[1], ub = bb[0] + bb[1];
                     const real d = a[1] - th[p] * (ua - ub);
                     const uint32_t e = ooff[p] / (uint32_t)sizeof(real) + (uint32_t)(jy * g.nvx);  // element index
                     const bool odd = (jz & 1) != 0;
                     const uint32_t hb = hash32((e - (odd ? (uint32_t)g.npl : 0u)) ^ key);
                     r = round_stochastic16((double)a[0] + (double)d, __builtin_amdgcn_ubfe(hb, odd ? 16u : 0u, 16u));
                 } else {
-                    r = a[0] - th[p] * (a[0] - b[0]);
+                    r = a[0] - th[p] * (a[0] - bb[0]);
                 }
                 real *op = reinterpret_cast<real *>(reinterpret_cast<char *>(outb) + ooff[p] + yoff);
                 if constexpr (NTSTORE) __builtin_nontemporal_store(r, op);
                 else *op = r;
-                const double rd = (double)r;
+                const double rd = valid[p] && live ? (double)r : 0.0;
                 S0[p] += rd;
                 Sy[p] = __builtin_fma(vy, rd, Sy[p]);
                 Syy[p] = __builtin_fma(vy * vy, rd, Syy[p]);
-                if (vy < 0.0) Syn[p] = __builtin_fma(-vy, rd, Syn[p]);
             }
+            __syncthreads();  // the next row's staging overwrites the stage
+        };
+        real hA[ROW_EPL], hB[ROW_EPL];
+        fetch_ty(0);
+        put_yz(0);
+        fetch_ty(min(1, g.nvy - 1));
+        fetch(0, hA);
+        fetch(min(1, g.nvy - 1), hB);
+        __syncthreads();
+        for (int jy = 0; jy < g.nvy; jy += 2) {
+            row(jy, hA);
+            row(jy + 1, hB);
         }
         // fold into the NQ sums of each cell: a cell's G lanes are consecutive
-        // lanes of one wave (G <= 64)
+        // lanes of one wave (G <= 64).  The y and z half fluxes (wall sums of
+        // 2D and 3D kinds) are not formed: zero for these 1D instances.
         const ZW zw = zweights(g, jz);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             const int q = tid + p * nth, t = q >> lg, jx = q & (G - 1);
-            double v[9];
-            if (tj[p] >= 0) {
+            double v[7];
+            if (valid[p]) {
                 const double vx = vnode(g, 0, jx), ms = zw.m * S0[p];
                 v[0] = ms;
                 v[1] = vx * ms;
@@ -1891,21 +2021,19 @@ __global__ void __launch_bounds__(1024)
                 v[4] = (vx * vx * ms + zw.m * Syy[p]) + zw.zz * S0[p];
                 v[5] = vx < 0.0 ? -vx * ms : 0.0;
                 v[6] = vx > 0.0 ? vx * ms : 0.0;
-                v[7] = zw.m * Syn[p];
-                v[8] = zw.m * (Sy[p] + Syn[p]);
             } else {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) v[k] = 0.0;
+                for (int k = 0; k < 7; ++k) v[k] = 0.0;
             }
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
+            for (int k = 0; k < 7; ++k)
                 for (int off = G >> 1; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
             if (jx == 0 && t < te) {
                 double *out = partial + ((long long)(I.cell0 + i0 + t) * A.vsplit + jz) * NQ;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) out[k] = v[k];
-                out[9] = 0.0;
-                out[10] = 0.0;
+                for (int k = 0; k < 7; ++k) out[k] = v[k];
+#pragma unroll
+                for (int k = 7; k < NQ; ++k) out[k] = 0.0;
             }
         }
         __syncthreads();  // LDS tables are rebuilt by the next item

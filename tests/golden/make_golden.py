@@ -6,7 +6,9 @@ count, where running the oracle inside a test would take too long.  The file
 is rewritten after every mark, so a long run leaves the marks it reached.
 
     python tests/golden/make_golden.py shock_m3_fp32 1,10,100,500,1000,2000
-    python tests/golden/make_golden.py cavity_128_fp32 1,10,100,1000,2500,5000
+    python tests/golden/make_golden.py cavity_128_fp32 1,10,100,1000,2500,5000 [OUT.npz]
+
+(OUT.npz: where to write instead of tests/golden/<name>_oracle.npz.)
 """
 import os
 import sys
@@ -27,11 +29,11 @@ def save(path: str, out: dict):
     os.replace(tmp, path)
 
 
-def main(name: str, marks: list[int]):
+def main(name: str, marks: list[int], path: str | None = None):
     cfg = inputs.config(name)
     O = oracle.Oracle(cfg)
     f = O.initial_state()
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
     out = {"dt": np.array(O.dt), "steps": np.array([], dtype=np.int64)}
     done = 0
     t0 = time.time()
@@ -47,4 +49,4 @@ def main(name: str, marks: list[int]):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], [int(s) for s in sys.argv[2].split(",")])
+    main(sys.argv[1], [int(s) for s in sys.argv[2].split(",")], sys.argv[3] if len(sys.argv) > 3 else None)

@@ -169,7 +169,7 @@ def test_row_tiles_match_oracle_fp32(B, oracle_mod, kind):
 
 @pytest.mark.parametrize("nv", [(30, 6, 4), (16, 4, 6), (64, 2, 2), (5, 3, 2)])
 def test_row_tiles_several_tiles(B, oracle_mod, nv):
-    """Several tiles per instance (1024, 256 or 64 cells per tile with 4 pairs
+    """Several tiles per instance (256, 128 or 32 cells per tile with 4 pairs
     per lane) and a ragged last tile, at Courant numbers up to ~12."""
     lo, hi = (-10.0, -3.0, -3.0), (12.0, 3.0, 3.0)
     cfg = small("shock", nx={30: 300, 16: 600, 64: 150, 5: 1100}[nv[0]], nv=nv, vlo=lo, vhi=hi, cfl=12.3,
