@@ -63,10 +63,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def read_traffic(workload: str):
+def read_traffic(workload: str, kname: str = "k_stream"):
     """HBM bytes per streaming launch from a committed counter summary
     (profiles/<kernel>_<workload>_counters.txt), if taken from these kernels."""
-    path = os.path.join(PROFILES, f"k_stream_{workload}_counters.txt")
+    path = os.path.join(PROFILES, f"{kname}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -423,8 +423,8 @@ def main():
     value = points * args.steps / secs
     bpu = bytes_per_update(prec)
     achieved = bpu * points / (kms * 1e-3) / 1e9
-    traffic = read_traffic(args.workload)
     kname = "k_shift" if probs[0].get("limiter") == "shift" else "k_stream"  # the streaming kernel of this workload
+    traffic = read_traffic(args.workload, kname)
     cells = sum(inputs.ncells(q) for q in probs)
     out = {
         "metric": "phase-space point updates/s",

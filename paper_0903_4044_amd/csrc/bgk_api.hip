@@ -837,17 +837,14 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
         const int nbr = c->persist ? std::min(items, c->persist * c->ncu) : items;
         const Args a = make_args(c);
         const size_t l = c->row_lds_bytes;
-        const int sel = (c->row_pcache ? 2 : 0) + (stream_nt(c) ? 1 : 0);
+        // plain stores (measured faster than non-temporal ones here even when
+        // the f buffers exceed the last-level cache)
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nbr), dim3(ROW_THREADS), l, s, a, (const real *)src, (real *)dst, p, c->partial,
                                c->row_tt, c->row_wmax, c->row_lg);
         };
-        switch (sel) {
-        case 3: go(k_shift_rows<real, 4, true, true>); break;
-        case 2: go(k_shift_rows<real, 4, true, false>); break;
-        case 1: go(k_shift_rows<real, 4, false, true>); break;
-        default: go(k_shift_rows<real, 4, false, false>); break;
-        }
+        if (c->row_pcache) go(k_shift_rows<real, 4, true, false>);
+        else go(k_shift_rows<real, 4, false, false>);
     } else if (c->shift) {
         const real *p = (const real *)params_buf<real>(c, c->pass_parity);
         // the v_z tables of a cell's 2 Nvx source entries, staged in LDS when they fit in 64 KB

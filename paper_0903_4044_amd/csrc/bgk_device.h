@@ -142,6 +142,23 @@ __device__ __forceinline__ int strip_cell(const Inst &I, int q)
     return iz * pl + iy * I.nx + nfull * W + (r - iy * rem);
 }
 
+// Order of the streaming kernel's (cell, jz chunk) items: superblocks of
+// SUPER cells in the visiting order, each walked chunk by chunk.  The items
+// in flight on one XCD are then one chunk of up to about SUPER consecutive
+// cells, and the cells their stencils reach (two rows either side in the
+// strip order) are the same chunk of nearby cells: a working set of one
+// chunk per cell, where walking all chunks of a cell together would keep
+// every chunk of all those cells in the XCD's L2 at once.
+constexpr int SUPER = 128;
+
+__device__ __forceinline__ void item_cell_chunk(int L, int ncells, int vsplit, int *cell, int *split)
+{
+    const int sb = L / (SUPER * vsplit), c0 = sb * SUPER;
+    const int n = min(SUPER, ncells - c0), k = L - c0 * vsplit;
+    *split = k / n;
+    *cell = c0 + (k - *split * n);
+}
+
 __device__ __forceinline__ double vnode(const Geo &g, int a, int k) { return g.lo[a] + (k + 0.5) * g.dv[a]; }
 
 // The jz planes [z0, z1) of chunk `split` of `vsplit`: chunks start on even
@@ -1135,7 +1152,8 @@ __global__ void __launch_bounds__(256)
     const int nitems = A.ncells * A.vsplit;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int Lq = xcd_remap(item, nitems);
-    const int gq = Lq / A.vsplit, split = Lq % A.vsplit;
+    int gq, split;
+    item_cell_chunk(Lq, A.ncells, A.vsplit, &gq, &split);
     const int ii = find_inst(A.cell_prefix, A.ninst, gq);
     const Inst &I = A.inst[ii];
     const int c = strip_cell(I, gq - I.cell0);
