@@ -48,6 +48,10 @@ DESCRIPTIONS = {
                        "FP64 throughout, Strang + minmod upwind, CFL 0.5",
     "cavity_128_fp32": "2D lid-driven cavity 128x128, lid Mach 0.1, Kn 0.1, T_w 1, 24^3 velocities on [-5,5]^3, "
                        "diffuse walls; f FP32, moments FP64",
+    "cube_48_fp32": "3D lid-driven cube 48^3, lid Mach 0.1 along x on the y = 1 face, Kn 0.1, T_w 1, six diffuse "
+                    "walls, 16^3 velocities on [-4.5,4.5]^3; f FP32, moments FP64",
+    "batch_mixed_fp32": "the 64-cavity batch with 8 seeded normal shocks (Nx from {256,512,1024}, Mach U(1.2,2)) "
+                        "on the same 24^3 grid, one context: 2D kernels with the shocks streaming along x only",
     "shock_m3_fp32_conservative": "the Mach-3 shock above with every relaxation towards the effective "
                                   "Maxwellian (per-cell Newton solve, exact conservation on the grid)",
     "cavity_128_fp32_conservative": "the 128^2 cavity above with every relaxation towards the effective "
@@ -92,7 +96,7 @@ def speed_scale(p) -> float:
     the lid speed of a cavity."""
     if p["kind"] == "shock":
         return p["mach"] * (GAMMA / 2) ** 0.5
-    if p["kind"] == "cavity" and p.get("lid_mach", 0.0) != 0.0:
+    if p["kind"] in ("cavity", "cavity3d") and p.get("lid_mach", 0.0) != 0.0:
         return abs(p["lid_mach"]) * (GAMMA / 2) ** 0.5
     return 1.0
 
@@ -369,6 +373,8 @@ def workload(inputs, name: str):
     """(problems, precision) of a named workload."""
     if name == BATCH:
         return inputs.batch_cavities(), "fp32"
+    if name == "batch_mixed_fp32":
+        return inputs.batch_mixed(), "fp32"
     cfg = inputs.config(name)
     return [cfg], cfg["precision"]
 
@@ -463,6 +469,10 @@ def main():
         runs = [("shock_m1.5_fp64", "fp64", 200, 10, False),
                 ("shock_m3_fp32", "fp32", 200, 10, False),
                 ("cavity_128_fp32", "fp32", 200, 10, False),
+                # three dimensions: the lid-driven cube
+                ("cube_48_fp32", "fp32", 20, 3, False),
+                # shocks batched with the cavities in one context
+                ("batch_mixed_fp32", "fp32", 20, 3, False),
                 # the headline batch again, one replayed graph per call (wall clock)
                 (BATCH + "_graph", "fp32", 20, 2, True),
                 # the paper's own shock runs: translation streaming, Courant numbers up to ~150

@@ -103,6 +103,11 @@ CONFIGS = {
                                     nv=(30, 1, 2), vlo=(-10.0, -1.0, -1.0), vhi=(12.0, 1.0, 1.0),
                                     kn=1.0, omega=0.74, dt=0.05, mach=3.0, splitting="lie",
                                     limiter="shift", steps=200, precision="fp32", reduced=True),
+    # The lid-driven cube: 48^3 cells, 16^3 velocities on [-4.5, 4.5]^3
+    # (v_z changes sign at plane 8), lid Mach 0.1, Kn 0.1, six diffuse walls.
+    "cube_48_fp32": _base(kind="cavity3d", nx=48, ny=48, nz=48, z0=0.0, z1=1.0, nv=(16, 16, 16),
+                          vlo=(-4.5,) * 3, vhi=(4.5,) * 3, kn=0.1, lid_mach=0.1, t_wall=1.0, steps=200,
+                          precision="fp32"),
     # Adjoint workload: 64^2 cavity, 200 steps.
     "cavity_64_adjoint": _base(kind="cavity", nx=64, ny=64, nv=(24, 24, 24),
                                vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=0.1,
@@ -153,6 +158,20 @@ def batch_cavities(n: int = 64, seed: int = BATCH_SEED, steps: int = 1000,
                          vlo=(-5.0,) * 3, vhi=(5.0,) * 3, kn=kn,
                          lid_mach=ma, t_wall=1.0, steps=steps,
                          precision=precision))
+    return out
+
+
+def batch_mixed(seed: int = BATCH_SEED + 2, precision: str = "fp32") -> list[dict]:
+    """The 64-cavity batch and 8 seeded normal shocks on the same 24^3 grid
+    on [-5, 5]^3, stepped together: per shock, in order, Nx from {256, 512,
+    1024} (uniform) on [-20, 20] and Mach U(1.2, 2.0), Kn 1."""
+    rng = np.random.default_rng(seed)
+    out = batch_cavities(precision=precision)
+    for _ in range(8):
+        nx = int(rng.choice((256, 512, 1024)))
+        mach = float(rng.uniform(1.2, 2.0))
+        out.append(_base(kind="shock", nx=nx, x0=-20.0, x1=20.0, nv=(24, 24, 24), vlo=(-5.0,) * 3,
+                         vhi=(5.0,) * 3, kn=1.0, mach=mach, steps=1000, precision=precision))
     return out
 
 

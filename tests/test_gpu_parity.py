@@ -36,7 +36,7 @@ def small(kind, **kw):
 def speed_scale(cfg):
     if cfg["kind"] == "shock":
         return cfg["mach"] * math.sqrt(GAMMA / 2)
-    if cfg["kind"] == "cavity" and cfg.get("lid_mach", 0.0) != 0.0:
+    if cfg["kind"] in ("cavity", "cavity3d") and cfg.get("lid_mach", 0.0) != 0.0:
         return abs(cfg["lid_mach"]) * math.sqrt(GAMMA / 2)
     return 1.0
 
@@ -183,7 +183,8 @@ def test_shock_m15_fp64_full_run(B, oracle_mod):
 
 @pytest.mark.parametrize("name,precision,nsteps", [
     ("shock_m3_fp32", "fp32", 2), ("shock_m3_fp32", "fp64", 1),
-    ("cavity_128_fp32", "fp32", 2), ("cavity_128_fp32", "fp64", 1)])
+    ("cavity_128_fp32", "fp32", 2), ("cavity_128_fp32", "fp64", 1),
+    ("cube_48_fp32", "fp32", 2), ("cube_48_fp32", "fp64", 1)])
 def test_full_size_few_steps(B, oracle_mod, name, precision, nsteps):
     """Full-size grids in the benchmark's launch configuration, a few steps."""
     cfg = inputs.config(name)
