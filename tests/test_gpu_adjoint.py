@@ -163,9 +163,11 @@ def test_full_adjoint_workload(B, prec):
         # The adjoint is piecewise constant in the state (minmod branches).
         # FP32 rounding of f moves near-ties to the other branch, which changes
         # the entry by C k mu (k = (1 - C)/2) there and spreads from it, so
-        # the FP32 bound is on the bulk of the entries, not on every one.
+        # the FP32 bound is on the bulk of the entries, with a looser one on
+        # every entry.  Measured with the recomputed trajectory equal to the
+        # forward one: p99 4.1e-4, max 8.8e-3 of max |lambda^0|.
         print(f"fp32 lambda0 on sampled cells: p99 {np.percentile(err, 99):.3e} max {err.max():.3e}")
-        assert np.percentile(err, 99) <= 1e-2 and err.max() <= 0.2, (np.percentile(err, 99), err.max())
+        assert np.percentile(err, 99) <= 2e-3 and err.max() <= 3e-2, (np.percentile(err, 99), err.max())
     if prec == "fp64":
         x = f0.detach()
         for key, got in (("kn", float(kn.grad)), ("t_wall", float(tw.grad))):
