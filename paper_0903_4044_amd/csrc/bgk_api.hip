@@ -683,19 +683,29 @@ static int pointwise_vec(const bgk_ctx *c)
     return 1;
 }
 
+// Arguments of the pointwise kernels (moments, initial state, closing
+// relaxation): their own jz chunk count, the streaming one except for the
+// row-tile translation form, whose one chunk per plane would leave these
+// kernels mostly empty workgroups; the moment sums still fill every one of
+// the nparts slots per cell that the table preparation adds up.
+static Args pointwise_args(const bgk_ctx *c)
+{
+    Args a = make_args(c);
+    if (c->shift && c->unroll == 2) a.vsplit = std::min(c->vsplit, vsplit_for(c, 2048));
+    return a;
+}
+
 template <typename real>
 static int launch_moments(bgk_ctx *c, const void *f, hipStream_t s)
 {
-    const int nb = c->ncells * c->vsplit;
+    const Args a = pointwise_args(c);
+    const int nb = c->ncells * a.vsplit;
     if (pointwise_vec(c) == 4)
-        hipLaunchKernelGGL((k_moments<real, 4>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
-                           c->partial);
+        hipLaunchKernelGGL((k_moments<real, 4>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
     else if (pointwise_vec(c) == 2)
-        hipLaunchKernelGGL((k_moments<real, 2>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
-                           c->partial);
+        hipLaunchKernelGGL((k_moments<real, 2>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
     else
-        hipLaunchKernelGGL((k_moments<real, 1>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)f,
-                           c->partial);
+        hipLaunchKernelGGL((k_moments<real, 1>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -875,17 +885,15 @@ static int launch_stream(bgk_ctx *c, const void *src, void *dst, hipStream_t s)
 template <typename real>
 static int launch_final(bgk_ctx *c, const void *src, void *dst, int parity, hipStream_t s)
 {
-    const int nb = c->ncells * c->vsplit;
+    const Args a = pointwise_args(c);
+    const int nb = c->ncells * a.vsplit;
     const real *p = (const real *)params_buf<real>(c, parity);
     if (pointwise_vec(c) == 4)
-        hipLaunchKernelGGL((k_final<real, 4>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
-                           (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 4>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
     else if (pointwise_vec(c) == 2)
-        hipLaunchKernelGGL((k_final<real, 2>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
-                           (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 2>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
     else
-        hipLaunchKernelGGL((k_final<real, 1>), dim3(nb), dim3(c->block), 0, s, make_args(c), (const real *)src,
-                           (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 1>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -1438,11 +1446,12 @@ extern "C" int bgk_initial_state(bgk_ctx *ctx, void *f, void *stream)
     if (!ctx) return BGK_E_INVALID;
     if (!f) return fail(ctx, BGK_E_INVALID, "bgk_initial_state: NULL buffer");
     hipStream_t s = (hipStream_t)stream;
-    const int nb = ctx->ncells * ctx->vsplit;
+    const Args a = pointwise_args(ctx);
+    const int nb = ctx->ncells * a.vsplit;
     if (ctx->precision == BGK_FP64)
-        hipLaunchKernelGGL(k_init<double>, dim3(nb), dim3(ctx->block), 0, s, make_args(ctx), (double *)f);
+        hipLaunchKernelGGL(k_init<double>, dim3(nb), dim3(ctx->block), 0, s, a, (double *)f);
     else
-        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(ctx->block), 0, s, make_args(ctx), (float *)f);
+        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(ctx->block), 0, s, a, (float *)f);
     HIP_TRY(ctx, hipGetLastError());
     return BGK_OK;
 }

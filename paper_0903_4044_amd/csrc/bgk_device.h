@@ -357,7 +357,7 @@ __device__ __forceinline__ V buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uin
 
 // ---------------------------------------------------------------- moments
 // Partial moment sums of f over one jz chunk of one cell:
-// partial[(cell * vsplit + split) * NQ + q] (without the dV factor).  Each
+// partial[(cell * nparts + split) * NQ + q] (without the dV factor).  Each
 // lane reads VEC consecutive jx at one jy (16-byte loads where the grid
 // allows) down its jz chunk.
 template <typename real, int VEC>
@@ -401,7 +401,12 @@ __global__ void __launch_bounds__(256) k_moments(Args A, const real *__restrict_
             fold_column(acc, vnode(g, 0, jx0 + e), vnode(g, 1, jy), A0[e], e == 0 ? Az : 0.0, e == 0 ? Azz : 0.0,
                         e == 0 ? Azm : 0.0, e == 0 ? Azp : 0.0);
     }
-    block_sum_store<NQ>(acc, partial + (long long)L * NQ);
+    // slot (cell, split) of the A.nparts per cell the consumers add up; a
+    // launch with fewer chunks than slots zeroes the remaining ones
+    block_sum_store<NQ>(acc, partial + ((long long)gc * A.nparts + split) * NQ);
+    if (split == 0)
+        for (int t = threadIdx.x; t < (A.nparts - A.vsplit) * NQ; t += blockDim.x)
+            partial[((long long)gc * A.nparts + A.vsplit) * NQ + t] = 0.0;
 }
 
 // Per-cell macroscopic moments (n, Vx, Vy, Vz, T) from the partial sums.
