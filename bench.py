@@ -208,12 +208,14 @@ def run_workload(binding, torch, problems, precision, steps, warmup, kernel_timi
     return t1 - t0, ms / max(launches, 1), points, shape
 
 
-def run_adjoint(binding, torch, cfg, precision, every=20):
+def run_adjoint(binding, torch, cfg, precision, every=None):
     """Differentiated rollout of the adjoint workload: forward with checkpoints
-    every `every` steps, then the checkpointed reverse sweep (segment
-    recomputation + one bgk_step_adjoint per step) down to dL/df0, dL/dKn and
-    dL/dT_w.  Returns (forward s, backward s, points, steps, gradient errors
-    against the stored FP64 oracle sweep or None)."""
+    every `every` steps (None: the interval the solver picks from the free
+    device memory, 1 when the whole trajectory fits), then the reverse sweep
+    (segment recomputation where every > 1, one bgk_step_adjoint per step)
+    down to dL/df0, dL/dKn and dL/dT_w.  Returns (forward s, backward s,
+    points, steps, gradient errors against the stored FP64 oracle sweep or
+    None, the checkpoint interval used)."""
     import numpy as np
 
     from paper_0903_4044_amd import inputs, solver
@@ -240,8 +242,9 @@ def run_adjoint(binding, torch, cfg, precision, every=20):
             raise RuntimeError("non-finite gradient in the adjoint run")
         return t1 - t0, t2 - t1, float(L.detach()), float(kn.grad), float(tw.grad)
 
-    once(every)  # warm-up: one segment
+    once(20)  # warm-up
     fwd, bwd, L, gkn, gtw = once(nsteps)
+    used = ctx.last_checkpoint_every
     err = None
     path = os.path.join(GOLDEN, "cavity_64_adjoint_oracle.npz")
     if os.path.exists(path):
@@ -253,7 +256,7 @@ def run_adjoint(binding, torch, cfg, precision, every=20):
     ctx.close()
     del f0
     torch.cuda.empty_cache()
-    return fwd, bwd, points, nsteps, err
+    return fwd, bwd, points, nsteps, err, used
 
 
 def _cpu_model() -> str:
@@ -514,11 +517,12 @@ def main():
         for p in ("fp32", "fp64"):
             if wanted and f"adjoint_cavity_64_{p}" not in wanted:
                 continue
-            fwd, bwd, pts, n, gerr = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
+            fwd, bwd, pts, n, gerr, every = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
             e = {"updates_per_s": pts * n / (fwd + bwd), "steps": n, "points": pts, "precision": p,
                  "forward_s": fwd, "reverse_s": bwd, "reverse_updates_per_s": pts * n / bwd,
-                 "checkpoint_every": 20,
-                 "note": "updates/s counts each of the rollout's steps once over forward + checkpointed reverse"}
+                 "checkpoint_every": every,
+                 "note": "updates/s counts each of the rollout's steps once over forward + reverse sweep "
+                         "(checkpoint_every 1: every state kept in HBM, no recomputation)"}
             if gerr:
                 e["error_vs_oracle"] = gerr
             extras[f"adjoint_cavity_64_{p}"] = e

@@ -161,7 +161,8 @@ const char *bgk_last_error(const bgk_ctx *ctx);
 /* Sizes: total f elements over all instances, total spatial cells, and
  * the bytes of the caller-owned workspaces: ws_step_bytes for bgk_step and
  * bgk_autotune (one f-sized buffer), ws_adjoint_bytes for bgk_step_adjoint
- * (two).  Any output pointer may be NULL. */
+ * (two f-sized buffers and one byte per element of f, rounded up to 256).
+ * Any output pointer may be NULL. */
 int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells, size_t *ws_step_bytes,
               size_t *ws_adjoint_bytes);
 
@@ -302,16 +303,15 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
  * Minmod branch decisions are those of the forward map at f_n: a limited
  * slope is differentiated as 0 unless both differences have the same strict
  * sign, else as the smaller-magnitude difference (the backward one on a tie
- * of magnitudes).  ws: the caller's device workspace of ws_adjoint_bytes
- * (bgk_sizes; two f-sized intermediate states, overwritten), not overlapping
- * f_n, lam_next or lam_n (BGK_E_ALIAS); NULL gives BGK_E_INVALID.  The first
- * call allocates the context's per-cell reverse-sweep coefficients;
- * BGK_E_HIP if that fails, BGK_E_UNSUPPORTED if the sweep's 17 (2D) or 9
- * (1D) table entries per
- * workgroup exceed the device's LDS, for BGK_SHIFT contexts (no reverse
- * sweep of the translation form) and for contexts with a BGK_CONSERVATIVE
- * instance (no reverse sweep of the effective parameters' solve) and for
- * 3D kinds.  Asynchronous on `stream`. */
+ * of magnitudes); the call's own recomputation of the forward streaming
+ * pass records them.  ws: the caller's device workspace of ws_adjoint_bytes
+ * (bgk_sizes; two f-sized intermediate states and the branch record,
+ * overwritten), not overlapping f_n, lam_next or lam_n (BGK_E_ALIAS); NULL
+ * gives BGK_E_INVALID.  The first call allocates the context's per-cell
+ * reverse-sweep coefficients; BGK_E_HIP if that fails, BGK_E_UNSUPPORTED for
+ * BGK_SHIFT contexts (no reverse sweep of the translation form), for contexts
+ * with a BGK_CONSERVATIVE instance (no reverse sweep of the effective
+ * parameters' solve) and for 3D kinds.  Asynchronous on `stream`. */
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *ws, void *stream);
 

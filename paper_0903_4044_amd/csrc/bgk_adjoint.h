@@ -12,10 +12,12 @@
 // 1, v, |v|^2 per cell whose coefficients come from six sums of mu against
 // Phi and x (k_adj_sums, then k_adj_coef; k_adj_apply applies them).  The
 // minmod streaming step is transposed on the branches the forward step takes
-// (k_adj_stream, gather form), reading f^n and lambda^{n+1} directly: a and
-// hbar are formed on the fly from per-cell tables and coefficients and never
-// stored.  The diffuse-wall ghosts of Eq. (bc_cavity) return their adjoint to
-// the wall density n_W and from there to the wall-adjacent cell (k_adj_wall).
+// (k_adj_stream, gather form): the step's own streaming pass h = S(a), run in
+// its recording form, stores each element's limiter branches, and the gather
+// reads them with lambda^{n+1}; hbar is formed on the fly from per-cell
+// coefficients and never stored.  The diffuse-wall ghosts of Eq. (bc_cavity)
+// return their adjoint to the wall density n_W and from there to the
+// wall-adjacent cell (k_adj_wall).
 #pragma once
 
 #include "bgk_device.h"
@@ -195,33 +197,18 @@ __global__ void __launch_bounds__(256) k_adj_apply(Args A, const real *__restric
 //   A0 = [b0 = a] - [b0 = b] + [b-1 = a],   A1 = [b1 = b] - [b0 = a] + [b0 = b],
 // plus mu(0) once for all directions; mu(m) is the adjoint at i + s m (zero
 // outside a non-periodic domain).  Here mu = R_b^T(lambda^{n+1}) is formed on
-// the fly from lambda^{n+1} and each slot cell's relaxation coefficients, and
-// G = R_a(f^n) from f^n and the opening tables of the forward step, so neither
-// is ever stored.
+// the fly from lambda^{n+1} and each slot cell's relaxation coefficients.
+// The branches are not recomputed: the step's own streaming pass, run in its
+// recording form, stored per element and direction beta(-1) and beta(0) as
+// it took them (one byte, x in bits 0-3, y in bits 4-7), and beta(1) is the
+// beta(0) that the pass recorded at i + s.  Where i + s lies outside the
+// domain, mu(1) = mu(2) = 0 and beta(1) does not enter.
 //
 // Slots: 0 centre; 1 + 8*d + 4*si + m for direction d (0 x, 1 y), si = 0 for
 // s = +1, 1 for s = -1, m = 0..3 for k = -2, -1, +1, +2.
 struct AdjSlots {
     int cell[17], par[17], mucell[17];
 };
-
-// Forward input at a slot, with the forward kernel's own arithmetic (so the
-// minmod branches are the ones the forward step took).
-template <typename real, int VEC>
-__device__ __forceinline__ Tap<real, VEC> input_tap(const Geo &g, const real *E, int cell, int p0, int jx0, int jy)
-{
-    Tap<real, VEC> t;
-    t.off = (uint32_t)(((long long)cell * g.nv + p0) * sizeof(real));
-    t.tz = E + g.tz;
-    t.c0 = E[0];
-    const real y1 = E[g.ty1 + jy], y2 = E[g.ty2 + jy];
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-        t.l1[k] = E[g.tx1 + jx0 + k] * y1;
-        t.l2[k] = E[g.tx2 + jx0 + k] * y2;
-    }
-    return t;
-}
 
 // Adjoint input at a slot: mu = c0 lambda + l1 + (g3 + g4 vz) vz, all zero at a ghost.
 template <typename real, int VEC>
@@ -253,67 +240,44 @@ __device__ __forceinline__ MuTap<real, VEC> mu_tap(const Geo &g, const double *c
     return t;
 }
 
-// Branch of minmod(a, b): 0 unless a and b have the same strict sign, then
-// 1 if |a| < |b| (slope = a, the forward difference), else 2 (slope = b).
-// It is read off the forward limiter's own value m = median(a, b, 0): m is
-// 0, or equal to b (taken on a tie |a| = |b|), or else equal to a.  (The
-// product a b of two Maxwellian-tail slopes would underflow in float.)
+// One direction's contribution (see above) from the branch codes bm1, b0, b1
+// of the slopes at i - s, i, i + s (mm_code: 0 zero, 1 a, 2 b).  The codes
+// enter only through 0/1 indicators, so the adjoint is a short sum of exact
+// integer multiples of the mu values.
 template <typename real>
-__device__ __forceinline__ int mm_branch(real a, real b)
+__device__ __forceinline__ real direction_adjoint(uint32_t bm1, uint32_t b0, uint32_t b1, real mm1, real m0, real m1,
+                                                  real m2, real C, real k)
 {
-    const real m = minmod3(a, b);
-    return m == (real)0 ? 0 : (m == b ? 2 : 1);
-}
-
-// Branch indicators of one limiter evaluation as numbers: p1 = [branch 1],
-// p2 = [branch 2] (mm_branch's cases), formed from the same median value.
-template <typename real>
-struct MmInd {
-    real p1, p2;
-};
-
-template <typename real>
-__device__ __forceinline__ MmInd<real> mm_ind(real a, real b)
-{
-    const real m = minmod3(a, b);
-    const bool nz = m != (real)0, eb = m == b;
-    return {nz && !eb ? (real)1 : (real)0, nz && eb ? (real)1 : (real)0};
-}
-
-// One direction's contribution (values in upwind order, see above).  The
-// branch codes enter only through 0/1 indicators, so the adjoint is a short
-// sum of exact integer multiples of the mu values.
-template <typename real>
-__device__ __forceinline__ real direction_adjoint(real um2, real um1, real u0, real u1, real u2, real mm1, real m0,
-                                                  real m1, real m2, real C, real k)
-{
-    const MmInd<real> bm1 = mm_ind<real>(u0 - um1, um1 - um2);
-    const MmInd<real> b0 = mm_ind<real>(u1 - u0, u0 - um1);
-    const MmInd<real> b1 = mm_ind<real>(u2 - u1, u1 - u0);
-    const real A0 = b0.p1 - b0.p2 + bm1.p1;
-    const real A1 = b1.p2 - b0.p1 + b0.p2;
-    const real lim = m0 * A0 + m1 * A1 - b1.p2 * m2 - bm1.p1 * mm1;
+    const real am1 = bm1 == 1u ? (real)1 : (real)0;
+    const real a0 = b0 == 1u ? (real)1 : (real)0, c0 = b0 == 2u ? (real)1 : (real)0;
+    const real c1 = b1 == 2u ? (real)1 : (real)0;
+    const real A0 = a0 - c0 + am1;
+    const real A1 = c1 - a0 + c0;
+    const real lim = m0 * A0 + m1 * A1 - c1 * m2 - am1 * mm1;
     return C * (m1 - m0) + C * k * lim;
 }
 
 // Lane tasks as in the forward kernel: VEC consecutive jx of one v_x sign at
-// one jy, residue zr of jz modulo A.zr.  The block of a wall-adjacent cavity
-// cell also accumulates, per wall it feeds, S_gamma = sum gamma Phi_W and
+// one jy, residue zr of jz modulo A.zr.  Per element the kernel reads its
+// branch byte, the branch bytes of its two downwind neighbours (x, y) and the
+// 7 (1D: 4) lambda taps.  The block of a wall-adjacent cavity cell also
+// accumulates, per wall it feeds, S_gamma = sum gamma Phi_W and
 // S_gamma' = sum gamma dPhi_W/dT_w over the emitted velocities, where
 // gamma = C mu(0) + C k [b0 = b] (mu(0) - mu(1)) is the adjoint of that
-// velocity's emitted ghost value per unit n_W.
-// ZU (one jz residue, all lanes of a wave on one plane): as in the forward
-// kernel, the plane offset goes into the scalar base of the loads and the f
-// taps' z-tables are read from a role-ordered LDS copy.
+// velocity's emitted ghost value per unit n_W; the emitted ghosts' table
+// entries sit in dynamic LDS (2 per direction: the k = -1 slots of both
+// signs).  ZU (one jz residue, all lanes of a wave on one plane): the plane
+// offset goes into the scalar base of the lambda loads.
 template <typename real, int DIM, int VEC, bool ZU>
 __global__ void __launch_bounds__(256)
-    k_adj_stream(Args A, const real *__restrict__ f, const real *__restrict__ params, const real *__restrict__ lam,
-                 const double *__restrict__ coef, real *__restrict__ out, double *__restrict__ wsum)
+    k_adj_stream(Args A, const unsigned char *__restrict__ rec, const real *__restrict__ params,
+                 const real *__restrict__ lam, const double *__restrict__ coef, real *__restrict__ out,
+                 double *__restrict__ wsum)
 {
     using V = vec_t<real, VEC>;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NSL = DIM == 1 ? 9 : 17;
-    real *sp = reinterpret_cast<real *>(smem);
+    real *sp = reinterpret_cast<real *>(smem);  // [2 d + si][entry]: the k = -1 slots' entries
     __shared__ AdjSlots S;
     __shared__ double cf[NSL][NCOEF];
     const Geo &g = A.g;
@@ -340,43 +304,31 @@ __global__ void __launch_bounds__(256)
         S.mucell[sl] = mc;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < NSL * g.pe; t += blockDim.x) {
-        const int sl = t / g.pe, o = t - sl * g.pe;
-        sp[t] = params[(long long)S.par[sl] * g.pe + o];
-    }
+    const bool cav = I.kind == KIND_CAVITY;
+    // walls whose emitted ghosts this cell's stencils read: 0 left, 1 right, 2 bottom, 3 top
+    const bool wl = cav && ix == 0, wr = cav && ix == I.nx - 1, wb = cav && iy == 0, wt = cav && iy == I.ny - 1;
+    const bool wall = wl || wr || wb || wt;
+    if (wall)
+        for (int t = threadIdx.x; t < 2 * DIM * g.pe; t += blockDim.x) {
+            const int q = t / g.pe, o = t - q * g.pe;  // q = 2 d + si
+            sp[t] = params[(long long)S.par[1 + 8 * (q >> 1) + 4 * (q & 1) + 1] * g.pe + o];
+        }
     for (int t = threadIdx.x; t < NSL * NCOEF; t += blockDim.x) {
         const int sl = t / NCOEF, q = t - sl * NCOEF;
         cf[sl][q] = S.mucell[sl] >= 0 ? coef[(long long)(I.cell0 + S.mucell[sl]) * NCOEF + q] : 0.0;
     }
     __syncthreads();
-    constexpr int NROLE = DIM == 1 ? 5 : 9;   // centre, x (-2, -1, +1, +2), y (-2, -1, +1, +2)
-    constexpr int NCOMBO = DIM == 1 ? 2 : 4;  // sign of v_x (and of v_y)
-    real *tzr = sp + NSL * g.pe;             // [combo][jz][role][2]
-    if constexpr (ZU) {
-        const int n = NCOMBO * g.nvz * NROLE;
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
-            const int role = t % NROLE, jz = (t / NROLE) % g.nvz, combo = t / (NROLE * g.nvz);
-            const int sx = combo & 1, sy = combo >> 1;
-            const int slot = role == 0 ? 0 : role <= 4 ? 1 + 4 * sx + (role - 1) : 9 + 4 * sy + (role - 5);
-            const real *E = sp + slot * g.pe + g.tz + 2 * jz;
-            tzr[2 * t] = E[0];
-            tzr[2 * t + 1] = E[1];
-        }
-        __syncthreads();
-    }
 
-    const real *fb = f + I.f0;
     const real *lb = lam + I.f0;
+    const unsigned char *rb = rec + I.f0;
     real *ob = out + I.f0;
     const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));  // below 2^32 (init)
-    const __amdgpu_buffer_rsrc_t frs = make_rsrc(fb, ibytes), lrs = make_rsrc(lb, ibytes);
+    const __amdgpu_buffer_rsrc_t lrs = make_rsrc(lb, ibytes);
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
+    const uint32_t rown = (uint32_t)c * (uint32_t)g.nv;  // element index of (cell, 0) in the instance
     int z0, z1;
     chunk_bounds(g.nvz, A.vsplit, split, &z0, &z1);
     const bool lim = I.minmod != 0;
-    const bool cav = I.kind == KIND_CAVITY;
-    // walls whose emitted ghosts this cell's stencils read: 0 left, 1 right, 2 bottom, 3 top
-    const bool wl = cav && ix == 0, wr = cav && ix == I.nx - 1, wb = cav && iy == 0, wt = cav && iy == I.ny - 1;
     const int ngx = g.nvx / VEC, ngroups = ngx * g.nvy, ntask = ngroups * A.zr;
     const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
     const double itw = 1.0 / I.tw;
@@ -394,115 +346,97 @@ __global__ void __launch_bounds__(256)
         }
         const double vy = vnode(g, 1, jy);
         const int sx = vnode(g, 0, jx0) > 0.0 ? 0 : 1;
-        const real *tzl = tzr + (DIM == 1 ? sx : sx + 2 * (vy > 0.0 ? 0 : 1)) * g.nvz * NROLE * 2;
         const int bx = 1 + 4 * sx;
-        const Tap<real, VEC> tc = input_tap<real, VEC>(g, sp, S.cell[0], p0, jx0, jy);
-        const Tap<real, VEC> xa = input_tap<real, VEC>(g, sp + (bx + 0) * g.pe, S.cell[bx + 0], p0, jx0, jy);
-        const Tap<real, VEC> xb = input_tap<real, VEC>(g, sp + (bx + 1) * g.pe, S.cell[bx + 1], p0, jx0, jy);
-        const Tap<real, VEC> xd = input_tap<real, VEC>(g, sp + (bx + 2) * g.pe, S.cell[bx + 2], p0, jx0, jy);
-        const Tap<real, VEC> xe = input_tap<real, VEC>(g, sp + (bx + 3) * g.pe, S.cell[bx + 3], p0, jx0, jy);
         const MuTap<real, VEC> mc = mu_tap<real, VEC>(g, cf[0], S.mucell[0], c, p0, jx0, vy);
         const MuTap<real, VEC> mxb = mu_tap<real, VEC>(g, cf[bx + 1], S.mucell[bx + 1], c, p0, jx0, vy);
         const MuTap<real, VEC> mxd = mu_tap<real, VEC>(g, cf[bx + 2], S.mucell[bx + 2], c, p0, jx0, vy);
         const MuTap<real, VEC> mxe = mu_tap<real, VEC>(g, cf[bx + 3], S.mucell[bx + 3], c, p0, jx0, vy);
+        // branch records: this element's, and its downwind x (and y) neighbour's
+        const unsigned char *rc = rb + rown + p0;
+        const unsigned char *rx = rb + (uint32_t)S.cell[bx + 2] * (uint32_t)g.nv + p0;
+        const unsigned char *ry = rc;
         // emitted x ghosts read by this cell: its own wall entry (slot k = -1)
         const bool emx = ((sx == 0 && wl) || (sx == 1 && wr));
         const int wx = sx == 0 ? 0 : 1;
-        Tap<real, VEC> ya, yb, yd, ye;
         MuTap<real, VEC> myb, myd, mye;
         V Cy = 0, ky = 0;
-        int by = 0;
+        int sy = 0;
         bool emy = false;
         int wy = 2;
         if constexpr (DIM == 2) {
-            const int sy = vy > 0.0 ? 0 : 1;
-            by = 9 + 4 * sy;
+            sy = vy > 0.0 ? 0 : 1;
+            const int by = 9 + 4 * sy;
             const real cy = (real)(fabs(vy) * I.cy);
             Cy = cy;
             ky = lim ? (real)0.5 * ((real)1 - cy) : (real)0;
-            ya = input_tap<real, VEC>(g, sp + (by + 0) * g.pe, S.cell[by + 0], p0, jx0, jy);
-            yb = input_tap<real, VEC>(g, sp + (by + 1) * g.pe, S.cell[by + 1], p0, jx0, jy);
-            yd = input_tap<real, VEC>(g, sp + (by + 2) * g.pe, S.cell[by + 2], p0, jx0, jy);
-            ye = input_tap<real, VEC>(g, sp + (by + 3) * g.pe, S.cell[by + 3], p0, jx0, jy);
             myb = mu_tap<real, VEC>(g, cf[by + 1], S.mucell[by + 1], c, p0, jx0, vy);
             myd = mu_tap<real, VEC>(g, cf[by + 2], S.mucell[by + 2], c, p0, jx0, vy);
             mye = mu_tap<real, VEC>(g, cf[by + 3], S.mucell[by + 3], c, p0, jx0, vy);
+            ry = rb + (uint32_t)S.cell[by + 2] * (uint32_t)g.nv + p0;
             emy = (sy == 0 && wb) || (sy == 1 && wt);
             wy = sy == 0 ? 2 : 3;
         }
-        // The 9 (1D: 5) f taps and 7 (1D: 4) lambda taps of one plane, loaded
+        // The 7 (1D: 4) lambda taps and the branch bytes of one plane, loaded
         // one plane ahead of their use (software pipeline; the prefetch after
         // the lane's last plane re-reads it).
-        constexpr int NF = DIM == 1 ? 5 : 9, NL = DIM == 1 ? 4 : 7;
-        auto load_plane = [&](int j, V (&F)[NF], V (&Lm)[NL]) {
+        constexpr int NL = DIM == 1 ? 4 : 7;
+        using B = vec_t<uint32_t, VEC>;
+        auto load_plane = [&](int j, V (&Lm)[NL], B (&Rc)[3]) {
             const uint32_t zo = (uint32_t)j * zstep;
             // under ZU the plane offset is wave-uniform: buffer loads take it as
             // their scalar offset next to the tap's per-lane offset
             const uint32_t zb = ZU ? __builtin_amdgcn_readfirstlane(zo) : 0u;
-            auto lf = [&](const auto &tp) -> V {
-                if constexpr (ZU) return buf_ld<V>(frs, tp.off, zb);
-                else return tp.load(fb, zo);
-            };
             auto ll = [&](const auto &tp) -> V {
                 if constexpr (ZU) return buf_ld<V>(lrs, tp.off, zb);
                 else return tp.load(lb, zo);
             };
-            F[0] = lf(tc);
-            F[1] = lf(xa);
-            F[2] = lf(xb);
-            F[3] = lf(xd);
-            F[4] = lf(xe);
             Lm[0] = ll(mc);
             Lm[1] = ll(mxb);
             Lm[2] = ll(mxd);
             Lm[3] = ll(mxe);
             if constexpr (DIM == 2) {
-                F[5] = lf(ya);
-                F[6] = lf(yb);
-                F[7] = lf(yd);
-                F[8] = lf(ye);
                 Lm[4] = ll(myb);
                 Lm[5] = ll(myd);
                 Lm[6] = ll(mye);
+            }
+            const uint32_t zi = (uint32_t)j * (uint32_t)g.npl;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                Rc[0][e] = rc[zi + e];
+                Rc[1][e] = rx[zi + e];
+                Rc[2][e] = DIM == 2 ? (uint32_t)ry[zi + e] : 0u;
             }
         };
         int jz = z0 + zr;
         if (jz >= z1) continue;
         const int zlast = z1 - 1 - ((z1 - 1 - jz) % A.zr);  // last plane of this lane's residue
-        V F[NF], Lm[NL];
-        load_plane(jz, F, Lm);
+        V Lm[NL];
+        B R[3];
+        load_plane(jz, Lm, R);
         for (; jz < z1; jz += A.zr) {
-            V Fn[NF], Ln[NL];
-            load_plane(min(jz + A.zr, zlast), Fn, Ln);
+            V Ln[NL];
+            B Rn[3];
+            load_plane(min(jz + A.zr, zlast), Ln, Rn);
             const uint32_t zo = (uint32_t)jz * zstep;
             const double vzd = vnode(g, 2, jz);
             const real vz = (real)vzd;
-            // relaxed f at a tap: z-table pair from the role rows (ZU) or the tap's entry
-            const real *row = tzl + jz * (NROLE * 2);
-            auto rl = [&](const Tap<real, VEC> &t, int role, V h) -> V {
-                if constexpr (ZU) return t.relax_ab(h, row[2 * role], row[2 * role + 1]);
-                else return t.relax(h, jz);
-            };
-            const V u0 = rl(tc, 0, F[0]);
             const V m0 = mc.value(Lm[0], vz);
             V r = m0;
             {
-                const V um2 = rl(xa, 1, F[1]), um1 = rl(xb, 2, F[2]);
-                const V u1 = rl(xd, 3, F[3]), u2 = rl(xe, 4, F[4]);
                 const V mm1 = mxb.value(Lm[1], vz), m1 = mxd.value(Lm[2], vz);
                 const V m2 = mxe.value(Lm[3], vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],
-                                                    Cx[e], kx[e]);
+                    r[e] += direction_adjoint<real>(R[0][e] & 3u, (R[0][e] >> 2) & 3u, (R[1][e] >> 2) & 3u, mm1[e],
+                                                    m0[e], m1[e], m2[e], Cx[e], kx[e]);
                 if (emx) {
-                    const real *E = sp + (bx + 1) * g.pe;
+                    const real *E = sp + sx * g.pe;
                     const double nw = (double)E[1];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        const int b0 = mm_branch<real>(u1[e] - u0[e], u0[e] - um1[e]);
+                        const bool b0b = ((R[0][e] >> 2) & 3u) == 2u;
                         const double C = (double)Cx[e];
-                        const double gam = C * (double)m0[e] + C * (double)kx[e] * (b0 == 2) * ((double)m0[e] - (double)m1[e]);
+                        const double gam = C * (double)m0[e] + C * (double)kx[e] * b0b * ((double)m0[e] - (double)m1[e]);
                         const double phiw = (double)E[g.tx1 + jx0 + e] * (double)E[g.ty1 + jy] *
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double vx = vnode(g, 0, jx0 + e);
@@ -513,23 +447,21 @@ __global__ void __launch_bounds__(256)
                 }
             }
             if constexpr (DIM == 2) {
-                const V um2 = rl(ya, 5, F[5]), um1 = rl(yb, 6, F[6]);
-                const V u1 = rl(yd, 7, F[7]), u2 = rl(ye, 8, F[8]);
                 const V mm1 = myb.value(Lm[4], vz), m1 = myd.value(Lm[5], vz);
                 const V m2 = mye.value(Lm[6], vz);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    r[e] += direction_adjoint<real>(um2[e], um1[e], u0[e], u1[e], u2[e], mm1[e], m0[e], m1[e], m2[e],
-                                                    Cy[e], ky[e]);
+                    r[e] += direction_adjoint<real>((R[0][e] >> 4) & 3u, (R[0][e] >> 6) & 3u, (R[2][e] >> 6) & 3u,
+                                                    mm1[e], m0[e], m1[e], m2[e], Cy[e], ky[e]);
                 if (emy) {
-                    const real *E = sp + (by + 1) * g.pe;
+                    const real *E = sp + (2 + sy) * g.pe;
                     const double nw = (double)E[1];
                     const double uw = wy == 3 ? I.uw : 0.0;
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        const int b0 = mm_branch<real>(u1[e] - u0[e], u0[e] - um1[e]);
+                        const bool b0b = ((R[0][e] >> 6) & 3u) == 2u;
                         const double C = (double)Cy[e];
-                        const double gam = C * (double)m0[e] + C * (double)ky[e] * (b0 == 2) * ((double)m0[e] - (double)m1[e]);
+                        const double gam = C * (double)m0[e] + C * (double)ky[e] * b0b * ((double)m0[e] - (double)m1[e]);
                         const double phiw = (double)E[g.tx1 + jx0 + e] * (double)E[g.ty1 + jy] *
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double ux = vnode(g, 0, jx0 + e) - uw;
@@ -541,12 +473,12 @@ __global__ void __launch_bounds__(256)
             }
             *reinterpret_cast<V *>(reinterpret_cast<char *>(ob) + out0 + zo + (uint32_t)(p0 * sizeof(real))) = r;
 #pragma unroll
-            for (int t = 0; t < NF; ++t) F[t] = Fn[t];
-#pragma unroll
             for (int t = 0; t < NL; ++t) Lm[t] = Ln[t];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) R[t] = Rn[t];
         }
     }
-    if (wl || wr || wb || wt) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);
+    if (wall) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);
 }
 
 // Per (instance, wall): D = sum_em (v.n) Phi_W and D' = dD/dT_w over the

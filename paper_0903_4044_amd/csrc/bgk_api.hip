@@ -77,10 +77,10 @@ struct bgk_ctx {
     double *mom = nullptr;     // ncells * 5 (bgk_check)
     // reverse sweep (allocated at the first bgk_step_adjoint / bgk_lid_shear call)
     bool adj_ready = false;
-    bool adjoint_fits = true;  // reverse-sweep tables fit the device's LDS
     bool mixed = false;        // instances of different dimensions
     int lds_max = 65536;       // device LDS per workgroup (bytes)
     void *adj_h = nullptr, *adj_hb = nullptr;                     // during a reverse step: h = S(R_a f), abar
+    void *adj_rec = nullptr;                                      // and the branch record of h's streaming pass
                                                                   // (the two halves of the caller's workspace)
     double *info_f = nullptr, *info_h = nullptr;                  // ncells * NINFO
     double *adj_sums = nullptr, *adj_wsum = nullptr;              // ncells * vsplit_max * (NSUM, NWALL)
@@ -142,6 +142,7 @@ static Args make_args(const bgk_ctx *c)
     a.nparts = c->vsplit;
     a.ntiles = c->row_ntiles;
     a.pass = c->pass;
+    a.rec = nullptr;
     a.g = c->geo;
     return a;
 }
@@ -505,7 +506,6 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
             lds_max = 65536;
         const size_t entry = (size_t)g.pe * c->esize, slack = 4096;
         const size_t fwd = (size_t)(1 + 6 * c->dim) * entry + slack + stream_acc_bytes(g, c->dim, 256);
-        const size_t adj = (c->dim == 2 ? 17 : 9) * entry + slack;
         c->lds_max = lds_max;
         if (fwd > (size_t)lds_max) {
             char b[160];
@@ -514,7 +514,6 @@ static int plan_ctx(const bgk_problem *probs, int n_probs, int precision, bgk_ct
             msg = b;
             return BGK_E_UNSUPPORTED;
         }
-        c->adjoint_fits = adj <= (size_t)lds_max;
     }
 
     c->h_cell_prefix.push_back(0);
@@ -644,6 +643,14 @@ extern "C" const char *bgk_last_error(const bgk_ctx *ctx)
     return ctx ? ctx->err.c_str() : g_init_error.c_str();
 }
 
+// Reverse-step workspace: h = S(R_a f_n), the streamed adjoint (f-sized
+// each) and the branch record of h's streaming pass (one byte per element,
+// rounded up to 256 bytes).
+static size_t adjoint_ws_bytes(const bgk_ctx *c)
+{
+    return 2 * c->f_elems * c->esize + ((c->f_elems + 255) & ~(size_t)255);
+}
+
 extern "C" int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells, size_t *ws_step_bytes,
                          size_t *ws_adjoint_bytes)
 {
@@ -651,8 +658,8 @@ extern "C" int bgk_sizes(const bgk_ctx *ctx, size_t *f_elems, size_t *n_cells, s
     const size_t fb = ctx->f_elems * ctx->esize;
     if (f_elems) *f_elems = ctx->f_elems;
     if (n_cells) *n_cells = (size_t)ctx->ncells;
-    if (ws_step_bytes) *ws_step_bytes = fb;          // the ping-pong buffer of bgk_step
-    if (ws_adjoint_bytes) *ws_adjoint_bytes = 2 * fb;  // h = S(R_a f_n) and the streamed adjoint
+    if (ws_step_bytes) *ws_step_bytes = fb;  // the ping-pong buffer of bgk_step
+    if (ws_adjoint_bytes) *ws_adjoint_bytes = adjoint_ws_bytes(ctx);
     return BGK_OK;
 }
 
@@ -742,19 +749,19 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
 // LDS of the role-ordered z-tables of the one-residue kernels:
 // [sign combination][jz][tap role][2] values; roles: 7 (2D) or 4 for the
 // streaming kernel, 9 or 5 for the reverse sweep's gather kernel.
-static size_t role_table_bytes(const bgk_ctx *c, bool adjoint)
+static size_t role_table_bytes(const bgk_ctx *c)
 {
     const int combos = c->dim >= 2 ? 4 : 2;
-    const int roles = adjoint ? (c->dim == 2 ? 9 : 5) : 1 + 3 * c->dim;
+    const int roles = 1 + 3 * c->dim;
     return (size_t)combos * c->geo.nvz * roles * 2 * c->esize;
 }
 
 // The one-residue form needs every lane of a wave on one plane (zr = 1) and
 // its role tables to fit in LDS next to the slot entries (and, for the
 // streaming kernel, the moment sums).
-static bool use_roles(const bgk_ctx *c, int zr, size_t lds, bool adjoint, int block = 0)
+static bool use_roles(const bgk_ctx *c, int zr, size_t lds, int block)
 {
-    return zr == 1 && lds + role_table_bytes(c, adjoint) + (adjoint ? 0 : stream_acc_bytes(c->geo, c->dim, block)) + 4096 <=
+    return zr == 1 && lds + role_table_bytes(c) + stream_acc_bytes(c->geo, c->dim, block) + 4096 <=
                           (size_t)c->lds_max;
 }
 
@@ -772,9 +779,9 @@ static void stream_kernel_z(bgk_ctx *c, int nb, size_t lds, const void *src, voi
 {
     const real *p = (const real *)params_buf<real>(c, c->pass_parity);
     const size_t acc = stream_acc_bytes(c->geo, DIM, c->sblock);
-    if (use_roles(c, c->zr, lds, false, c->sblock))  // one plane per wave: role-ordered z-tables after the slots
+    if (use_roles(c, c->zr, lds, c->sblock))  // one plane per wave: role-ordered z-tables after the slots
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, PD, NTS, true>), dim3(nb), dim3(c->sblock),
-                           lds + role_table_bytes(c, false) + acc, s, make_args(c), (const real *)src, (real *)dst,
+                           lds + role_table_bytes(c) + acc, s, make_args(c), (const real *)src, (real *)dst,
                            p, c->partial);
     else
         hipLaunchKernelGGL((k_stream<real, DIM, VEC, UNR, 1, NTS, false>), dim3(nb), dim3(c->sblock), lds + acc, s,
@@ -1062,36 +1069,53 @@ static int relax_info(bgk_ctx *c, double *info, int which, hipStream_t s)
     return BGK_OK;
 }
 
+// The recording form of the step's first streaming pass (h = S(R_a f) with
+// the opening tables of parity 0): the plain pass plus one branch byte per
+// element into rec.  One jx per lane task, two planes per pipeline stage,
+// plain stores, whatever the context's tuned shape.
 template <typename real, int DIM>
-static void adj_stream_dispatch(bgk_ctx *c, const void *f, const void *lam, hipStream_t s)
+static int launch_stream_rec(bgk_ctx *c, const void *src, void *dst, unsigned char *rec, hipStream_t s)
+{
+    Args a = make_args(c);
+    a.rec = rec;
+    int block = 256;
+    task_shape(c->geo, 1, c->geo.nvz / c->vsplit, &a.zr, &block);
+    const int nb = c->ncells * c->vsplit;
+    const size_t lds = (size_t)(1 + 6 * DIM) * c->geo.pe * sizeof(real);
+    const size_t acc = stream_acc_bytes(c->geo, DIM, block);
+    const real *p = (const real *)params_buf<real>(c, 0);
+    if (use_roles(c, a.zr, lds, block))
+        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, false, true, true>), dim3(nb), dim3(block),
+                           lds + role_table_bytes(c) + acc, s, a, (const real *)src, (real *)dst, p, c->partial);
+    else
+        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, false, false, true>), dim3(nb), dim3(block), lds + acc, s, a,
+                           (const real *)src, (real *)dst, p, c->partial);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+template <typename real, int DIM>
+static void adj_stream_dispatch(bgk_ctx *c, const unsigned char *rec, const void *lam, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
-    const size_t lds = (size_t)(DIM == 1 ? 9 : 17) * c->geo.pe * sizeof(real);
+    const size_t lds = (size_t)(2 * DIM) * c->geo.pe * sizeof(real);  // the emitted ghosts' entries
     const real *p0 = params_buf<real>(c, 0);
-    const real *fr = (const real *)f, *lr = (const real *)lam;
+    const real *lr = (const real *)lam;
     real *o = (real *)c->adj_hb;
-    // its own lane-task shape (measured on the 64^2 cavity: one jx per lane
-    // task for float, two for double where the grid allows)
+    // its own lane-task shape: two jx per lane task for double where the grid allows
     const int vec = (sizeof(real) == 8 && vec_valid(c, 2)) ? 2 : 1;
     Args a = make_args(c);
     int block = 256;
     task_shape(c->geo, vec, c->geo.nvz / c->vsplit, &a.zr, &block);
-    // (measured on the 64^2 cavity: the role form helps float, not double)
-    if (sizeof(real) == 4 && use_roles(c, a.zr, lds, true)) {
-        const size_t l = lds + role_table_bytes(c, true);
-        if (vec == 2)
-            hipLaunchKernelGGL((k_adj_stream<real, DIM, 2, true>), dim3(nb), dim3(block), l, s, a, fr, p0, lr,
-                               c->adj_coef, o, c->adj_wsum);
-        else
-            hipLaunchKernelGGL((k_adj_stream<real, DIM, 1, true>), dim3(nb), dim3(block), l, s, a, fr, p0, lr,
-                               c->adj_coef, o, c->adj_wsum);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(block), lds, s, a, rec, p0, lr, c->adj_coef, o, c->adj_wsum);
+    };
+    if (a.zr == 1) {
+        if (vec == 2) go(k_adj_stream<real, DIM, 2, true>);
+        else go(k_adj_stream<real, DIM, 1, true>);
     } else {
-        if (vec == 2)
-            hipLaunchKernelGGL((k_adj_stream<real, DIM, 2, false>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr,
-                               c->adj_coef, o, c->adj_wsum);
-        else
-            hipLaunchKernelGGL((k_adj_stream<real, DIM, 1, false>), dim3(nb), dim3(block), lds, s, a, fr, p0, lr,
-                               c->adj_coef, o, c->adj_wsum);
+        if (vec == 2) go(k_adj_stream<real, DIM, 2, false>);
+        else go(k_adj_stream<real, DIM, 1, false>);
     }
 }
 
@@ -1110,15 +1134,13 @@ static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam
     TRY(relax_info<real>(c, c->info_f, 0, s));
     TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
     c->pass_parity = 0;
-    const bool timing = c->timing;
-    c->timing = false;
-    int rc = launch_stream<real>(c, f, c->adj_h, s);
-    c->timing = timing;
-    TRY(rc);
+    unsigned char *rec = (unsigned char *)c->adj_rec;
+    if (c->dim == 1) TRY((launch_stream_rec<real, 1>(c, f, c->adj_h, rec, s)));
+    else TRY((launch_stream_rec<real, 2>(c, f, c->adj_h, rec, s)));
     TRY(relax_info<real>(c, c->info_h, 1, s));
     TRY(relax_coef<real>(c, c->adj_h, lam_next, c->info_h, s));
-    if (c->dim == 1) adj_stream_dispatch<real, 1>(c, f, lam_next, s);
-    else adj_stream_dispatch<real, 2>(c, f, lam_next, s);
+    if (c->dim == 1) adj_stream_dispatch<real, 1>(c, rec, lam_next, s);
+    else adj_stream_dispatch<real, 2>(c, rec, lam_next, s);
     HIP_TRY(c, hipGetLastError());
     if (c->n_wall_cells > 0) {
         const real *p0 = params_buf<real>(c, 0);
@@ -1154,12 +1176,10 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     if (lam_n == f_n || lam_n == lam_next) return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: lam_n must not alias inputs");
     const size_t fb = ctx->f_elems * ctx->esize;
     for (const void *q : {f_n, lam_next, (const void *)lam_n})
-        if (overlaps(ws, 2 * fb, q, fb))
+        if (overlaps(ws, adjoint_ws_bytes(ctx), q, fb))
             return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: the workspace must not overlap f_n, lam_next or lam_n");
     if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: one- and two-dimensional kinds only");
     if (ctx->mixed) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: instances of one dimension only");
-    if (!ctx->adjoint_fits)
-        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: velocity grid too large for the reverse sweep's LDS tables");
     if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
     if (ctx->conservative)
         return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of the effective Maxwellian parameters");
@@ -1168,9 +1188,10 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     hipStream_t s = (hipStream_t)stream;
     ctx->adj_h = ws;
     ctx->adj_hb = (char *)ws + fb;
+    ctx->adj_rec = (char *)ws + 2 * fb;
     const int rc = ctx->precision == BGK_FP64 ? do_adjoint<double>(ctx, f_n, lam_next, lam_n, grad_params, s)
                                               : do_adjoint<float>(ctx, f_n, lam_next, lam_n, grad_params, s);
-    ctx->adj_h = ctx->adj_hb = nullptr;
+    ctx->adj_h = ctx->adj_hb = ctx->adj_rec = nullptr;
     return rc;
 }
 

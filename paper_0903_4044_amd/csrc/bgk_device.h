@@ -90,6 +90,7 @@ struct Args {
     int nparts;                 // partial moment sums per cell that consumers add up
     int ntiles;                 // row-tile translation streaming: tiles over all instances
     uint32_t *pass;             // rounding counter: advanced once per streaming pass
+    unsigned char *rec;         // branch record of a recording streaming pass (else unused)
     Geo g;
 };
 
@@ -258,6 +259,17 @@ __device__ __forceinline__ float round_stochastic(double x, uint32_t r)
     return (float)__longlong_as_double((long long)b);
 }
 __device__ __forceinline__ double minmod3(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
+
+// Branch of a limited slope minmod(a, b), read off the limiter's own value
+// m = median(a, b, 0): 0 when m = 0 (the differences disagree in sign or one
+// is zero), 2 when m equals b (b the smaller magnitude, ties included), else
+// 1 (a).  The reverse sweep differentiates the slope on this branch.
+template <typename real>
+__device__ __forceinline__ uint32_t mm_code(real a, real b)
+{
+    const real m = minmod3(a, b);
+    return m == (real)0 ? 0u : (m == b ? 2u : 1u);
+}
 
 // Deterministic block reduction of NQ doubles; thread q < NQ writes out[q].
 template <int N>
@@ -1113,11 +1125,12 @@ __device__ __forceinline__ vec_t<real, VEC> flux_diff(vec_t<real, VEC> um2, vec_
 template <typename real>
 __host__ __device__ constexpr size_t stream_acc_offset(size_t elems) { return (elems * sizeof(real) + 7) & ~(size_t)7; }
 
-template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU>
+template <typename real, int DIM, int VEC, int UNR, int PD, bool NTSTORE, bool ZU, bool REC = false>
 __global__ void __launch_bounds__(256)
     k_stream(Args A, const real *__restrict__ src, real *__restrict__ dst, const real *__restrict__ params,
              double *__restrict__ partial)
 {
+    static_assert(!REC || DIM <= 2, "branch records of one- and two-dimensional kinds");
     using V = vec_t<real, VEC>;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NSLOT = 1 + 6 * DIM;
@@ -1297,12 +1310,34 @@ __global__ void __launch_bounds__(256)
                 }
             }
             const V u0 = tc.relax_ab(hv[0], ta[0], tb[0]);
-            V dx = flux_diff<real, VEC>(xa.relax_ab(hv[1], ta[1], tb[1]), xb.relax_ab(hv[2], ta[2], tb[2]), u0,
-                                        xd.relax_ab(hv[3], ta[3], tb[3]), Cx, kx);
+            const V xm2 = xa.relax_ab(hv[1], ta[1], tb[1]), xm1 = xb.relax_ab(hv[2], ta[2], tb[2]);
+            const V xp1 = xd.relax_ab(hv[3], ta[3], tb[3]);
+            V dx = flux_diff<real, VEC>(xm2, xm1, u0, xp1, Cx, kx);
             V dy = 0;
-            if constexpr (DIM >= 2)
-                dy = flux_diff<real, VEC>(ya.relax_ab(hv[4], ta[4], tb[4]), yb.relax_ab(hv[5], ta[5], tb[5]), u0,
-                                          yd.relax_ab(hv[6], ta[6], tb[6]), Cy, ky);
+            V ym2 = 0, ym1 = 0, yp1 = 0;
+            if constexpr (DIM >= 2) {
+                ym2 = ya.relax_ab(hv[4], ta[4], tb[4]);
+                ym1 = yb.relax_ab(hv[5], ta[5], tb[5]);
+                yp1 = yd.relax_ab(hv[6], ta[6], tb[6]);
+                dy = flux_diff<real, VEC>(ym2, ym1, u0, yp1, Cy, ky);
+            }
+            if constexpr (REC) {
+                // branch record for the reverse sweep, one byte per element:
+                // per direction (x in bits 0-3, y in bits 4-7) the branch of
+                // the slope at the upwind neighbour (low two bits) and at the
+                // element itself (high two), from the limiter arguments above
+                unsigned char *rp = A.rec + I.f0 + ecell + (uint32_t)p0 + zo / (uint32_t)sizeof(real);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const real dx0 = u0[e] - xm1[e];
+                    uint32_t code = mm_code<real>(dx0, xm1[e] - xm2[e]) | mm_code<real>(xp1[e] - u0[e], dx0) << 2;
+                    if constexpr (DIM >= 2) {
+                        const real dy0 = u0[e] - ym1[e];
+                        code |= (mm_code<real>(dy0, ym1[e] - ym2[e]) | mm_code<real>(yp1[e] - u0[e], dy0) << 2) << 4;
+                    }
+                    rp[e] = (unsigned char)code;
+                }
+            }
             if constexpr (DIM == 3) {
                 // the plane's Courant number along z (v_z of the plane from LDS)
                 const real cz = (real)(fabs(vzt[2 * jz]) * I.cz);

@@ -8,7 +8,12 @@ values must equal the ones the Context was built with.
 The backward pass recomputes states from checkpoints: the forward pass keeps
 f every `every` steps, and the backward pass re-runs each segment forward
 (storing its states) before sweeping back through it, so memory is
-(nsteps / every + every) states instead of nsteps.
+(nsteps / every + every) states instead of nsteps.  With every = None the
+interval is picked from the free device memory: 1 (every state kept, no
+recomputation) when the whole trajectory fits the budget, which on a
+288 GB device is the common case (200 states of a 64^2 x 24^3 cavity take
+45 GB in FP32), else the smallest interval whose checkpoints and one
+recomputed segment fit.
 
 The recomputed states are the forward pass's own, bit for bit.  A call of n
 steps keeps the relaxations between its streaming passes fused and
@@ -20,6 +25,8 @@ recomputes a segment and restores the caller's seed at the end.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
 from .binding import Context
@@ -29,6 +36,23 @@ def _check_param(value: torch.Tensor, expected: float, name: str):
     v = float(value.detach().reshape(-1)[0])
     if abs(v - expected) > 1e-12 * max(1.0, abs(expected)):
         raise ValueError(f"{name}={v} differs from the Context's {expected}; build a Context for it")
+
+
+def auto_every(f0: torch.Tensor, nsteps: int, fraction: float = 0.5, free_bytes: int | None = None) -> int:
+    """Checkpoint interval for a rollout of nsteps steps from f0: the smallest
+    `every` whose ceil(nsteps / every) stored states plus the `every` states
+    of one recomputed segment (every = 1: the nsteps + 1 states of the whole
+    trajectory) fit in `fraction` of the device's free memory (free_bytes
+    overrides the query); ceil(sqrt(nsteps)) if none does."""
+    state = f0.numel() * f0.element_size()
+    if free_bytes is None:
+        free_bytes = torch.cuda.mem_get_info(f0.device)[0]
+    budget = fraction * free_bytes
+    for every in range(1, nsteps + 1):
+        held = nsteps + 1 if every == 1 else -(-nsteps // every) + every
+        if held * state <= budget:
+            return every
+    return max(1, math.isqrt(nsteps - 1) + 1)
 
 
 def forward_checkpoints(solver: Context, f0: torch.Tensor, nsteps: int, every: int):
@@ -61,10 +85,13 @@ class Rollout(torch.autograd.Function):
     """f_N = step^nsteps(f_0) for a single-instance Context."""
 
     @staticmethod
-    def forward(ctx, f0, kn, tw, solver: Context, nsteps: int, every: int):
+    def forward(ctx, f0, kn, tw, solver: Context, nsteps: int, every: int | None):
         p = solver.problems[0]
         _check_param(kn, p["kn"], "kn")
         _check_param(tw, p.get("t_wall", 1.0), "t_wall")
+        if every is None:
+            every = auto_every(f0, nsteps)
+        solver.last_checkpoint_every = every
         f, checkpoints, seeds = forward_checkpoints(solver, f0.detach().contiguous(), nsteps, every)
         ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
         ctx.checkpoints, ctx.seeds = checkpoints, seeds
@@ -83,6 +110,7 @@ class Rollout(torch.autograd.Function):
         for seg in range(len(ctx.checkpoints) - 1, -1, -1):
             k = min(every, nsteps - seg * every)
             states = recompute_segment(solver, ctx.checkpoints[seg], ctx.seeds[seg], k)
+            ctx.checkpoints[seg] = None  # held by `states` until the segment is swept
             for i in range(k - 1, -1, -1):
                 solver.step_adjoint(states[i], lam, other, grad)
                 lam, other = other, lam
@@ -112,7 +140,9 @@ class LidShear(torch.autograd.Function):
         return lam * s.to(lam.dtype), (grad[0, 1] * s).reshape(ctx.tw_shape).to(ctx.tw_device), None
 
 
-def rollout(f0, kn, tw, solver: Context, nsteps: int, every: int = 20):
+def rollout(f0, kn, tw, solver: Context, nsteps: int, every: int | None = None):
+    """f_N of nsteps steps from f0, differentiable in f0, kn and tw; every:
+    checkpoint interval (None: picked by auto_every from the free memory)."""
     return Rollout.apply(f0, kn, tw, solver, nsteps, every)
 
 

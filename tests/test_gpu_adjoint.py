@@ -112,6 +112,65 @@ def test_rollout_autograd_matches_oracle(B, oracle_mod):
     assert float(tw.grad) == pytest.approx(gtw, rel=1e-11)
 
 
+@pytest.mark.parametrize("kind", ["shock", "cavity"])
+def test_branch_record_fully_written(B, kind):
+    """The recording streaming pass of a reverse step writes a branch byte for
+    every element over the workspace's 0xFF poison: each 2-bit code is 0, 1
+    or 2, and a one-dimensional kind leaves the y half zero."""
+    cfg = small(kind)
+    C = B.Context(cfg, "fp64")
+    f = C.initial_state()
+    xi = dev(inputs.noise((C.f_elems,), seed=43), C.dtype)
+    f = f * (1 + 0.05 * xi)
+    lam = dev(inputs.noise((C.f_elems,), seed=44), C.dtype)
+    C.step_adjoint(f, lam)
+    torch.cuda.synchronize()
+    fb = C.f_elems * 8
+    rec = C.workspace("adjoint")[2 * fb:2 * fb + C.f_elems].to(torch.int32)
+    for shift in (0, 2, 4, 6):
+        assert int(((rec >> shift) & 3).max()) <= 2, shift
+    if kind == "shock":
+        assert int((rec >> 4).max()) == 0
+    # the limiter takes each branch somewhere on a perturbed state
+    for code in (0, 1, 2):
+        assert bool(((rec & 3) == code).any()), code
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_rollout_keeping_every_state_equals_checkpointed(B, prec):
+    """every = None keeps every state when the trajectory fits the free
+    memory (no recomputation).  The trajectory is the checkpointed rollout's
+    bit for bit, and so are the FP64 gradients.  In FP32 a reverse step
+    rounds its recomputed intermediate h stochastically with bits keyed by
+    the context's rounding counter, which the recomputation of the
+    checkpointed rollout advances differently, so there the gradients agree
+    to rounding (1e-5)."""
+    from paper_0903_4044_amd import solver
+    cfg = small("cavity", nx=6, ny=5, kn=0.1, lid_mach=0.1, t_wall=1.0)
+    C = B.Context(cfg, prec)
+    f0 = C.initial_state()
+    xi = dev(inputs.noise((C.f_elems,), seed=41), C.dtype)
+    f0 = f0 * (1 + 1e-3 * xi)
+    out = []
+    for every in (3, None):
+        C.set_seed(77)
+        x = f0.clone().requires_grad_(True)
+        kn = torch.tensor(cfg["kn"], dtype=torch.float64, requires_grad=True)
+        tw = torch.tensor(cfg["t_wall"], dtype=torch.float64, requires_grad=True)
+        L = solver.lid_shear(solver.rollout(x, kn, tw, C, 8, every=every), tw, C)
+        L.backward()
+        out.append((C.last_checkpoint_every, float(L.detach()), x.grad.clone(), float(kn.grad), float(tw.grad)))
+    (e3, L3, g3, k3, t3), (e1, L1, g1, k1, t1) = out
+    assert e3 == 3 and e1 == 1
+    assert L1 == L3
+    if prec == "fp64":
+        assert k1 == k3 and t1 == t3
+        assert torch.equal(g1, g3)
+    else:
+        assert k1 == pytest.approx(k3, rel=1e-5) and t1 == pytest.approx(t3, rel=1e-5)
+        assert float((g1 - g3).abs().max()) <= 1e-5 * float(g3.abs().max())
+
+
 def _loss(B, cfg, prec, f0, nsteps):
     C = B.Context(cfg, prec)
     return float(C.lid_shear(C.step(f0, n=nsteps))[0])

@@ -415,14 +415,14 @@ def test_graph_replay_matches_eager(B):
 
 
 def test_workspace_is_the_callers(B):
-    """bgk_sizes reports the workspaces (one f for bgk_step, two for the
-    reverse sweep); bgk_step needs one for n >= 2 and rejects one that
-    overlaps f_in or f_out; the output matches a run with the binding's own
-    workspace."""
+    """bgk_sizes reports the workspaces (one f for bgk_step; two and a byte
+    per element, rounded up to 256, for the reverse sweep); bgk_step needs
+    one for n >= 2 and rejects one that overlaps f_in or f_out; the output
+    matches a run with the binding's own workspace."""
     cfg = small("cavity", nx=5, ny=4, nv=(12, 12, 8))
     C = B.Context(cfg, "fp32")
     fb = C.f_elems * 4
-    assert C.ws_step_bytes == fb and C.ws_adjoint_bytes == 2 * fb
+    assert C.ws_step_bytes == fb and C.ws_adjoint_bytes == 2 * fb + (C.f_elems + 255) // 256 * 256
     L = B.load()
     s = torch.cuda.current_stream().cuda_stream
     x = C.initial_state()
