@@ -10,7 +10,8 @@
 // wall).  Relaxation, Eq. (relaxation) of Sec. 2.1, is y = (1 - E) Phi + E x
 // with E = exp(-nu tau), so its transpose is E mu plus a velocity polynomial
 // 1, v, |v|^2 per cell whose coefficients come from six sums of mu against
-// Phi and x (k_adj_sums, then k_adj_coef; k_adj_apply applies them).  The
+// Phi and x (k_adj_sums, then k_adj_coef; k_adj_apply applies them; with
+// one chunk per cell k_adj_close does all three in one pass per cell).  The
 // minmod streaming step is transposed on the branches the forward step takes
 // (k_adj_stream, gather form): the step's own streaming pass h = S(a), run in
 // its recording form, stores each element's limiter branches, and the gather
@@ -121,16 +122,10 @@ __global__ void __launch_bounds__(256) k_adj_sums(Args A, const real *__restrict
 // The relaxation's dL/dKn goes to gk[cell].  One thread per cell.
 constexpr int NCOEF = 8;
 
-__global__ void k_adj_coef(Args A, const double *__restrict__ info, const double *__restrict__ sums,
-                           double *__restrict__ coef, double *__restrict__ gk)
+// Coefficients of one cell from its six sums s and relaxation data in:
+// o = (G0, G1, G2, G3, G4, E, 0, 0); returns the relaxation's dL/dKn.
+__device__ __forceinline__ double cell_coef(const Inst &I, const double *in, const double (&s)[NSUM], double *o)
 {
-    const int gc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gc >= A.ncells) return;
-    const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gc)];
-    const double *in = info + (long long)gc * NINFO;
-    double s[NSUM] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < A.vsplit; ++k)
-        for (int q = 0; q < NSUM; ++q) s[q] += sums[((long long)gc * A.vsplit + k) * NSUM + q];
     const double n = in[0], T = in[4], nu = in[5], E = in[6], tau = in[7];
     const double V[3] = {in[1], in[2], in[3]};
     // adjoints of n, V, T (dPhi/dn = Phi/n, dPhi/dV = 2 Phi (v - V)/T,
@@ -142,7 +137,6 @@ __global__ void k_adj_coef(Args A, const double *__restrict__ info, const double
     // chain to the raw sums M0 = n, M1 = n V, M2 = n (|V|^2 + 3T/2)
     const double V2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
     double G0 = Gn + GT * (2.0 / 3.0) * (V2 - 1.5 * T) / n;
-    double *o = coef + (long long)gc * NCOEF;
     for (int a = 0; a < 3; ++a) {
         G0 -= GV[a] * V[a] / n;
         o[1 + a] = GV[a] / n - GT * (4.0 / 3.0) * V[a] / n;
@@ -152,7 +146,19 @@ __global__ void k_adj_coef(Args A, const double *__restrict__ info, const double
     o[5] = E;
     o[6] = 0.0;
     o[7] = 0.0;
-    gk[gc] += tau * E * nu / I.kn * s[5];  // dE/dKn = tau E nu / Kn
+    return tau * E * nu / I.kn * s[5];  // dE/dKn = tau E nu / Kn
+}
+
+__global__ void k_adj_coef(Args A, const double *__restrict__ info, const double *__restrict__ sums,
+                           double *__restrict__ coef, double *__restrict__ gk)
+{
+    const int gc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gc >= A.ncells) return;
+    const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gc)];
+    double s[NSUM] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < A.vsplit; ++k)
+        for (int q = 0; q < NSUM; ++q) s[q] += sums[((long long)gc * A.vsplit + k) * NSUM + q];
+    gk[gc] += cell_coef(I, info + (long long)gc * NINFO, s, coef + (long long)gc * NCOEF);
 }
 
 // out = R^T mu with the cell coefficients of k_adj_coef.
@@ -177,6 +183,70 @@ __global__ void __launch_bounds__(256) k_adj_apply(Args A, const real *__restric
         const double base = G0 + G1 * vx + G2 * vy + G4 * (vx * vx + vy * vy);
 #pragma unroll 4
         for (int jz = z0; jz < z1; ++jz) {
+            const int i = jz * g.npl + p;
+            const double vz = vnode(g, 2, jz);
+            oc[i] = (real)(E * (double)mc[i] + dV * (base + G3 * vz + G4 * vz * vz));
+        }
+    }
+}
+
+// The last part of a reverse step in one pass per cell (one workgroup per
+// cell, all its velocities): the six sums of mu against the Maxwellian of x
+// and x itself, the cell's coefficients (dL/dKn into gk), and
+// out = R^T mu with them; the second read of mu hits the cache.  The same
+// arithmetic as k_adj_sums, k_adj_coef and k_adj_apply with one chunk per
+// cell, so the same bits.
+template <typename real>
+__global__ void __launch_bounds__(256) k_adj_close(Args A, const real *__restrict__ x, const real *__restrict__ mu,
+                                                   const double *__restrict__ info, double *__restrict__ gk,
+                                                   real *__restrict__ out)
+{
+    __shared__ PhiTab T;
+    __shared__ double sums[NSUM], G[NCOEF];
+    const Geo &g = A.g;
+    const int gc = xcd_remap(blockIdx.x, gridDim.x);
+    const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gc)];
+    const double *in = info + (long long)gc * NINFO;
+    build_phi(g, in, T);
+    const long long off = I.f0 + (long long)(gc - I.cell0) * g.nv;
+    double acc[NSUM] = {0, 0, 0, 0, 0, 0};
+    for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
+        const int jx = p % g.nvx, jy = p / g.nvx;
+        const double cx = vnode(g, 0, jx) - in[1], cy = vnode(g, 1, jy) - in[2];
+        const double pxy = T.P * T.e[0][jx] * T.e[1][jy];
+#pragma unroll 4
+        for (int jz = 0; jz < g.nvz; ++jz) {
+            const long long i = off + (long long)jz * g.npl + p;
+            const double m = (double)mu[i], xv = (double)x[i];
+            const double cz = vnode(g, 2, jz) - in[3];
+            const double phi = pxy * T.e[2][jz];
+            const double w = m * phi;
+            acc[0] += w;
+            acc[1] += w * cx;
+            acc[2] += w * cy;
+            acc[3] += w * cz;
+            acc[4] += w * (cx * cx + cy * cy + cz * cz);
+            acc[5] += m * (xv - phi);
+        }
+    }
+    block_sum_store<NSUM>(acc, sums);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[NSUM];
+        for (int q = 0; q < NSUM; ++q) s[q] = 0.0 + sums[q];
+        gk[gc] += cell_coef(I, in, s, G);
+    }
+    __syncthreads();
+    const double G0 = G[0], G1 = G[1], G2 = G[2], G3 = G[3], G4 = G[4], E = G[5];
+    const real *mc = mu + off;
+    real *oc = out + off;
+    const double dV = g.dV;
+    for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
+        const int jx = p % g.nvx, jy = p / g.nvx;
+        const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
+        const double base = G0 + G1 * vx + G2 * vy + G4 * (vx * vx + vy * vy);
+#pragma unroll 4
+        for (int jz = 0; jz < g.nvz; ++jz) {
             const int i = jz * g.npl + p;
             const double vz = vnode(g, 2, jz);
             oc[i] = (real)(E * (double)mc[i] + dV * (base + G3 * vz + G4 * vz * vz));

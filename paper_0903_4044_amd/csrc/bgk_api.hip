@@ -1071,8 +1071,22 @@ static int relax_info(bgk_ctx *c, double *info, int which, hipStream_t s)
 
 // The recording form of the step's first streaming pass (h = S(R_a f) with
 // the opening tables of parity 0): the plain pass plus one branch byte per
-// element into rec.  One jx per lane task, two planes per pipeline stage,
-// plain stores, whatever the context's tuned shape.
+// element into rec.  One jx per lane task and two planes per pipeline stage
+// whatever the context's tuned shape; stores as the plain pass's.
+template <typename real, int DIM, bool NTS>
+static void stream_rec_kernel(bgk_ctx *c, const Args &a, int nb, int block, size_t lds, const void *src, void *dst,
+                              hipStream_t s)
+{
+    const size_t acc = stream_acc_bytes(c->geo, DIM, block);
+    const real *p = (const real *)params_buf<real>(c, 0);
+    if (use_roles(c, a.zr, lds, block))
+        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, NTS, true, true>), dim3(nb), dim3(block),
+                           lds + role_table_bytes(c) + acc, s, a, (const real *)src, (real *)dst, p, c->partial);
+    else
+        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, NTS, false, true>), dim3(nb), dim3(block), lds + acc, s, a,
+                           (const real *)src, (real *)dst, p, c->partial);
+}
+
 template <typename real, int DIM>
 static int launch_stream_rec(bgk_ctx *c, const void *src, void *dst, unsigned char *rec, hipStream_t s)
 {
@@ -1082,14 +1096,8 @@ static int launch_stream_rec(bgk_ctx *c, const void *src, void *dst, unsigned ch
     task_shape(c->geo, 1, c->geo.nvz / c->vsplit, &a.zr, &block);
     const int nb = c->ncells * c->vsplit;
     const size_t lds = (size_t)(1 + 6 * DIM) * c->geo.pe * sizeof(real);
-    const size_t acc = stream_acc_bytes(c->geo, DIM, block);
-    const real *p = (const real *)params_buf<real>(c, 0);
-    if (use_roles(c, a.zr, lds, block))
-        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, false, true, true>), dim3(nb), dim3(block),
-                           lds + role_table_bytes(c) + acc, s, a, (const real *)src, (real *)dst, p, c->partial);
-    else
-        hipLaunchKernelGGL((k_stream<real, DIM, 1, 2, 1, false, false, true>), dim3(nb), dim3(block), lds + acc, s, a,
-                           (const real *)src, (real *)dst, p, c->partial);
+    if (stream_nt(c)) stream_rec_kernel<real, DIM, true>(c, a, nb, block, lds, src, dst, s);
+    else stream_rec_kernel<real, DIM, false>(c, a, nb, block, lds, src, dst, s);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -1150,11 +1158,18 @@ static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam
                            c->adj_dw, c->adj_wsum, (real *)c->adj_hb, c->gt);
         HIP_TRY(c, hipGetLastError());
     }
-    TRY(relax_coef<real>(c, f, c->adj_hb, c->info_f, s));
-    const int nb = c->ncells * c->vsplit;
-    hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)c->adj_hb,
-                       c->adj_coef, (real *)lam_n);
-    HIP_TRY(c, hipGetLastError());
+    if (c->vsplit == 1) {
+        // one workgroup per cell: sums, coefficients and lambda^n in one pass
+        hipLaunchKernelGGL(k_adj_close<real>, dim3(c->ncells), dim3(256), 0, s, make_args(c), (const real *)f,
+                           (const real *)c->adj_hb, c->info_f, c->gk, (real *)lam_n);
+        HIP_TRY(c, hipGetLastError());
+    } else {
+        TRY(relax_coef<real>(c, f, c->adj_hb, c->info_f, s));
+        const int nb = c->ncells * c->vsplit;
+        hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)c->adj_hb,
+                           c->adj_coef, (real *)lam_n);
+        HIP_TRY(c, hipGetLastError());
+    }
     hipLaunchKernelGGL(k_grad_reduce, dim3(c->ninst), dim3(256), 0, s, make_args(c), c->gk, c->gt, grad);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
