@@ -208,14 +208,13 @@ def run_workload(binding, torch, problems, precision, steps, warmup, kernel_timi
     return t1 - t0, ms / max(launches, 1), points, shape
 
 
-def run_adjoint(binding, torch, cfg, precision, every=None):
-    """Differentiated rollout of the adjoint workload: forward with checkpoints
-    every `every` steps (None: the interval the solver picks from the free
-    device memory, 1 when the whole trajectory fits), then the reverse sweep
-    (segment recomputation where every > 1, one bgk_step_adjoint per step)
-    down to dL/df0, dL/dKn and dL/dT_w.  Returns (forward s, backward s,
-    points, steps, gradient errors against the stored FP64 oracle sweep or
-    None, the checkpoint interval used)."""
+def run_adjoint(binding, torch, cfg, precision, every=None, mode="auto"):
+    """Differentiated rollout of the adjoint workload: forward keeping step
+    records (mode "record"; "auto" takes them when they fit the free device
+    memory) or checkpoints every `every` steps, then the reverse sweep down to
+    dL/df0, dL/dKn and dL/dT_w.  Returns (forward s, backward s, points,
+    steps, gradient errors against the stored FP64 oracle sweep or None, the
+    rollout plan used)."""
     import numpy as np
 
     from paper_0903_4044_amd import inputs, solver
@@ -227,12 +226,13 @@ def run_adjoint(binding, torch, cfg, precision, every=None):
     ctx.autotune(f0)
 
     def once(n):
+        ctx.set_seed(0)  # the warm-up and the timed rollout take the same trajectory
         x = f0.clone().requires_grad_(True)
         kn = torch.tensor(cfg["kn"], dtype=torch.float64, requires_grad=True)
         tw = torch.tensor(cfg["t_wall"], dtype=torch.float64, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        L = solver.lid_shear(solver.rollout(x, kn, tw, ctx, n, every=every), tw, ctx)
+        L = solver.lid_shear(solver.rollout(x, kn, tw, ctx, n, every=every, mode=mode), tw, ctx)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         L.backward()
@@ -242,9 +242,9 @@ def run_adjoint(binding, torch, cfg, precision, every=None):
             raise RuntimeError("non-finite gradient in the adjoint run")
         return t1 - t0, t2 - t1, float(L.detach()), float(kn.grad), float(tw.grad)
 
-    once(20)  # warm-up
+    once(nsteps)  # warm-up: the same rollout, so that its buffers come from torch's cache when timed
     fwd, bwd, L, gkn, gtw = once(nsteps)
-    used = ctx.last_checkpoint_every
+    used = ctx.last_rollout
     err = None
     path = os.path.join(GOLDEN, "cavity_64_adjoint_oracle.npz")
     if os.path.exists(path):
@@ -517,12 +517,13 @@ def main():
         for p in ("fp32", "fp64"):
             if wanted and f"adjoint_cavity_64_{p}" not in wanted:
                 continue
-            fwd, bwd, pts, n, gerr, every = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
+            fwd, bwd, pts, n, gerr, plan = run_adjoint(binding, torch, inputs.config("cavity_64_adjoint"), p)
             e = {"updates_per_s": pts * n / (fwd + bwd), "steps": n, "points": pts, "precision": p,
                  "forward_s": fwd, "reverse_s": bwd, "reverse_updates_per_s": pts * n / bwd,
-                 "checkpoint_every": every,
-                 "note": "updates/s counts each of the rollout's steps once over forward + reverse sweep "
-                         "(checkpoint_every 1: every state kept in HBM, no recomputation)"}
+                 "rollout": plan,
+                 "note": "updates/s counts each of the rollout's steps once over forward + reverse sweep; "
+                         "rollout mode record: every state and step record kept in HBM, nothing recomputed; "
+                         "checkpoint: states every k steps, one streaming pass recomputed per reverse step"}
             if gerr:
                 e["error_vs_oracle"] = gerr
             extras[f"adjoint_cavity_64_{p}"] = e

@@ -315,6 +315,34 @@ int bgk_get_rounding_seed(const bgk_ctx *ctx, unsigned int *seed);
 int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
                      void *ws, void *stream);
 
+/* Step records: a forward step that keeps what its reverse step needs, so
+ * that the reverse step recomputes nothing (the adjoint of one step of
+ * Eq. (relaxation) and the streaming of Sec. 2.1, as bgk_step_adjoint).
+ * A record holds h = S(R_a f_n) as the step stored it, the per-cell totals
+ * of the FP64 moment sums of f_n and of h, and the minmod branch of every
+ * limited slope the streaming pass evaluated (one byte per element); its
+ * size, bgk_record_bytes, is about one f plus a quarter (FP32) or an
+ * eighth (FP64) of one, and a record stays valid for any later launch
+ * shape of the context.
+ *
+ * bgk_step_record: f_out = one step of f_in (as bgk_step with n_steps = 1:
+ * the same rounding counter use and the same trajectory up to the rounding
+ * of the moment sums, whose order can follow the launch shape), and the
+ * step's record into rec (device, bgk_record_bytes, overwritten).  f_in,
+ * f_out and rec must not overlap (BGK_E_ALIAS); NULL gives BGK_E_INVALID;
+ * BGK_E_UNSUPPORTED for the contexts bgk_step_adjoint rejects.
+ *
+ * bgk_step_adjoint_record: the reverse step of bgk_step_adjoint at f_n,
+ * reading the record rec that bgk_step_record wrote for the step from f_n
+ * instead of recomputing it; same outputs, accumulation of grad_params and
+ * errors.  ws: the caller's workspace of ws_adjoint_bytes, of which the
+ * first f-sized part is used; ws and lam_n must not overlap f_n, rec,
+ * lam_next or each other (BGK_E_ALIAS).  Asynchronous on `stream`. */
+int bgk_record_bytes(const bgk_ctx *ctx, size_t *bytes);
+int bgk_step_record(bgk_ctx *ctx, const void *f_in, void *f_out, void *rec, void *stream);
+int bgk_step_adjoint_record(bgk_ctx *ctx, const void *f_n, const void *rec, const void *lam_next, void *lam_n,
+                            double *grad_params, void *ws, void *stream);
+
 /* Shear stress on the moving lid (Sec. 5.1 cavity; the xy momentum flux
  * through the top wall, integrated along it):
  *   L_k = dx * dV * sum_{top cells} [ sum_{v_y>0} v_x v_y f

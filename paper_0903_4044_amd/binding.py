@@ -53,7 +53,8 @@ EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_
            "bgk_initial_state", "bgk_step", "bgk_moments", "bgk_check", "bgk_set_timing",
            "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph",
            "bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad", "bgk_set_rounding_seed",
-           "bgk_get_rounding_seed", "bgk_cavity_metrics", "bgk_step_noalloc")
+           "bgk_get_rounding_seed", "bgk_cavity_metrics", "bgk_step_noalloc", "bgk_record_bytes",
+           "bgk_step_record", "bgk_step_adjoint_record")
 
 TUNED_PATH = os.path.join(HERE, "tuned.json")
 
@@ -93,6 +94,9 @@ def load(path: str = LIB_PATH):
     L.bgk_lid_shear_grad.argtypes = [vp, vp, vp, vp, vp]
     L.bgk_cavity_metrics.argtypes = [vp, vp, dp, vp]
     L.bgk_step_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp]
+    L.bgk_record_bytes.argtypes = [vp, sz]
+    L.bgk_step_record.argtypes = [vp, vp, vp, vp, vp]
+    L.bgk_step_adjoint_record.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -200,6 +204,9 @@ class Context:
         self._check(self.L.bgk_sizes(self.h, ctypes.byref(fe), ctypes.byref(nc), ctypes.byref(ws), ctypes.byref(wa)))
         self.f_elems, self.ncells = fe.value, nc.value
         self.ws_step_bytes, self.ws_adjoint_bytes = ws.value, wa.value
+        rb = ctypes.c_size_t()
+        self._check(self.L.bgk_record_bytes(self.h, ctypes.byref(rb)))
+        self.record_bytes = rb.value
         self._ws = {}  # caller-owned workspaces (torch), made at first use
         self.nvel = inputs.nvel(self.problems[0])
         self.offsets, self.cell_offsets, self.dts = [], [], []
@@ -286,6 +293,26 @@ class Context:
         grad = self.grad_buffer(f_n.device) if grad is None else grad
         self._check(self.L.bgk_step_adjoint(self.h, _ptr(f_n), _ptr(lam_next), _ptr(lam_n), _ptr(grad),
                                             _ptr(self.workspace("adjoint", f_n.device)), _stream_handle(stream)))
+        return lam_n, grad
+
+    def step_record(self, f_in: torch.Tensor, f_out: torch.Tensor | None = None, rec: torch.Tensor | None = None,
+                    stream=None):
+        """One step f_out = step(f_in) that keeps its record (a byte tensor of
+        record_bytes) for step_adjoint_record.  Returns (f_out, rec)."""
+        f_out = torch.empty_like(f_in) if f_out is None else f_out
+        rec = torch.empty(self.record_bytes, dtype=torch.uint8, device=f_in.device) if rec is None else rec
+        self._check(self.L.bgk_step_record(self.h, _ptr(f_in), _ptr(f_out), _ptr(rec), _stream_handle(stream)))
+        return f_out, rec
+
+    def step_adjoint_record(self, f_n: torch.Tensor, rec: torch.Tensor, lam_next: torch.Tensor,
+                            lam_n: torch.Tensor | None = None, grad: torch.Tensor | None = None, stream=None):
+        """step_adjoint at f_n from the record step_record kept for the step
+        from f_n (nothing recomputed).  Returns (lam_n, grad)."""
+        lam_n = torch.empty_like(lam_next) if lam_n is None else lam_n
+        grad = self.grad_buffer(f_n.device) if grad is None else grad
+        self._check(self.L.bgk_step_adjoint_record(self.h, _ptr(f_n), _ptr(rec), _ptr(lam_next), _ptr(lam_n),
+                                                   _ptr(grad), _ptr(self.workspace("adjoint", f_n.device)),
+                                                   _stream_handle(stream)))
         return lam_n, grad
 
     def lid_shear(self, f: torch.Tensor, stream=None) -> torch.Tensor:

@@ -551,6 +551,32 @@ __global__ void __launch_bounds__(256)
     if (wall) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);
 }
 
+// Per-cell totals of the partial moment sums (the step record keeps them
+// independent of the chunk count): tot[c][q] = sum over the nparts slots in
+// slot order, as the table preparation adds them.  One thread per (cell, q).
+__global__ void k_part_totals(Args A, const double *__restrict__ partial, double *__restrict__ tot)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)A.ncells * NQ) return;
+    const long long c = t / NQ;
+    const int q = (int)(t - c * NQ);
+    double v = 0.0;
+    for (int k = 0; k < A.nparts; ++k) v += partial[(c * A.nparts + k) * NQ + q];
+    tot[t] = v;
+}
+
+// The inverse for the current chunk count: slot 0 holds the total, the
+// others zero (so every consumer's slot sum is the total again, exactly).
+__global__ void k_part_restore(Args A, const double *__restrict__ tot, double *__restrict__ partial)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)A.ncells * A.nparts * NQ) return;
+    const long long slot = t / NQ;
+    const int q = (int)(t - slot * NQ);
+    const long long c = slot / A.nparts;
+    partial[t] = slot - c * A.nparts == 0 ? tot[c * NQ + q] : 0.0;
+}
+
 // Per (instance, wall): D = sum_em (v.n) Phi_W and D' = dD/dT_w over the
 // emitted velocities, Phi_W the unit-density wall Maxwellian of the wall's
 // first table entry.  One workgroup per (instance, wall); 0 for non-cavities.

@@ -1127,28 +1127,18 @@ static void adj_stream_dispatch(bgk_ctx *c, const unsigned char *rec, const void
     }
 }
 
-// One reverse step.  The first streaming pass of the step is recomputed
-// (h = S(R_a f) with the opening tables in parity buffer 0, which stay valid
-// for the rest of the call), then
-//   abar = S^T(R_b^T lambda^{n+1})   (k_adj_stream, k_adj_wall),
-//   lambda^n = R_a^T(abar)           (k_adj_sums, k_adj_coef, k_adj_apply).
+// The reverse step once its forward data are in place -- the relaxation
+// data of f and h (info_f, info_h), the opening tables in parity buffer 0,
+// h = S(R_a f) and the branch record of that streaming pass:
+//   abar = S^T(R_b^T lambda^{n+1})   (k_adj_sums/coef at h, k_adj_stream, k_adj_wall),
+//   lambda^n = R_a^T(abar)           (k_adj_close, or k_adj_sums, k_adj_coef, k_adj_apply).
 template <typename real>
-static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam_n, double *grad, hipStream_t s)
+static int adjoint_tail(bgk_ctx *c, const void *f, const void *h, const unsigned char *br, const void *lam_next,
+                        void *lam_n, double *grad, hipStream_t s)
 {
-    TRY(ensure_adjoint(c));
-    TRY(fill(c, c->gk, c->ncells, 0.0, s));
-    TRY(fill(c, c->gt, c->ncells, 0.0, s));
-    TRY(launch_moments<real>(c, f, s));
-    TRY(relax_info<real>(c, c->info_f, 0, s));
-    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
-    c->pass_parity = 0;
-    unsigned char *rec = (unsigned char *)c->adj_rec;
-    if (c->dim == 1) TRY((launch_stream_rec<real, 1>(c, f, c->adj_h, rec, s)));
-    else TRY((launch_stream_rec<real, 2>(c, f, c->adj_h, rec, s)));
-    TRY(relax_info<real>(c, c->info_h, 1, s));
-    TRY(relax_coef<real>(c, c->adj_h, lam_next, c->info_h, s));
-    if (c->dim == 1) adj_stream_dispatch<real, 1>(c, rec, lam_next, s);
-    else adj_stream_dispatch<real, 2>(c, rec, lam_next, s);
+    TRY(relax_coef<real>(c, h, lam_next, c->info_h, s));
+    if (c->dim == 1) adj_stream_dispatch<real, 1>(c, br, lam_next, s);
+    else adj_stream_dispatch<real, 2>(c, br, lam_next, s);
     HIP_TRY(c, hipGetLastError());
     if (c->n_wall_cells > 0) {
         const real *p0 = params_buf<real>(c, 0);
@@ -1175,11 +1165,165 @@ static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam
     return BGK_OK;
 }
 
+// One reverse step from f^n alone: the step's first streaming pass is
+// recomputed in its recording form into the workspace.
+template <typename real>
+static int do_adjoint(bgk_ctx *c, const void *f, const void *lam_next, void *lam_n, double *grad, hipStream_t s)
+{
+    TRY(ensure_adjoint(c));
+    TRY(fill(c, c->gk, c->ncells, 0.0, s));
+    TRY(fill(c, c->gt, c->ncells, 0.0, s));
+    TRY(launch_moments<real>(c, f, s));
+    TRY(relax_info<real>(c, c->info_f, 0, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    c->pass_parity = 0;
+    unsigned char *br = (unsigned char *)c->adj_rec;
+    if (c->dim == 1) TRY((launch_stream_rec<real, 1>(c, f, c->adj_h, br, s)));
+    else TRY((launch_stream_rec<real, 2>(c, f, c->adj_h, br, s)));
+    TRY(relax_info<real>(c, c->info_h, 1, s));
+    return adjoint_tail<real>(c, f, c->adj_h, br, lam_next, lam_n, grad, s);
+}
+
+// Step record (bgk_step_record): h = S(R_a f_n) as the step stored it, the
+// per-cell totals of the moment sums of f_n and of h, and the branch record
+// of the streaming pass; each part 256-byte aligned.
+struct RecordLayout {
+    size_t h, tot_f, tot_h, br, bytes;
+};
+
+static RecordLayout record_layout(const bgk_ctx *c)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    RecordLayout r;
+    r.h = 0;
+    r.tot_f = up(c->f_elems * c->esize);
+    r.tot_h = r.tot_f + up(sizeof(double) * (size_t)c->ncells * NQ);
+    r.br = r.tot_h + up(sizeof(double) * (size_t)c->ncells * NQ);
+    r.bytes = r.br + up(c->f_elems);
+    return r;
+}
+
+static int part_totals(bgk_ctx *c, double *tot, hipStream_t s)
+{
+    const long long n = (long long)c->ncells * NQ;
+    hipLaunchKernelGGL(k_part_totals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, make_args(c), c->partial, tot);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+static int part_restore(bgk_ctx *c, const double *tot, hipStream_t s)
+{
+    const long long n = (long long)c->ncells * c->vsplit * NQ;
+    hipLaunchKernelGGL(k_part_restore, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, make_args(c), tot,
+                       c->partial);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
+// One step that keeps its record: the launch sequence of a one-step
+// bgk_step with the streaming pass in its recording form writing h into the
+// record, and the closing relaxation reading it from there.
+template <typename real>
+static int do_step_record(bgk_ctx *c, const void *f_in, void *f_out, char *rec, hipStream_t s)
+{
+    const RecordLayout L = record_layout(c);
+    hipLaunchKernelGGL(k_set_pass, dim3(1), dim3(64), 0, s, c->pass, c->seed);
+    HIP_TRY(c, hipGetLastError());
+    c->seed += 1u;
+    TRY(launch_moments<real>(c, f_in, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    TRY(part_totals(c, (double *)(rec + L.tot_f), s));
+    c->pass_parity = 0;
+    unsigned char *br = (unsigned char *)(rec + L.br);
+    if (c->dim == 1) TRY((launch_stream_rec<real, 1>(c, f_in, rec + L.h, br, s)));
+    else TRY((launch_stream_rec<real, 2>(c, f_in, rec + L.h, br, s)));
+    TRY(part_totals(c, (double *)(rec + L.tot_h), s));
+    TRY(launch_prep<real>(c, MODE_FINAL, c->vsplit, 1, s));
+    return launch_final<real>(c, rec + L.h, f_out, 1, s);
+}
+
+// One reverse step from f^n and its step record: nothing is recomputed.
+template <typename real>
+static int do_adjoint_record(bgk_ctx *c, const void *f, const char *rec, const void *lam_next, void *lam_n,
+                             double *grad, hipStream_t s)
+{
+    const RecordLayout L = record_layout(c);
+    TRY(ensure_adjoint(c));
+    TRY(fill(c, c->gk, c->ncells, 0.0, s));
+    TRY(fill(c, c->gt, c->ncells, 0.0, s));
+    TRY(part_restore(c, (const double *)(rec + L.tot_f), s));
+    TRY(relax_info<real>(c, c->info_f, 0, s));
+    TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+    TRY(part_restore(c, (const double *)(rec + L.tot_h), s));
+    TRY(relax_info<real>(c, c->info_h, 1, s));
+    return adjoint_tail<real>(c, f, rec + L.h, (const unsigned char *)(rec + L.br), lam_next, lam_n, grad, s);
+}
+
 // Does [a, a + na) overlap [b, b + nb)?
 static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
 {
     const char *x = (const char *)a, *y = (const char *)b;
     return x < y + nb && y < x + na;
+}
+
+// Contexts with a reverse sweep: one- and two-dimensional kinds of one
+// dimension, the per-cell streaming, the point-value Maxwellian, the full
+// velocity space.
+static int adjoint_kinds(bgk_ctx *ctx, const char *who)
+{
+    const std::string w(who);
+    if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, w + ": one- and two-dimensional kinds only");
+    if (ctx->mixed) return fail(ctx, BGK_E_UNSUPPORTED, w + ": instances of one dimension only");
+    if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, w + ": no reverse sweep of shift streaming");
+    if (ctx->conservative)
+        return fail(ctx, BGK_E_UNSUPPORTED, w + ": no reverse sweep of the effective Maxwellian parameters");
+    if (ctx->geo.red) return fail(ctx, BGK_E_UNSUPPORTED, w + ": no reverse sweep in the reduced velocity space");
+    return BGK_OK;
+}
+
+extern "C" int bgk_record_bytes(const bgk_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return BGK_E_INVALID;
+    *bytes = record_layout(ctx).bytes;
+    return BGK_OK;
+}
+
+extern "C" int bgk_step_record(bgk_ctx *ctx, const void *f_in, void *f_out, void *rec, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f_in || !f_out || !rec) return fail(ctx, BGK_E_INVALID, "bgk_step_record: NULL buffer");
+    const size_t fb = ctx->f_elems * ctx->esize, rb = record_layout(ctx).bytes;
+    if (overlaps(f_in, fb, f_out, fb)) return fail(ctx, BGK_E_ALIAS, "bgk_step_record: f_in and f_out must not overlap");
+    if (overlaps(rec, rb, f_in, fb) || overlaps(rec, rb, f_out, fb))
+        return fail(ctx, BGK_E_ALIAS, "bgk_step_record: the record must not overlap f_in or f_out");
+    TRY(adjoint_kinds(ctx, "bgk_step_record"));
+    hipStream_t s = (hipStream_t)stream;
+    return ctx->precision == BGK_FP64 ? do_step_record<double>(ctx, f_in, f_out, (char *)rec, s)
+                                      : do_step_record<float>(ctx, f_in, f_out, (char *)rec, s);
+}
+
+extern "C" int bgk_step_adjoint_record(bgk_ctx *ctx, const void *f_n, const void *rec, const void *lam_next,
+                                       void *lam_n, double *grad_params, void *ws, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (!f_n || !rec || !lam_next || !lam_n || !grad_params || !ws)
+        return fail(ctx, BGK_E_INVALID, "bgk_step_adjoint_record: NULL buffer");
+    const size_t fb = ctx->f_elems * ctx->esize, rb = record_layout(ctx).bytes;
+    if (overlaps(lam_n, fb, f_n, fb) || overlaps(lam_n, fb, lam_next, fb) || overlaps(lam_n, fb, rec, rb))
+        return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint_record: lam_n must not overlap f_n, rec or lam_next");
+    for (const void *q : {f_n, lam_next, (const void *)lam_n})
+        if (overlaps(ws, fb, q, fb))
+            return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint_record: the workspace must not overlap f_n, lam_next or lam_n");
+    if (overlaps(ws, fb, rec, rb))
+        return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint_record: the workspace must not overlap the record");
+    TRY(adjoint_kinds(ctx, "bgk_step_adjoint_record"));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->adj_hb = ws;
+    const int rc = ctx->precision == BGK_FP64
+                       ? do_adjoint_record<double>(ctx, f_n, (const char *)rec, lam_next, lam_n, grad_params, s)
+                       : do_adjoint_record<float>(ctx, f_n, (const char *)rec, lam_next, lam_n, grad_params, s);
+    ctx->adj_hb = nullptr;
+    return rc;
 }
 
 extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *lam_n, double *grad_params,
@@ -1193,13 +1337,7 @@ extern "C" int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_n
     for (const void *q : {f_n, lam_next, (const void *)lam_n})
         if (overlaps(ws, adjoint_ws_bytes(ctx), q, fb))
             return fail(ctx, BGK_E_ALIAS, "bgk_step_adjoint: the workspace must not overlap f_n, lam_next or lam_n");
-    if (ctx->dim == 3) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: one- and two-dimensional kinds only");
-    if (ctx->mixed) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: instances of one dimension only");
-    if (ctx->shift) return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of shift streaming");
-    if (ctx->conservative)
-        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep of the effective Maxwellian parameters");
-    if (ctx->geo.red)
-        return fail(ctx, BGK_E_UNSUPPORTED, "bgk_step_adjoint: no reverse sweep in the reduced velocity space");
+    TRY(adjoint_kinds(ctx, "bgk_step_adjoint"));
     hipStream_t s = (hipStream_t)stream;
     ctx->adj_h = ws;
     ctx->adj_hb = (char *)ws + fb;

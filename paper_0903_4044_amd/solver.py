@@ -8,12 +8,17 @@ values must equal the ones the Context was built with.
 The backward pass recomputes states from checkpoints: the forward pass keeps
 f every `every` steps, and the backward pass re-runs each segment forward
 (storing its states) before sweeping back through it, so memory is
-(nsteps / every + every) states instead of nsteps.  With every = None the
-interval is picked from the free device memory: 1 (every state kept, no
-recomputation) when the whole trajectory fits the budget, which on a
-288 GB device is the common case (200 states of a 64^2 x 24^3 cavity take
-45 GB in FP32), else the smallest interval whose checkpoints and one
-recomputed segment fit.
+(nsteps / every + every) states instead of nsteps.
+
+Where memory allows, the rollout instead keeps every state together with
+its step record (bgk_step_record: the step's streamed intermediate, its
+moment sums and its limiter branches), and each reverse step reads the
+record instead of recomputing the forward pass (bgk_step_adjoint_record).
+mode = "auto" takes records when nsteps states and records fit in 70% of
+the free device memory (200 steps of a 64^2 x 24^3 cavity: 102 GB in FP32,
+193 GB in FP64, of a 288 GB device), else checkpoints with the smallest
+interval whose states fit half of it (every = 1 keeps every state and
+recomputes one streaming pass per reverse step).
 
 The recomputed states are the forward pass's own, bit for bit.  A call of n
 steps keeps the relaxations between its streaming passes fused and
@@ -55,6 +60,28 @@ def auto_every(f0: torch.Tensor, nsteps: int, fraction: float = 0.5, free_bytes:
     return max(1, math.isqrt(nsteps - 1) + 1)
 
 
+def auto_mode(f0: torch.Tensor, nsteps: int, record_bytes: int, fraction: float = 0.7,
+              free_bytes: int | None = None) -> str:
+    """"record" when the nsteps states and step records of a rollout from f0
+    fit in `fraction` of the device's free memory, else "checkpoint"."""
+    state = f0.numel() * f0.element_size()
+    if free_bytes is None:
+        free_bytes = torch.cuda.mem_get_info(f0.device)[0]
+    return "record" if (nsteps + 1) * state + nsteps * record_bytes <= fraction * free_bytes else "checkpoint"
+
+
+def forward_records(solver: Context, f0: torch.Tensor, nsteps: int):
+    """Steps f0 forward nsteps times keeping every state and step record;
+    returns (f_N, states f^0 .. f^(N-1), their records)."""
+    states, records = [], []
+    f = f0
+    for _ in range(nsteps):
+        states.append(f)
+        f, rec = solver.step_record(f)
+        records.append(rec)
+    return f, states, records
+
+
 def forward_checkpoints(solver: Context, f0: torch.Tensor, nsteps: int, every: int):
     """Steps f0 forward nsteps times; returns (f_N, the state at the start of
     every segment of `every` steps, the rounding seed at each of them)."""
@@ -85,40 +112,57 @@ class Rollout(torch.autograd.Function):
     """f_N = step^nsteps(f_0) for a single-instance Context."""
 
     @staticmethod
-    def forward(ctx, f0, kn, tw, solver: Context, nsteps: int, every: int | None):
+    def forward(ctx, f0, kn, tw, solver: Context, nsteps: int, every: int | None, mode: str):
         p = solver.problems[0]
         _check_param(kn, p["kn"], "kn")
         _check_param(tw, p.get("t_wall", 1.0), "t_wall")
-        if every is None:
-            every = auto_every(f0, nsteps)
-        solver.last_checkpoint_every = every
-        f, checkpoints, seeds = forward_checkpoints(solver, f0.detach().contiguous(), nsteps, every)
-        ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
-        ctx.checkpoints, ctx.seeds = checkpoints, seeds
+        f0 = f0.detach().contiguous()
+        if mode == "auto":
+            mode = "checkpoint" if every is not None else auto_mode(f0, nsteps, solver.record_bytes)
+        if mode not in ("record", "checkpoint"):
+            raise ValueError(f"mode {mode!r}: auto, record or checkpoint")
+        ctx.solver, ctx.nsteps, ctx.mode = solver, nsteps, mode
         ctx.shapes = (kn.shape, tw.shape)
         ctx.devices = (kn.device, tw.device)
+        if mode == "record":
+            f, ctx.states, ctx.records = forward_records(solver, f0, nsteps)
+            solver.last_rollout = {"mode": "record", "every": 1}
+            return f
+        if every is None:
+            every = auto_every(f0, nsteps)
+        f, checkpoints, seeds = forward_checkpoints(solver, f0, nsteps, every)
+        ctx.every, ctx.checkpoints, ctx.seeds = every, checkpoints, seeds
+        solver.last_rollout = {"mode": "checkpoint", "every": every}
         return f
 
     @staticmethod
     def backward(ctx, lam):
-        solver, every, nsteps = ctx.solver, ctx.every, ctx.nsteps
+        solver, nsteps = ctx.solver, ctx.nsteps
         # own copy: the incoming gradient may be shared with other graph nodes
         lam = lam.to(solver.dtype).contiguous().clone()
         grad = solver.grad_buffer(lam.device)
         other = torch.empty_like(lam)
-        caller_seed = solver.seed()
-        for seg in range(len(ctx.checkpoints) - 1, -1, -1):
-            k = min(every, nsteps - seg * every)
-            states = recompute_segment(solver, ctx.checkpoints[seg], ctx.seeds[seg], k)
-            ctx.checkpoints[seg] = None  # held by `states` until the segment is swept
-            for i in range(k - 1, -1, -1):
-                solver.step_adjoint(states[i], lam, other, grad)
+        if ctx.mode == "record":
+            for i in range(nsteps - 1, -1, -1):
+                solver.step_adjoint_record(ctx.states[i], ctx.records[i], lam, other, grad)
                 lam, other = other, lam
-        solver.set_seed(caller_seed)
-        ctx.checkpoints = ctx.seeds = None
+                ctx.states[i] = ctx.records[i] = None
+            ctx.states = ctx.records = None
+        else:
+            every = ctx.every
+            caller_seed = solver.seed()
+            for seg in range(len(ctx.checkpoints) - 1, -1, -1):
+                k = min(every, nsteps - seg * every)
+                states = recompute_segment(solver, ctx.checkpoints[seg], ctx.seeds[seg], k)
+                ctx.checkpoints[seg] = None  # held by `states` until the segment is swept
+                for i in range(k - 1, -1, -1):
+                    solver.step_adjoint(states[i], lam, other, grad)
+                    lam, other = other, lam
+            solver.set_seed(caller_seed)
+            ctx.checkpoints = ctx.seeds = None
         g = grad[0]
         return (lam, g[0].reshape(ctx.shapes[0]).to(ctx.devices[0]), g[1].reshape(ctx.shapes[1]).to(ctx.devices[1]),
-                None, None, None)
+                None, None, None, None)
 
 
 class LidShear(torch.autograd.Function):
@@ -140,10 +184,12 @@ class LidShear(torch.autograd.Function):
         return lam * s.to(lam.dtype), (grad[0, 1] * s).reshape(ctx.tw_shape).to(ctx.tw_device), None
 
 
-def rollout(f0, kn, tw, solver: Context, nsteps: int, every: int | None = None):
-    """f_N of nsteps steps from f0, differentiable in f0, kn and tw; every:
-    checkpoint interval (None: picked by auto_every from the free memory)."""
-    return Rollout.apply(f0, kn, tw, solver, nsteps, every)
+def rollout(f0, kn, tw, solver: Context, nsteps: int, every: int | None = None, mode: str = "auto"):
+    """f_N of nsteps steps from f0, differentiable in f0, kn and tw.  mode:
+    "record" (every state and step record kept), "checkpoint" (states every
+    `every` steps; None: auto_every's interval) or "auto" (checkpoints if
+    `every` is given, else records when they fit the free memory)."""
+    return Rollout.apply(f0, kn, tw, solver, nsteps, every, mode)
 
 
 def lid_shear(f, tw, solver: Context):

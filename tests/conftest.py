@@ -22,8 +22,9 @@ def oracle_mod():
 
 @pytest.fixture(autouse=True)
 def poisoned_outputs(request, monkeypatch):
-    """In every GPU test, the outputs of bgk_step, bgk_step_adjoint and
-    bgk_moments and the workspaces they use are filled with NaN before the
+    """In every GPU test, the outputs of bgk_step, bgk_step_adjoint,
+    bgk_moments, bgk_step_record and bgk_step_adjoint_record, the records and
+    the workspaces they use are filled with NaN (all-ones bytes) before the
     call, and the call must leave no NaN behind: an element that some launch
     shape never writes cannot pass on a value an earlier call left in the
     same memory (torch's caching allocator reuses blocks)."""
@@ -36,6 +37,7 @@ def poisoned_outputs(request, monkeypatch):
 
     nan = float("nan")
     step, adjoint, moments = binding.Context.step, binding.Context.step_adjoint, binding.Context.moments
+    step_record, adjoint_record = binding.Context.step_record, binding.Context.step_adjoint_record
 
     def no_nan(t, what):
         assert not torch.isnan(t).any(), f"{what}: elements left unwritten (NaN poison survived)"
@@ -58,6 +60,22 @@ def poisoned_outputs(request, monkeypatch):
         no_nan(out[0], "bgk_step_adjoint")
         return out
 
+    def p_step_record(self, f_in, f_out=None, rec=None, stream=None):
+        f_out = torch.full_like(f_in, nan) if f_out is None else f_out.fill_(nan)
+        rec = torch.full((self.record_bytes,), 255, dtype=torch.uint8, device=f_in.device) if rec is None \
+            else rec.fill_(255)
+        out, rec = step_record(self, f_in, f_out, rec, stream)
+        if not torch.isnan(f_in).any():
+            no_nan(out, "bgk_step_record")
+        return out, rec
+
+    def p_adjoint_record(self, f_n, rec, lam_next, lam_n=None, grad=None, stream=None):
+        lam_n = torch.full_like(lam_next, nan) if lam_n is None else lam_n.fill_(nan)
+        self.workspace("adjoint", f_n.device).fill_(255)
+        out = adjoint_record(self, f_n, rec, lam_next, lam_n, grad, stream)
+        no_nan(out[0], "bgk_step_adjoint_record")
+        return out
+
     def p_moments(self, f, out=None, stream=None):
         out = torch.full((self.ncells, 5), nan, dtype=torch.float64, device=f.device) if out is None \
             else out.fill_(nan)
@@ -69,4 +87,6 @@ def poisoned_outputs(request, monkeypatch):
     monkeypatch.setattr(binding.Context, "step", p_step)
     monkeypatch.setattr(binding.Context, "step_adjoint", p_adjoint)
     monkeypatch.setattr(binding.Context, "moments", p_moments)
+    monkeypatch.setattr(binding.Context, "step_record", p_step_record)
+    monkeypatch.setattr(binding.Context, "step_adjoint_record", p_adjoint_record)
     yield
