@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(256)
     real *sp = reinterpret_cast<real *>(smem);  // [2 d + si][entry]: the k = -1 slots' entries
     __shared__ AdjSlots S;
     __shared__ double cf[NSL][NCOEF];
+    __shared__ double vzs[NVMAX];  // v_z of every plane (wave-uniform reads)
     const Geo &g = A.g;
     const int Lq = xcd_remap(blockIdx.x, gridDim.x);
     const int gq = Lq / A.vsplit, split = Lq % A.vsplit;
@@ -358,6 +359,7 @@ __global__ void __launch_bounds__(256)
     const int gc = I.cell0 + c;
     const int L = gc * A.vsplit + split;  // (cell, chunk) index of the wall sums
     const bool per = I.kind == KIND_PER1 || I.kind == KIND_PER2;
+    for (int k = threadIdx.x; k < g.nvz; k += blockDim.x) vzs[k] = vnode(g, 2, k);
     if (threadIdx.x < NSL) {
         const int sl = threadIdx.x;
         int cell = c, par = gc, mc = c;
@@ -480,6 +482,8 @@ __global__ void __launch_bounds__(256)
         int jz = z0 + zr;
         if (jz >= z1) continue;
         const int zlast = z1 - 1 - ((z1 - 1 - jz) % A.zr);  // last plane of this lane's residue
+        // this task's wall sums (its x wall, its y wall), folded into ws per task
+        double ex0 = 0.0, ex1 = 0.0, ey0 = 0.0, ey1 = 0.0;
         V Lm[NL];
         B R[3];
         load_plane(jz, Lm, R);
@@ -488,7 +492,7 @@ __global__ void __launch_bounds__(256)
             B Rn[3];
             load_plane(min(jz + A.zr, zlast), Ln, Rn);
             const uint32_t zo = (uint32_t)jz * zstep;
-            const double vzd = vnode(g, 2, jz);
+            const double vzd = vzs[jz];
             const real vz = (real)vzd;
             const V m0 = mc.value(Lm[0], vz);
             V r = m0;
@@ -511,8 +515,8 @@ __global__ void __launch_bounds__(256)
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double vx = vnode(g, 0, jx0 + e);
                         const double c2 = vx * vx + vy * vy + vzd * vzd;
-                        ws[2 * wx] += gam * phiw;
-                        ws[2 * wx + 1] += gam * phiw * (c2 * itw * itw - 1.5 * itw);
+                        ex0 += gam * phiw;
+                        ex1 += gam * phiw * (c2 * itw * itw - 1.5 * itw);
                     }
                 }
             }
@@ -536,8 +540,8 @@ __global__ void __launch_bounds__(256)
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double ux = vnode(g, 0, jx0 + e) - uw;
                         const double c2 = ux * ux + vy * vy + vzd * vzd;
-                        ws[2 * wy] += gam * phiw;
-                        ws[2 * wy + 1] += gam * phiw * (c2 * itw * itw - 1.5 * itw);
+                        ey0 += gam * phiw;
+                        ey1 += gam * phiw * (c2 * itw * itw - 1.5 * itw);
                     }
                 }
             }
@@ -546,6 +550,18 @@ __global__ void __launch_bounds__(256)
             for (int t = 0; t < NL; ++t) Lm[t] = Ln[t];
 #pragma unroll
             for (int t = 0; t < 3; ++t) R[t] = Rn[t];
+        }
+        if (wall) {
+            // (selects instead of indexing ws by the lane's wall: no dynamic
+            // register indexing)
+            ws[0] += wx == 0 ? ex0 : 0.0;
+            ws[1] += wx == 0 ? ex1 : 0.0;
+            ws[2] += wx == 1 ? ex0 : 0.0;
+            ws[3] += wx == 1 ? ex1 : 0.0;
+            ws[4] += wy == 2 ? ey0 : 0.0;
+            ws[5] += wy == 2 ? ey1 : 0.0;
+            ws[6] += wy == 3 ? ey0 : 0.0;
+            ws[7] += wy == 3 ? ey1 : 0.0;
         }
     }
     if (wall) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);

@@ -38,7 +38,6 @@ struct bgk_ctx {
     size_t f_elems = 0;
     int vsplit = 1;            // jz chunks per cell (one workgroup each)
     int vsplit_max = 1;        // largest vsplit the partial-sum buffer holds
-    int block = 256;           // moments / final / init kernels
     int vec = 1;               // streaming kernel: jx per lane task
     int zr = 1;                // streaming kernel: jz residues per workgroup
     int sblock = 256;          // streaming kernel: threads per workgroup
@@ -416,7 +415,6 @@ static void choose_launch(bgk_ctx *c)
     if (c->shift && c->row_ok && c->row_ntiles * c->geo.nvz >= c->ncu) unroll = 2;
     const int target = c->dim == 1 ? (c->precision == BGK_FP32 ? 1024 : 512) : 2048;
     set_shape(c, vec, unroll, vsplit_for(c, target));
-    c->block = 256;
 }
 
 // Host-side set-up of a context: validation, geometry, instance tables,
@@ -682,6 +680,19 @@ static real *params_buf(bgk_ctx *c, int parity)
 }
 
 // Jx values per lane of the pointwise kernels (16-byte loads where Nvx allows).
+// Threads per workgroup of a kernel whose threads stride over `ntask` tasks
+// of one plane: the multiple of 64 up to 256 that leaves the fewest idle
+// lanes in the last round (the larger on a tie), e.g. 192 for 144 or 576.
+static int fit_block(int ntask)
+{
+    int best = 256, idle = 1 << 30;
+    for (int b = 256; b >= 64; b -= 64) {
+        const int w = (ntask + b - 1) / b * b - ntask;
+        if (w < idle) { best = b; idle = w; }
+    }
+    return best;
+}
+
 static int pointwise_vec(const bgk_ctx *c)
 {
     const int want = c->precision == BGK_FP32 ? 4 : 2;
@@ -689,6 +700,9 @@ static int pointwise_vec(const bgk_ctx *c)
         if (c->geo.nvx % v == 0) return v;
     return 1;
 }
+
+// Workgroup of the moment and closing-relaxation kernels (VEC jx per task).
+static int pointwise_block(const bgk_ctx *c) { return fit_block(c->geo.npl / pointwise_vec(c)); }
 
 // Arguments of the pointwise kernels (moments, initial state, closing
 // relaxation): their own jz chunk count, the streaming one except for the
@@ -708,11 +722,11 @@ static int launch_moments(bgk_ctx *c, const void *f, hipStream_t s)
     const Args a = pointwise_args(c);
     const int nb = c->ncells * a.vsplit;
     if (pointwise_vec(c) == 4)
-        hipLaunchKernelGGL((k_moments<real, 4>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
+        hipLaunchKernelGGL((k_moments<real, 4>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)f, c->partial);
     else if (pointwise_vec(c) == 2)
-        hipLaunchKernelGGL((k_moments<real, 2>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
+        hipLaunchKernelGGL((k_moments<real, 2>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)f, c->partial);
     else
-        hipLaunchKernelGGL((k_moments<real, 1>), dim3(nb), dim3(c->block), 0, s, a, (const real *)f, c->partial);
+        hipLaunchKernelGGL((k_moments<real, 1>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)f, c->partial);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -896,11 +910,11 @@ static int launch_final(bgk_ctx *c, const void *src, void *dst, int parity, hipS
     const int nb = c->ncells * a.vsplit;
     const real *p = (const real *)params_buf<real>(c, parity);
     if (pointwise_vec(c) == 4)
-        hipLaunchKernelGGL((k_final<real, 4>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 4>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)src, (real *)dst, p);
     else if (pointwise_vec(c) == 2)
-        hipLaunchKernelGGL((k_final<real, 2>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 2>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)src, (real *)dst, p);
     else
-        hipLaunchKernelGGL((k_final<real, 1>), dim3(nb), dim3(c->block), 0, s, a, (const real *)src, (real *)dst, p);
+        hipLaunchKernelGGL((k_final<real, 1>), dim3(nb), dim3(pointwise_block(c)), 0, s, a, (const real *)src, (real *)dst, p);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }
@@ -1051,8 +1065,8 @@ template <typename real>
 static int relax_coef(bgk_ctx *c, const void *x, const void *mu, const double *info, hipStream_t s)
 {
     const int nb = c->ncells * c->vsplit;
-    hipLaunchKernelGGL(k_adj_sums<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)x, (const real *)mu,
-                       info, c->adj_sums);
+    hipLaunchKernelGGL(k_adj_sums<real>, dim3(nb), dim3(fit_block(c->geo.npl)), 0, s, make_args(c), (const real *)x,
+                       (const real *)mu, info, c->adj_sums);
     HIP_TRY(c, hipGetLastError());
     hipLaunchKernelGGL(k_adj_coef, dim3((c->ncells + 255) / 256), dim3(256), 0, s, make_args(c), info, c->adj_sums,
                        c->adj_coef, c->gk);
@@ -1150,13 +1164,13 @@ static int adjoint_tail(bgk_ctx *c, const void *f, const void *h, const unsigned
     }
     if (c->vsplit == 1) {
         // one workgroup per cell: sums, coefficients and lambda^n in one pass
-        hipLaunchKernelGGL(k_adj_close<real>, dim3(c->ncells), dim3(256), 0, s, make_args(c), (const real *)f,
+        hipLaunchKernelGGL(k_adj_close<real>, dim3(c->ncells), dim3(fit_block(c->geo.npl)), 0, s, make_args(c), (const real *)f,
                            (const real *)c->adj_hb, c->info_f, c->gk, (real *)lam_n);
         HIP_TRY(c, hipGetLastError());
     } else {
         TRY(relax_coef<real>(c, f, c->adj_hb, c->info_f, s));
         const int nb = c->ncells * c->vsplit;
-        hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(256), 0, s, make_args(c), (const real *)c->adj_hb,
+        hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(fit_block(c->geo.npl)), 0, s, make_args(c), (const real *)c->adj_hb,
                            c->adj_coef, (real *)lam_n);
         HIP_TRY(c, hipGetLastError());
     }
@@ -1623,9 +1637,9 @@ extern "C" int bgk_initial_state(bgk_ctx *ctx, void *f, void *stream)
     const Args a = pointwise_args(ctx);
     const int nb = ctx->ncells * a.vsplit;
     if (ctx->precision == BGK_FP64)
-        hipLaunchKernelGGL(k_init<double>, dim3(nb), dim3(ctx->block), 0, s, a, (double *)f);
+        hipLaunchKernelGGL(k_init<double>, dim3(nb), dim3(fit_block(ctx->geo.npl)), 0, s, a, (double *)f);
     else
-        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(ctx->block), 0, s, a, (float *)f);
+        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(fit_block(ctx->geo.npl)), 0, s, a, (float *)f);
     HIP_TRY(ctx, hipGetLastError());
     return BGK_OK;
 }

@@ -14,7 +14,7 @@ Where memory allows, the rollout instead keeps every state together with
 its step record (bgk_step_record: the step's streamed intermediate, its
 moment sums and its limiter branches), and each reverse step reads the
 record instead of recomputing the forward pass (bgk_step_adjoint_record).
-mode = "auto" takes records when nsteps states and records fit in 70% of
+mode = "auto" takes records when nsteps states and records fit in 60% of
 the free device memory (200 steps of a 64^2 x 24^3 cavity: 102 GB in FP32,
 193 GB in FP64, of a 288 GB device), else checkpoints with the smallest
 interval whose states fit half of it (every = 1 keeps every state and
@@ -51,7 +51,7 @@ def auto_every(f0: torch.Tensor, nsteps: int, fraction: float = 0.5, free_bytes:
     overrides the query); ceil(sqrt(nsteps)) if none does."""
     state = f0.numel() * f0.element_size()
     if free_bytes is None:
-        free_bytes = torch.cuda.mem_get_info(f0.device)[0]
+        free_bytes = _free_bytes(f0.device)
     budget = fraction * free_bytes
     for every in range(1, nsteps + 1):
         held = nsteps + 1 if every == 1 else -(-nsteps // every) + every
@@ -60,13 +60,19 @@ def auto_every(f0: torch.Tensor, nsteps: int, fraction: float = 0.5, free_bytes:
     return max(1, math.isqrt(nsteps - 1) + 1)
 
 
-def auto_mode(f0: torch.Tensor, nsteps: int, record_bytes: int, fraction: float = 0.7,
+def _free_bytes(device) -> int:
+    """Free device memory plus what torch's caching allocator holds unused."""
+    free = torch.cuda.mem_get_info(device)[0]
+    return free + torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
+
+
+def auto_mode(f0: torch.Tensor, nsteps: int, record_bytes: int, fraction: float = 0.6,
               free_bytes: int | None = None) -> str:
     """"record" when the nsteps states and step records of a rollout from f0
     fit in `fraction` of the device's free memory, else "checkpoint"."""
     state = f0.numel() * f0.element_size()
     if free_bytes is None:
-        free_bytes = torch.cuda.mem_get_info(f0.device)[0]
+        free_bytes = _free_bytes(f0.device)
     return "record" if (nsteps + 1) * state + nsteps * record_bytes <= fraction * free_bytes else "checkpoint"
 
 
