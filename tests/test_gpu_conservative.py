@@ -48,8 +48,6 @@ GRIDS = {
 @pytest.mark.parametrize("kind", ["shock", "cavity", "periodic2d"])
 @pytest.mark.parametrize("splitting,limiter", [("strang", "minmod"), ("lie", "none")])
 def test_conservative_matches_oracle_fp64(B, oracle_mod, grid, kind, splitting, limiter):
-    if grid == "w64" and kind != "shock":
-        pytest.skip("the 64-lane segment is covered on the 1D case (oracle time)")
     cfg = small(kind, splitting=splitting, limiter=limiter, **GRIDS[grid])
     O = oracle_mod.Oracle(cfg)
     f0 = perturbed(O, 91)
