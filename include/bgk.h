@@ -57,7 +57,7 @@ extern "C" {
 #define BGK_OK 0
 #define BGK_E_INVALID 1     /* bad argument (NULL, size, kind, non-positive parameter) */
 #define BGK_E_CFL 2         /* Courant sum above 2/3: positivity not guaranteed */
-#define BGK_E_UNSUPPORTED 3 /* valid but outside what this build handles */
+#define BGK_E_UNSUPPORTED 3 /* valid but outside what the library handles */
 #define BGK_E_HIP 4         /* a HIP runtime call failed */
 #define BGK_E_NONFINITE 5   /* bgk_check: a moment is NaN or infinite */
 #define BGK_E_NEGATIVE 6    /* bgk_check: a density or temperature is <= 0 */
