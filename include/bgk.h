@@ -338,6 +338,20 @@ int bgk_step_adjoint(bgk_ctx *ctx, const void *f_n, const void *lam_next, void *
  * errors.  ws: the caller's workspace of ws_adjoint_bytes, of which the
  * first f-sized part is used; ws and lam_n must not overlap f_n, rec,
  * lam_next or each other (BGK_E_ALIAS).  Asynchronous on `stream`. */
+/* bgk_adjoint_sweep_record: the reverse sweep of n >= 0 recorded steps in
+ * one call: lambda^0 = J_0^T ... J_{n-1}^T lambda^n, with f[i] the state at
+ * the start of step i and rec[i] its record (host arrays of n device
+ * pointers, i = 0 .. n-1), lam_N = lambda^n, lam_0 the output; grad_params
+ * accumulates every step's parameter gradients, as n calls of
+ * bgk_step_adjoint_record would (same lambda^0; the gradient sums in another
+ * order).  Steps run from the last to the first, and each step's closing
+ * pass also forms the sums at h of the step before it, so the sweep reads
+ * lambda one time fewer per step.  ws: ws_adjoint_bytes, of which the first
+ * two f-sized parts are used; lam_0 and ws must not overlap lam_N, a state,
+ * a record or each other (BGK_E_ALIAS).  Errors as bgk_step_adjoint.
+ * Asynchronous on `stream`. */
+int bgk_adjoint_sweep_record(bgk_ctx *ctx, int n, const void *const *f, const void *const *rec, const void *lam_N,
+                             void *lam_0, double *grad_params, void *ws, void *stream);
 int bgk_record_bytes(const bgk_ctx *ctx, size_t *bytes);
 int bgk_step_record(bgk_ctx *ctx, const void *f_in, void *f_out, void *rec, void *stream);
 int bgk_step_adjoint_record(bgk_ctx *ctx, const void *f_n, const void *rec, const void *lam_next, void *lam_n,

@@ -54,7 +54,7 @@ EXPORTS = ("bgk_init", "bgk_free", "bgk_last_error", "bgk_sizes", "bgk_instance_
            "bgk_timing", "bgk_autotune", "bgk_get_launch", "bgk_set_launch", "bgk_set_graph",
            "bgk_step_adjoint", "bgk_lid_shear", "bgk_lid_shear_grad", "bgk_set_rounding_seed",
            "bgk_get_rounding_seed", "bgk_cavity_metrics", "bgk_step_noalloc", "bgk_record_bytes",
-           "bgk_step_record", "bgk_step_adjoint_record")
+           "bgk_step_record", "bgk_step_adjoint_record", "bgk_adjoint_sweep_record")
 
 TUNED_PATH = os.path.join(HERE, "tuned.json")
 
@@ -97,6 +97,8 @@ def load(path: str = LIB_PATH):
     L.bgk_record_bytes.argtypes = [vp, sz]
     L.bgk_step_record.argtypes = [vp, vp, vp, vp, vp]
     L.bgk_step_adjoint_record.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.bgk_adjoint_sweep_record.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp, vp,
+                                           vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
     L.bgk_last_error.restype = ctypes.c_char_p
@@ -314,6 +316,22 @@ class Context:
                                                    _ptr(grad), _ptr(self.workspace("adjoint", f_n.device)),
                                                    _stream_handle(stream)))
         return lam_n, grad
+
+    def adjoint_sweep_record(self, states, records, lam_N: torch.Tensor, lam_0: torch.Tensor | None = None,
+                             grad: torch.Tensor | None = None, stream=None):
+        """lambda^0 from lambda^N through the recorded steps (states[i], records[i])
+        of a rollout, in one call.  Returns (lam_0, grad)."""
+        n = len(states)
+        if len(records) != n:
+            raise ValueError("one record per state")
+        lam_0 = torch.empty_like(lam_N) if lam_0 is None else lam_0
+        grad = self.grad_buffer(lam_N.device) if grad is None else grad
+        fp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t) for t in states])
+        rp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t) for t in records])
+        self._check(self.L.bgk_adjoint_sweep_record(self.h, n, fp, rp, _ptr(lam_N), _ptr(lam_0), _ptr(grad),
+                                                    _ptr(self.workspace("adjoint", lam_N.device)),
+                                                    _stream_handle(stream)))
+        return lam_0, grad
 
     def lid_shear(self, f: torch.Tensor, stream=None) -> torch.Tensor:
         """Lid shear of every cavity instance (0 for other kinds), float64 [ninst]."""

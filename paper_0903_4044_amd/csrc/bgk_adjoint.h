@@ -196,18 +196,27 @@ __global__ void __launch_bounds__(256) k_adj_apply(Args A, const real *__restric
 // out = R^T mu with them; the second read of mu hits the cache.  The same
 // arithmetic as k_adj_sums, k_adj_coef and k_adj_apply with one chunk per
 // cell, so the same bits.
-template <typename real>
+// NEXT (a reverse sweep over step records): out is lambda^n, and the pass also
+// forms the six sums of the previous step's closing relaxation, of out
+// against the Maxwellian of that step's streamed intermediate hn (relaxation
+// data info_n) and hn itself, into sums_n -- k_adj_sums' arithmetic on
+// (hn, out), so the same bits, without reading out again.
+template <typename real, bool NEXT = false>
 __global__ void __launch_bounds__(256) k_adj_close(Args A, const real *__restrict__ x, const real *__restrict__ mu,
                                                    const double *__restrict__ info, double *__restrict__ gk,
-                                                   real *__restrict__ out)
+                                                   real *__restrict__ out, const real *__restrict__ hn,
+                                                   const double *__restrict__ info_n, double *__restrict__ sums_n)
 {
     __shared__ PhiTab T;
+    __shared__ PhiTab Tn;
     __shared__ double sums[NSUM], G[NCOEF];
     const Geo &g = A.g;
     const int gc = xcd_remap(blockIdx.x, gridDim.x);
     const Inst &I = A.inst[find_inst(A.cell_prefix, A.ninst, gc)];
     const double *in = info + (long long)gc * NINFO;
+    const double *inn = NEXT ? info_n + (long long)gc * NINFO : in;
     build_phi(g, in, T);
+    if constexpr (NEXT) build_phi(g, inn, Tn);
     const long long off = I.f0 + (long long)(gc - I.cell0) * g.nv;
     double acc[NSUM] = {0, 0, 0, 0, 0, 0};
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
@@ -241,17 +250,38 @@ __global__ void __launch_bounds__(256) k_adj_close(Args A, const real *__restric
     const real *mc = mu + off;
     real *oc = out + off;
     const double dV = g.dV;
+    double accn[NSUM] = {0, 0, 0, 0, 0, 0};
     for (int p = threadIdx.x; p < g.npl; p += blockDim.x) {
         const int jx = p % g.nvx, jy = p / g.nvx;
         const double vx = vnode(g, 0, jx), vy = vnode(g, 1, jy);
         const double base = G0 + G1 * vx + G2 * vy + G4 * (vx * vx + vy * vy);
+        double cxn = 0.0, cyn = 0.0, pxyn = 0.0;
+        if constexpr (NEXT) {
+            cxn = vnode(g, 0, jx) - inn[1];
+            cyn = vnode(g, 1, jy) - inn[2];
+            pxyn = Tn.P * Tn.e[0][jx] * Tn.e[1][jy];
+        }
 #pragma unroll 4
         for (int jz = 0; jz < g.nvz; ++jz) {
             const int i = jz * g.npl + p;
             const double vz = vnode(g, 2, jz);
-            oc[i] = (real)(E * (double)mc[i] + dV * (base + G3 * vz + G4 * vz * vz));
+            const real r = (real)(E * (double)mc[i] + dV * (base + G3 * vz + G4 * vz * vz));
+            oc[i] = r;
+            if constexpr (NEXT) {
+                const double m = (double)r, xv = (double)hn[off + i];
+                const double cz = vnode(g, 2, jz) - inn[3];
+                const double phi = pxyn * Tn.e[2][jz];
+                const double w = m * phi;
+                accn[0] += w;
+                accn[1] += w * cxn;
+                accn[2] += w * cyn;
+                accn[3] += w * cz;
+                accn[4] += w * (cxn * cxn + cyn * cyn + cz * cz);
+                accn[5] += m * (xv - phi);
+            }
         }
     }
+    if constexpr (NEXT) block_sum_store<NSUM>(accn, sums_n + (long long)gc * NSUM);
 }
 
 // ---------------------------------------------------------------- streaming

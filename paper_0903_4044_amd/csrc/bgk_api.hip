@@ -1141,16 +1141,11 @@ static void adj_stream_dispatch(bgk_ctx *c, const unsigned char *rec, const void
     }
 }
 
-// The reverse step once its forward data are in place -- the relaxation
-// data of f and h (info_f, info_h), the opening tables in parity buffer 0,
-// h = S(R_a f) and the branch record of that streaming pass:
-//   abar = S^T(R_b^T lambda^{n+1})   (k_adj_sums/coef at h, k_adj_stream, k_adj_wall),
-//   lambda^n = R_a^T(abar)           (k_adj_close, or k_adj_sums, k_adj_coef, k_adj_apply).
+// abar = S^T(R_b^T lambda^{n+1}): the gather pass with the step's branch
+// record and the diffuse-wall returns (R_b^T coefficients in place).
 template <typename real>
-static int adjoint_tail(bgk_ctx *c, const void *f, const void *h, const unsigned char *br, const void *lam_next,
-                        void *lam_n, double *grad, hipStream_t s)
+static int adj_gather_wall(bgk_ctx *c, const unsigned char *br, const void *lam_next, hipStream_t s)
 {
-    TRY(relax_coef<real>(c, h, lam_next, c->info_h, s));
     if (c->dim == 1) adj_stream_dispatch<real, 1>(c, br, lam_next, s);
     else adj_stream_dispatch<real, 2>(c, br, lam_next, s);
     HIP_TRY(c, hipGetLastError());
@@ -1162,18 +1157,41 @@ static int adjoint_tail(bgk_ctx *c, const void *f, const void *h, const unsigned
                            c->adj_dw, c->adj_wsum, (real *)c->adj_hb, c->gt);
         HIP_TRY(c, hipGetLastError());
     }
+    return BGK_OK;
+}
+
+// lambda^n = R_a^T(abar) at f (relaxation data info_f).
+template <typename real>
+static int adj_close(bgk_ctx *c, const void *f, void *lam_n, hipStream_t s)
+{
     if (c->vsplit == 1) {
         // one workgroup per cell: sums, coefficients and lambda^n in one pass
-        hipLaunchKernelGGL(k_adj_close<real>, dim3(c->ncells), dim3(fit_block(c->geo.npl)), 0, s, make_args(c), (const real *)f,
-                           (const real *)c->adj_hb, c->info_f, c->gk, (real *)lam_n);
+        hipLaunchKernelGGL((k_adj_close<real, false>), dim3(c->ncells), dim3(fit_block(c->geo.npl)), 0, s,
+                           make_args(c), (const real *)f, (const real *)c->adj_hb, c->info_f, c->gk, (real *)lam_n,
+                           (const real *)nullptr, (const double *)nullptr, (double *)nullptr);
         HIP_TRY(c, hipGetLastError());
     } else {
         TRY(relax_coef<real>(c, f, c->adj_hb, c->info_f, s));
         const int nb = c->ncells * c->vsplit;
-        hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(fit_block(c->geo.npl)), 0, s, make_args(c), (const real *)c->adj_hb,
-                           c->adj_coef, (real *)lam_n);
+        hipLaunchKernelGGL(k_adj_apply<real>, dim3(nb), dim3(fit_block(c->geo.npl)), 0, s, make_args(c),
+                           (const real *)c->adj_hb, c->adj_coef, (real *)lam_n);
         HIP_TRY(c, hipGetLastError());
     }
+    return BGK_OK;
+}
+
+// The reverse step once its forward data are in place -- the relaxation
+// data of f and h (info_f, info_h), the opening tables in parity buffer 0,
+// h = S(R_a f) and the branch record of that streaming pass:
+//   abar = S^T(R_b^T lambda^{n+1})   (k_adj_sums/coef at h, k_adj_stream, k_adj_wall),
+//   lambda^n = R_a^T(abar)           (k_adj_close, or k_adj_sums, k_adj_coef, k_adj_apply).
+template <typename real>
+static int adjoint_tail(bgk_ctx *c, const void *f, const void *h, const unsigned char *br, const void *lam_next,
+                        void *lam_n, double *grad, hipStream_t s)
+{
+    TRY(relax_coef<real>(c, h, lam_next, c->info_h, s));
+    TRY(adj_gather_wall<real>(c, br, lam_next, s));
+    TRY(adj_close<real>(c, f, lam_n, s));
     hipLaunchKernelGGL(k_grad_reduce, dim3(c->ninst), dim3(256), 0, s, make_args(c), c->gk, c->gt, grad);
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
@@ -1273,6 +1291,57 @@ static int do_adjoint_record(bgk_ctx *c, const void *f, const char *rec, const v
     return adjoint_tail<real>(c, f, rec + L.h, (const unsigned char *)(rec + L.br), lam_next, lam_n, grad, s);
 }
 
+// A reverse sweep over n recorded steps: lambda^0 from lambda^n with the
+// states f[i] and records rec[i] of steps i = 0 .. n-1, one step after the
+// other from the last.  With one chunk per cell the close pass of step i also
+// forms step i-1's sums at h (k_adj_close<real, true>), so only the last step
+// runs a separate sums pass; the parameter gradients are reduced once.
+// lambda^i lands in lam_0 for even i and in lam_tmp for odd i.
+template <typename real>
+static int do_adjoint_sweep(bgk_ctx *c, int n, const void *const *f, const void *const *rec, const void *lam_N,
+                            void *lam_0, double *grad, void *lam_tmp, hipStream_t s)
+{
+    const RecordLayout L = record_layout(c);
+    TRY(ensure_adjoint(c));
+    TRY(fill(c, c->gk, c->ncells, 0.0, s));
+    TRY(fill(c, c->gt, c->ncells, 0.0, s));
+    const bool fuse = c->vsplit == 1;
+    auto R = [&](int i) { return (const char *)rec[i]; };
+    auto lam_out = [&](int i) -> void * { return i % 2 == 0 ? lam_0 : lam_tmp; };
+    auto lam_in = [&](int i) -> const void * { return i + 1 == n ? lam_N : (const void *)lam_out(i + 1); };
+    for (int i = n - 1; i >= 0; --i) {
+        // step i's opening relaxation data and tables
+        TRY(part_restore(c, (const double *)(R(i) + L.tot_f), s));
+        TRY(relax_info<real>(c, c->info_f, 0, s));
+        TRY(launch_prep<real>(c, MODE_FIRST, c->vsplit, 0, s));
+        if (i == n - 1 || !fuse) {
+            // R_b^T coefficients of step i from its own sums at h
+            TRY(part_restore(c, (const double *)(R(i) + L.tot_h), s));
+            TRY(relax_info<real>(c, c->info_h, 1, s));
+            TRY(relax_coef<real>(c, R(i) + L.h, lam_in(i), c->info_h, s));
+        }
+        TRY(adj_gather_wall<real>(c, (const unsigned char *)(R(i) + L.br), lam_in(i), s));
+        if (fuse && i > 0) {
+            // lambda^i, and with it step i-1's sums at h and its R_b^T coefficients
+            TRY(part_restore(c, (const double *)(R(i - 1) + L.tot_h), s));
+            TRY(relax_info<real>(c, c->info_h, 1, s));
+            hipLaunchKernelGGL((k_adj_close<real, true>), dim3(c->ncells), dim3(fit_block(c->geo.npl)), 0, s,
+                               make_args(c), (const real *)f[i], (const real *)c->adj_hb, c->info_f, c->gk,
+                               (real *)lam_out(i), (const real *)(R(i - 1) + L.h), (const double *)c->info_h,
+                               c->adj_sums);
+            HIP_TRY(c, hipGetLastError());
+            hipLaunchKernelGGL(k_adj_coef, dim3((c->ncells + 255) / 256), dim3(256), 0, s, make_args(c), c->info_h,
+                               c->adj_sums, c->adj_coef, c->gk);
+            HIP_TRY(c, hipGetLastError());
+        } else {
+            TRY(adj_close<real>(c, f[i], lam_out(i), s));
+        }
+    }
+    hipLaunchKernelGGL(k_grad_reduce, dim3(c->ninst), dim3(256), 0, s, make_args(c), c->gk, c->gt, grad);
+    HIP_TRY(c, hipGetLastError());
+    return BGK_OK;
+}
+
 // Does [a, a + na) overlap [b, b + nb)?
 static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
 {
@@ -1336,6 +1405,38 @@ extern "C" int bgk_step_adjoint_record(bgk_ctx *ctx, const void *f_n, const void
     const int rc = ctx->precision == BGK_FP64
                        ? do_adjoint_record<double>(ctx, f_n, (const char *)rec, lam_next, lam_n, grad_params, s)
                        : do_adjoint_record<float>(ctx, f_n, (const char *)rec, lam_next, lam_n, grad_params, s);
+    ctx->adj_hb = nullptr;
+    return rc;
+}
+
+extern "C" int bgk_adjoint_sweep_record(bgk_ctx *ctx, int n, const void *const *f, const void *const *rec,
+                                        const void *lam_N, void *lam_0, double *grad_params, void *ws, void *stream)
+{
+    if (!ctx) return BGK_E_INVALID;
+    if (n < 0) return fail(ctx, BGK_E_INVALID, "bgk_adjoint_sweep_record: n < 0");
+    if ((n > 0 && (!f || !rec)) || !lam_N || !lam_0 || !grad_params || !ws)
+        return fail(ctx, BGK_E_INVALID, "bgk_adjoint_sweep_record: NULL buffer");
+    const size_t fb = ctx->f_elems * ctx->esize, rb = record_layout(ctx).bytes;
+    if (overlaps(lam_0, fb, lam_N, fb) || overlaps(ws, 2 * fb, lam_N, fb) || overlaps(ws, 2 * fb, lam_0, fb))
+        return fail(ctx, BGK_E_ALIAS, "bgk_adjoint_sweep_record: lam_0, lam_N and the workspace must not overlap");
+    for (int i = 0; i < n; ++i) {
+        if (!f[i] || !rec[i]) return fail(ctx, BGK_E_INVALID, "bgk_adjoint_sweep_record: NULL state or record");
+        if (overlaps(lam_0, fb, f[i], fb) || overlaps(lam_0, fb, rec[i], rb) || overlaps(ws, 2 * fb, f[i], fb) ||
+            overlaps(ws, 2 * fb, rec[i], rb))
+            return fail(ctx, BGK_E_ALIAS, "bgk_adjoint_sweep_record: lam_0 and the workspace must not overlap a "
+                                          "state or record");
+    }
+    TRY(adjoint_kinds(ctx, "bgk_adjoint_sweep_record"));
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(lam_0, lam_N, fb, hipMemcpyDeviceToDevice, s));
+        return BGK_OK;
+    }
+    ctx->adj_hb = ws;
+    void *tmp = (char *)ws + fb;
+    const int rc = ctx->precision == BGK_FP64
+                       ? do_adjoint_sweep<double>(ctx, n, f, rec, lam_N, lam_0, grad_params, tmp, s)
+                       : do_adjoint_sweep<float>(ctx, n, f, rec, lam_N, lam_0, grad_params, tmp, s);
     ctx->adj_hb = nullptr;
     return rc;
 }

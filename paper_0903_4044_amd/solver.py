@@ -149,10 +149,9 @@ class Rollout(torch.autograd.Function):
         grad = solver.grad_buffer(lam.device)
         other = torch.empty_like(lam)
         if ctx.mode == "record":
-            for i in range(nsteps - 1, -1, -1):
-                solver.step_adjoint_record(ctx.states[i], ctx.records[i], lam, other, grad)
-                lam, other = other, lam
-                ctx.states[i] = ctx.records[i] = None
+            # one call for the whole sweep (each step's close pass forms the
+            # sums of the step before it)
+            lam, _ = solver.adjoint_sweep_record(ctx.states, ctx.records, lam, other, grad)
             ctx.states = ctx.records = None
         else:
             every = ctx.every

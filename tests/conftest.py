@@ -23,7 +23,8 @@ def oracle_mod():
 @pytest.fixture(autouse=True)
 def poisoned_outputs(request, monkeypatch):
     """In every GPU test, the outputs of bgk_step, bgk_step_adjoint,
-    bgk_moments, bgk_step_record and bgk_step_adjoint_record, the records and
+    bgk_moments, bgk_step_record, bgk_step_adjoint_record and
+    bgk_adjoint_sweep_record, the records and
     the workspaces they use are filled with NaN (all-ones bytes) before the
     call, and the call must leave no NaN behind: an element that some launch
     shape never writes cannot pass on a value an earlier call left in the
@@ -38,6 +39,7 @@ def poisoned_outputs(request, monkeypatch):
     nan = float("nan")
     step, adjoint, moments = binding.Context.step, binding.Context.step_adjoint, binding.Context.moments
     step_record, adjoint_record = binding.Context.step_record, binding.Context.step_adjoint_record
+    sweep_record = binding.Context.adjoint_sweep_record
 
     def no_nan(t, what):
         assert not torch.isnan(t).any(), f"{what}: elements left unwritten (NaN poison survived)"
@@ -76,6 +78,13 @@ def poisoned_outputs(request, monkeypatch):
         no_nan(out[0], "bgk_step_adjoint_record")
         return out
 
+    def p_sweep_record(self, states, records, lam_N, lam_0=None, grad=None, stream=None):
+        lam_0 = torch.full_like(lam_N, nan) if lam_0 is None else lam_0.fill_(nan)
+        self.workspace("adjoint", lam_N.device).fill_(255)
+        out = sweep_record(self, states, records, lam_N, lam_0, grad, stream)
+        no_nan(out[0], "bgk_adjoint_sweep_record")
+        return out
+
     def p_moments(self, f, out=None, stream=None):
         out = torch.full((self.ncells, 5), nan, dtype=torch.float64, device=f.device) if out is None \
             else out.fill_(nan)
@@ -89,4 +98,5 @@ def poisoned_outputs(request, monkeypatch):
     monkeypatch.setattr(binding.Context, "moments", p_moments)
     monkeypatch.setattr(binding.Context, "step_record", p_step_record)
     monkeypatch.setattr(binding.Context, "step_adjoint_record", p_adjoint_record)
+    monkeypatch.setattr(binding.Context, "adjoint_sweep_record", p_sweep_record)
     yield

@@ -201,6 +201,37 @@ def test_step_record_matches_step_and_adjoint(B, kind, prec):
     assert torch.allclose(g1, g2, rtol=tol, atol=tol * float(g1.abs().max()))
 
 
+@pytest.mark.parametrize("kind", ["shock", "cavity"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_sweep_matches_per_step(B, kind, prec):
+    """bgk_adjoint_sweep_record over 5 recorded steps (the close pass of each
+    step forming the sums of the step before) against 5 calls of
+    bgk_step_adjoint_record: lambda^0 to 1e-12 of its largest entry in FP64
+    and 1e-6 in FP32, the parameter gradients to 1e-12 relative (summed in
+    another order); no steps gives lambda^0 = lambda^N."""
+    cfg = small(kind)
+    C = B.Context(cfg, prec)
+    f = C.initial_state()
+    f = f * (1 + 0.05 * dev(inputs.noise((C.f_elems,), seed=48), C.dtype))
+    states, recs = [], []
+    for _ in range(5):
+        states.append(f)
+        f, rec = C.step_record(f)
+        recs.append(rec)
+    lamN = dev(inputs.noise((C.f_elems,), seed=49), C.dtype)
+    lam, g1 = lamN.clone(), C.grad_buffer()
+    for i in range(4, -1, -1):
+        lam, _ = C.step_adjoint_record(states[i], recs[i], lam, None, g1)
+    l2, g2 = C.adjoint_sweep_record(states, recs, lamN)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert float((lam - l2).abs().max()) <= tol * float(lam.abs().max())
+    assert torch.allclose(g1, g2, rtol=1e-12, atol=1e-12 * float(g1.abs().max()))
+    l0, _ = C.adjoint_sweep_record([], [], lamN)
+    torch.cuda.synchronize()
+    assert torch.equal(l0, lamN)
+
+
 def test_step_record_rules(B):
     """Record entry points: the record must not overlap f_in or f_out, lam_n
     not the record; 3D contexts have no reverse sweep (BGK_E_UNSUPPORTED)."""
@@ -219,6 +250,16 @@ def test_step_record_rules(B):
     ws = C.workspace("adjoint")
     assert L.bgk_step_adjoint_record(C.h, f.data_ptr(), rec.data_ptr(), f.data_ptr(), rec.data_ptr(),
                                      grad.data_ptr(), ws.data_ptr(), s) == B.E_ALIAS
+    import ctypes
+    arr = (ctypes.c_void_p * 1)(f.data_ptr())
+    rarr = (ctypes.c_void_p * 1)(rec.data_ptr())
+    lam = torch.zeros_like(f)
+    assert L.bgk_adjoint_sweep_record(C.h, 1, None, rarr, lam.data_ptr(), out.data_ptr(), grad.data_ptr(),
+                                      ws.data_ptr(), s) == B.E_INVALID
+    assert L.bgk_adjoint_sweep_record(C.h, 1, arr, rarr, lam.data_ptr(), f.data_ptr(), grad.data_ptr(),
+                                      ws.data_ptr(), s) == B.E_ALIAS
+    assert L.bgk_adjoint_sweep_record(C.h, -1, arr, rarr, lam.data_ptr(), out.data_ptr(), grad.data_ptr(),
+                                      ws.data_ptr(), s) == B.E_INVALID
     cube = small("cavity3d", nx=4, ny=3, nz=4, z0=0.0, z1=1.0, nv=(8, 6, 8), vlo=(-4.0, -3.0, -4.0),
                  vhi=(4.0, 3.0, 4.0), lid_mach=0.2)
     C3 = B.Context(cube, "fp64")
