@@ -369,7 +369,8 @@ __device__ __forceinline__ real direction_adjoint(uint32_t bm1, uint32_t b0, uin
 // signs).  ZU (one jz residue, all lanes of a wave on one plane): the plane
 // offset goes into the scalar base of the lambda loads.
 template <typename real, int DIM, int VEC, bool ZU>
-__global__ void __launch_bounds__(256)
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 256),
+                               amdgpu_waves_per_eu(sizeof(real) == 4 && VEC == 1 ? 4 : 1)))
     k_adj_stream(Args A, const unsigned char *__restrict__ rec, const real *__restrict__ params,
                  const real *__restrict__ lam, const double *__restrict__ coef, real *__restrict__ out,
                  double *__restrict__ wsum)
@@ -426,6 +427,8 @@ __global__ void __launch_bounds__(256)
     real *ob = out + I.f0;
     const uint32_t ibytes = (uint32_t)((long long)I.ncell * g.nv * sizeof(real));  // below 2^32 (init)
     const __amdgpu_buffer_rsrc_t lrs = make_rsrc(lb, ibytes);
+    // the branch record of the instance as a buffer too (one byte per element)
+    const __amdgpu_buffer_rsrc_t brs = make_rsrc(rb, (uint32_t)((long long)I.ncell * g.nv));
     const uint32_t out0 = (uint32_t)((long long)c * g.nv * sizeof(real));
     const uint32_t rown = (uint32_t)c * (uint32_t)g.nv;  // element index of (cell, 0) in the instance
     int z0, z1;
@@ -434,7 +437,11 @@ __global__ void __launch_bounds__(256)
     const int ngx = g.nvx / VEC, ngroups = ngx * g.nvy, ntask = ngroups * A.zr;
     const uint32_t zstep = (uint32_t)(g.npl * sizeof(real));
     const double itw = 1.0 / I.tw;
-    double ws[NWALL] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // this thread's wall sums, accumulated in LDS (wall cells only; an LDS
+    // address per wall instead of registers indexed by the lane's wall)
+    __shared__ double wsl[NWALL][256];
+    if (wall)
+        for (int q = 0; q < NWALL; ++q) wsl[q][threadIdx.x] = 0.0;
 
     for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
         const int pg = task % ngroups, zr = ZU ? 0 : task / ngroups;
@@ -454,9 +461,10 @@ __global__ void __launch_bounds__(256)
         const MuTap<real, VEC> mxd = mu_tap<real, VEC>(g, cf[bx + 2], S.mucell[bx + 2], c, p0, jx0, vy);
         const MuTap<real, VEC> mxe = mu_tap<real, VEC>(g, cf[bx + 3], S.mucell[bx + 3], c, p0, jx0, vy);
         // branch records: this element's, and its downwind x (and y) neighbour's
-        const unsigned char *rc = rb + rown + p0;
-        const unsigned char *rx = rb + (uint32_t)S.cell[bx + 2] * (uint32_t)g.nv + p0;
-        const unsigned char *ry = rc;
+        // (element offsets in the instance's record)
+        const uint32_t rc = rown + (uint32_t)p0;
+        const uint32_t rx = (uint32_t)S.cell[bx + 2] * (uint32_t)g.nv + (uint32_t)p0;
+        uint32_t ry = rc;
         // emitted x ghosts read by this cell: its own wall entry (slot k = -1)
         const bool emx = ((sx == 0 && wl) || (sx == 1 && wr));
         const int wx = sx == 0 ? 0 : 1;
@@ -474,7 +482,7 @@ __global__ void __launch_bounds__(256)
             myb = mu_tap<real, VEC>(g, cf[by + 1], S.mucell[by + 1], c, p0, jx0, vy);
             myd = mu_tap<real, VEC>(g, cf[by + 2], S.mucell[by + 2], c, p0, jx0, vy);
             mye = mu_tap<real, VEC>(g, cf[by + 3], S.mucell[by + 3], c, p0, jx0, vy);
-            ry = rb + (uint32_t)S.cell[by + 2] * (uint32_t)g.nv + p0;
+            ry = (uint32_t)S.cell[by + 2] * (uint32_t)g.nv + (uint32_t)p0;
             emy = (sy == 0 && wb) || (sy == 1 && wt);
             wy = sy == 0 ? 2 : 3;
         }
@@ -502,18 +510,27 @@ __global__ void __launch_bounds__(256)
                 Lm[6] = ll(mye);
             }
             const uint32_t zi = (uint32_t)j * (uint32_t)g.npl;
+            if constexpr (ZU) {
+                const uint32_t zs = __builtin_amdgcn_readfirstlane(zi);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                Rc[0][e] = rc[zi + e];
-                Rc[1][e] = rx[zi + e];
-                Rc[2][e] = DIM == 2 ? (uint32_t)ry[zi + e] : 0u;
+                for (int e = 0; e < VEC; ++e) {
+                    Rc[0][e] = __builtin_amdgcn_raw_buffer_load_b8(brs, (int)(rc + e), (int)zs, 0);
+                    Rc[1][e] = __builtin_amdgcn_raw_buffer_load_b8(brs, (int)(rx + e), (int)zs, 0);
+                    Rc[2][e] = DIM == 2 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(brs, (int)(ry + e), (int)zs, 0)
+                                        : 0u;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    Rc[0][e] = rb[rc + zi + e];
+                    Rc[1][e] = rb[rx + zi + e];
+                    Rc[2][e] = DIM == 2 ? (uint32_t)rb[ry + zi + e] : 0u;
+                }
             }
         };
         int jz = z0 + zr;
         if (jz >= z1) continue;
         const int zlast = z1 - 1 - ((z1 - 1 - jz) % A.zr);  // last plane of this lane's residue
-        // this task's wall sums (its x wall, its y wall), folded into ws per task
-        double ex0 = 0.0, ex1 = 0.0, ey0 = 0.0, ey1 = 0.0;
         V Lm[NL];
         B R[3];
         load_plane(jz, Lm, R);
@@ -545,8 +562,8 @@ __global__ void __launch_bounds__(256)
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double vx = vnode(g, 0, jx0 + e);
                         const double c2 = vx * vx + vy * vy + vzd * vzd;
-                        ex0 += gam * phiw;
-                        ex1 += gam * phiw * (c2 * itw * itw - 1.5 * itw);
+                        wsl[2 * wx][threadIdx.x] += gam * phiw;
+                        wsl[2 * wx + 1][threadIdx.x] += gam * phiw * (c2 * itw * itw - 1.5 * itw);
                     }
                 }
             }
@@ -570,8 +587,8 @@ __global__ void __launch_bounds__(256)
                                             (double)E[g.tz + 2 * jz] / nw;
                         const double ux = vnode(g, 0, jx0 + e) - uw;
                         const double c2 = ux * ux + vy * vy + vzd * vzd;
-                        ey0 += gam * phiw;
-                        ey1 += gam * phiw * (c2 * itw * itw - 1.5 * itw);
+                        wsl[2 * wy][threadIdx.x] += gam * phiw;
+                        wsl[2 * wy + 1][threadIdx.x] += gam * phiw * (c2 * itw * itw - 1.5 * itw);
                     }
                 }
             }
@@ -581,20 +598,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int t = 0; t < 3; ++t) R[t] = Rn[t];
         }
-        if (wall) {
-            // (selects instead of indexing ws by the lane's wall: no dynamic
-            // register indexing)
-            ws[0] += wx == 0 ? ex0 : 0.0;
-            ws[1] += wx == 0 ? ex1 : 0.0;
-            ws[2] += wx == 1 ? ex0 : 0.0;
-            ws[3] += wx == 1 ? ex1 : 0.0;
-            ws[4] += wy == 2 ? ey0 : 0.0;
-            ws[5] += wy == 2 ? ey1 : 0.0;
-            ws[6] += wy == 3 ? ey0 : 0.0;
-            ws[7] += wy == 3 ? ey1 : 0.0;
-        }
     }
-    if (wall) block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);
+    if (wall) {
+        double ws[NWALL];
+#pragma unroll
+        for (int q = 0; q < NWALL; ++q) ws[q] = wsl[q][threadIdx.x];
+        block_sum_store<NWALL>(ws, wsum + (long long)L * NWALL);
+    }
 }
 
 // Per-cell totals of the partial moment sums (the step record keeps them
