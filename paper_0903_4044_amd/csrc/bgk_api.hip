@@ -743,15 +743,25 @@ static int launch_prep(bgk_ctx *c, int mode, int nparts, int parity, hipStream_t
     const int w = nvmax <= 16 ? 16 : nvmax <= 32 ? 32 : 64;
     const int per_block = 4 * (64 / w);
     real *pb = params_buf<real>(c, parity);
-    if (w == 16)
-        hipLaunchKernelGGL((k_prep<real, 16>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
-                           pb, mode, ne, copy);
-    else if (w == 32)
-        hipLaunchKernelGGL((k_prep<real, 32>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
-                           pb, mode, ne, copy);
-    else
-        hipLaunchKernelGGL((k_prep<real, 64>), dim3((ne + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial,
-                           pb, mode, ne, copy);
+    // cells, then (with their own kernel) the ghost sources
+    auto go = [&](auto kern, int first, int count) {
+        if (count > 0)
+            hipLaunchKernelGGL(kern, dim3((count + per_block - 1) / per_block), dim3(256), 0, s, a, c->partial, pb,
+                               mode, ne, copy);
+    };
+    auto both = [&](auto cells, auto ghosts) {
+        go(cells, 0, c->ncells);
+        go(ghosts, c->ncells, ne - c->ncells);
+    };
+    if (c->conservative) {
+        if (w == 16) both(k_prep<real, 16, false, true>, k_prep<real, 16, true, true>);
+        else if (w == 32) both(k_prep<real, 32, false, true>, k_prep<real, 32, true, true>);
+        else both(k_prep<real, 64, false, true>, k_prep<real, 64, true, true>);
+    } else {
+        if (w == 16) both(k_prep<real, 16, false, false>, k_prep<real, 16, true, false>);
+        else if (w == 32) both(k_prep<real, 32, false, false>, k_prep<real, 32, true, false>);
+        else both(k_prep<real, 64, false, false>, k_prep<real, 64, true, false>);
+    }
     HIP_TRY(c, hipGetLastError());
     return BGK_OK;
 }

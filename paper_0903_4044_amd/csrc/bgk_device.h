@@ -753,7 +753,7 @@ struct Coef {
 
 // Coefficients of the relaxations folded into one cell's entry, from that
 // cell's partial moment sums (A.nparts per cell).  Wave-uniform control flow.
-template <int W = 64>
+template <int W = 64, bool CONS = true>
 __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, int gc, int mode,
                                                   const double *partial, Coef &C, bool want_sums)
 {
@@ -773,10 +773,13 @@ __device__ __forceinline__ void cell_coefficients(const Args &A, const Inst &I, 
     if (C.nr == 0) return;
     moments_from_raw(C.raw, &C.r1);
     finish_relax(I, ta, &C.r1);
-    if (I.conservative) effective_tables<W>(g, &C.r1, C.t1);
+    // CONS = false: no conservative instance in the launch (the point form
+    // alone, far fewer registers)
+    const bool cons = CONS && I.conservative;
+    if (cons) effective_tables<W>(g, &C.r1, C.t1);
     else lane_tables<W>(g, C.r1.V, C.r1.T, C.t1);
-    if ((C.nr == 2 && !I.conservative) || want_sums) wave_table_sums<W>(g, C.t1, C.s1, want_sums);
-    if (C.nr == 2 && I.conservative) {
+    if ((C.nr == 2 && !cons) || want_sums) wave_table_sums<W>(g, C.t1, C.s1, want_sums);
+    if (C.nr == 2 && cons) {
         // R1 keeps the grid moments, so R2 relaxes towards the same Maxwellian
         C.r2 = C.r1;
         finish_relax(I, tb, &C.r2);
@@ -880,20 +883,26 @@ __device__ __forceinline__ int wall_cell(const Inst &I, int w, int pos)
     return ((low ? 0 : I.nz - 1) * I.ny + iy) * I.nx + ix;
 }
 
-// Table entry e (a cell, or a ghost source after the ncells cells), computed by
-// the calling W-lane segment from the partial moment sums of the streaming input.
-template <typename real, int W>
-__device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const double *partial, real *params)
+// Table entry of cell e, computed by the calling W-lane segment from the
+// partial moment sums of the streaming input.
+template <typename real, int W, bool CONS>
+__device__ __forceinline__ void prep_cell(const Args &A, int e, int mode, const double *partial, real *params)
 {
     const Geo &g = A.g;
     real *E = params + (long long)e * g.pe;
     Coef C;
-    if (e < A.ncells) {
-        const int ii = find_inst(A.cell_prefix, A.ninst, e);
-        cell_coefficients<W>(A, A.inst[ii], e, mode, partial, C, false);
-        write_entry<real, W>(g, E, C.c0, C.cA, C.t1, C.cB, C.t2);
-        return;
-    }
+    const int ii = find_inst(A.cell_prefix, A.ninst, e);
+    cell_coefficients<W, CONS>(A, A.inst[ii], e, mode, partial, C, false);
+    write_entry<real, W>(g, E, C.c0, C.cA, C.t1, C.cB, C.t2);
+}
+
+// Table entry e >= ncells (a ghost source), likewise.
+template <typename real, int W, bool CONS>
+__device__ __forceinline__ void prep_ghost(const Args &A, int e, int mode, const double *partial, real *params)
+{
+    const Geo &g = A.g;
+    real *E = params + (long long)e * g.pe;
+    Coef C;
     // ghost sources
     const int pe = e - A.ncells;
     const int ii = find_inst(A.pseudo_prefix, A.ninst, pe);
@@ -918,7 +927,7 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     const int w = wall_of_entry(I, k, &pos);
     const int axis = w >> 1;
     const int adj = wall_cell(I, w, pos);
-    cell_coefficients<W>(A, I, I.cell0 + adj, mode, partial, C, true);
+    cell_coefficients<W, CONS>(A, I, I.cell0 + adj, mode, partial, C, true);
     const double VW[3] = {w == 3 ? I.uw : 0.0, 0.0, 0.0};
     Tables tw;
     lane_tables<W>(g, VW, I.tw, tw);
@@ -927,16 +936,21 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
     const int b1 = axis == 0 ? 1 : 0, b2 = axis == 2 ? 1 : 2;  // the two other components
     // incident: v_axis < 0 for the low walls (sum index 3), v_axis > 0 for the high ones (index 4)
     const bool lowwall = (w & 1) == 0;
-    const double hin1 = lowwall ? C.s1[axis][3] : C.s1[axis][4];
-    const double hin2 = lowwall ? C.s2[axis][3] : C.s2[axis][4];
-    const double out_w = lowwall ? sw[axis][4] : sw[axis][3];
-    const double o1 = C.s1[b1][0], o2 = C.s2[b1][0], ow = sw[b1][0];
-    const double hraw = C.raw[5 + w];
+    // (run-time axes select among registers: indexing the arrays with them
+    // would put the whole entry's state in scratch memory)
+    auto pick = [](const double (&t)[3][5], int a, int q) { return a == 0 ? t[0][q] : (a == 1 ? t[1][q] : t[2][q]); };
+    const double hin1 = lowwall ? pick(C.s1, axis, 3) : pick(C.s1, axis, 4);
+    const double hin2 = lowwall ? pick(C.s2, axis, 3) : pick(C.s2, axis, 4);
+    const double out_w = lowwall ? pick(sw, axis, 4) : pick(sw, axis, 3);
+    const double o1 = pick(C.s1, b1, 0), o2 = pick(C.s2, b1, 0), ow = pick(sw, b1, 0);
+    double hraw = C.raw[5];
+#pragma unroll
+    for (int q = 1; q < 6; ++q) hraw = w == q ? C.raw[5 + q] : hraw;
     double flux = C.c0 * hraw;
-    if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * C.s1[b2][0];
-    if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * C.s2[b2][0];
+    if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * pick(C.s1, b2, 0);
+    if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * pick(C.s2, b2, 0);
     const double pw = pi_t_m32(I.tw);
-    const double den = pw * g.dV * out_w * ow * sw[b2][0];
+    const double den = pw * g.dV * out_w * ow * pick(sw, b2, 0);
     write_entry<real, W>(g, E, 0.0, flux / den * pw, tw, 0.0, z);
     if ((threadIdx.x & (W - 1)) == 1) E[1] = (real)(flux / den);  // n_W, read by the reverse sweep
 }
@@ -946,20 +960,30 @@ __device__ __forceinline__ void prep_entry(const Args &A, int e, int mode, const
 // largest velocity axis, so few lanes idle on small grids; every sum is a
 // butterfly inside the segment, and a segment's results equal those of a
 // whole wave with the extra lanes holding zeros).
-template <typename real, int W>
+// The table entries of one preparation: cells (GHOST = false, entries
+// [0, ncells)) or ghost sources (GHOST = true, entries [ncells, nentries)),
+// two launches, so that the cells' kernel keeps its state in registers (the
+// ghost faces index per-axis sums with a run-time axis).
+template <typename real, int W, bool GHOST, bool CONS>
 __global__ void __launch_bounds__(256) k_prep(Args A, const double *__restrict__ partial, real *__restrict__ params,
                                               int mode, int nentries, real *__restrict__ params_shock_copy)
 {
     // Tables of these modes follow a streaming pass: advance the rounding
     // counter once (stream order puts this after that pass's reads).
-    if (blockIdx.x == 0 && threadIdx.x == 0 && (mode == MODE_MID || mode == MODE_FINAL)) A.pass[0] = A.pass[0] + 1u;
-    const int e = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / W) + (int)((threadIdx.x & 63) / W);
-    if (e >= nentries) return;  // the whole segment leaves; sums never leave a segment
-    prep_entry<real, W>(A, e, mode, partial, params);
-    // Far-field entries never change: give the other parity buffer a copy.
-    if (params_shock_copy && e >= A.ncells) {
-        const int ii = find_inst(A.pseudo_prefix, A.ninst, e - A.ncells);
-        if (A.inst[ii].kind == KIND_SHOCK) prep_entry<real, W>(A, e, mode, partial, params_shock_copy);
+    if (!GHOST && blockIdx.x == 0 && threadIdx.x == 0 && (mode == MODE_MID || mode == MODE_FINAL))
+        A.pass[0] = A.pass[0] + 1u;
+    const int e = (GHOST ? A.ncells : 0) + (blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / W) +
+                  (int)((threadIdx.x & 63) / W);
+    if (e >= (GHOST ? nentries : A.ncells)) return;  // the whole segment leaves; sums never leave a segment
+    if constexpr (!GHOST) {
+        prep_cell<real, W, CONS>(A, e, mode, partial, params);
+    } else {
+        prep_ghost<real, W, CONS>(A, e, mode, partial, params);
+        // Far-field entries never change: give the other parity buffer a copy.
+        if (params_shock_copy) {
+            const int ii = find_inst(A.pseudo_prefix, A.ninst, e - A.ncells);
+            if (A.inst[ii].kind == KIND_SHOCK) prep_ghost<real, W, CONS>(A, e, mode, partial, params_shock_copy);
+        }
     }
 }
 
