@@ -936,16 +936,19 @@ __device__ __forceinline__ void prep_ghost(const Args &A, int e, int mode, const
     const int b1 = axis == 0 ? 1 : 0, b2 = axis == 2 ? 1 : 2;  // the two other components
     // incident: v_axis < 0 for the low walls (sum index 3), v_axis > 0 for the high ones (index 4)
     const bool lowwall = (w & 1) == 0;
-    // (run-time axes select among registers: indexing the arrays with them
-    // would put the whole entry's state in scratch memory)
-    auto pick = [](const double (&t)[3][5], int a, int q) { return a == 0 ? t[0][q] : (a == 1 ? t[1][q] : t[2][q]); };
+    // (run-time axes blend registers with 0/1 weights, exact for the finite
+    // sums here: a select of array elements becomes an indexed access, which
+    // puts the whole entry's state in scratch memory)
+    auto pick = [](const double (&t)[3][5], int a, int q) {
+        return t[0][q] * (double)(a == 0) + t[1][q] * (double)(a == 1) + t[2][q] * (double)(a == 2);
+    };
     const double hin1 = lowwall ? pick(C.s1, axis, 3) : pick(C.s1, axis, 4);
     const double hin2 = lowwall ? pick(C.s2, axis, 3) : pick(C.s2, axis, 4);
     const double out_w = lowwall ? pick(sw, axis, 4) : pick(sw, axis, 3);
     const double o1 = pick(C.s1, b1, 0), o2 = pick(C.s2, b1, 0), ow = pick(sw, b1, 0);
-    double hraw = C.raw[5];
+    double hraw = 0.0;
 #pragma unroll
-    for (int q = 1; q < 6; ++q) hraw = w == q ? C.raw[5 + q] : hraw;
+    for (int q = 0; q < 6; ++q) hraw += C.raw[5 + q] * (double)(w == q);
     double flux = C.c0 * hraw;
     if (C.nr >= 1) flux += C.cA * g.dV * hin1 * o1 * pick(C.s1, b2, 0);
     if (C.nr == 2) flux += C.cB * g.dV * hin2 * o2 * pick(C.s2, b2, 0);
