@@ -1572,12 +1572,12 @@ extern "C" int bgk_cavity_metrics(bgk_ctx *ctx, const void *f, double *out, void
 
 // ------------------------------------------------------------- autotuning
 
-// Time of one step in the steady part of bgk_step: (10 steps - 2 steps) / 8,
-// so the once-per-call passes (moments of the input, closing relaxation)
-// cancel; f -> tmp, with graph replay, timing and the rounding seed saved
-// and restored.
+// Time of one step in the steady part of bgk_step: ((2 + n) steps - 2 steps)
+// / n, so the once-per-call passes (moments of the input, closing relaxation)
+// cancel, after `warm` untimed steps; f -> tmp, with graph replay, timing and
+// the rounding seed saved and restored.
 template <typename real>
-static int time_steps(bgk_ctx *c, const void *f, void *tmp, hipStream_t s, double *us)
+static int time_steps(bgk_ctx *c, const void *f, void *tmp, hipStream_t s, double *us, int n = 8, int warm = 0)
 {
     hipEvent_t e[3];
     for (auto &x : e) HIP_TRY(c, hipEventCreate(&x));
@@ -1587,10 +1587,11 @@ static int time_steps(bgk_ctx *c, const void *f, void *tmp, hipStream_t s, doubl
     c->use_graph = false;
     // untimed first: a shape's first launch loads its code object
     int rc = do_step<real>(c, f, tmp, 1, s);
+    if (!rc && warm > 0) rc = do_step<real>(c, f, tmp, warm, s);
     if (!rc) rc = hipEventRecord(e[0], s) == hipSuccess ? 0 : BGK_E_HIP;
     if (!rc) rc = do_step<real>(c, f, tmp, 2, s);
     if (!rc) rc = hipEventRecord(e[1], s) == hipSuccess ? 0 : BGK_E_HIP;
-    if (!rc) rc = do_step<real>(c, f, tmp, 10, s);
+    if (!rc) rc = do_step<real>(c, f, tmp, 2 + n, s);
     if (!rc) rc = hipEventRecord(e[2], s) == hipSuccess ? 0 : BGK_E_HIP;
     float a = 0.0f, b = 0.0f;
     if (!rc) rc = hipEventSynchronize(e[2]) == hipSuccess ? 0 : BGK_E_HIP;
@@ -1601,15 +1602,17 @@ static int time_steps(bgk_ctx *c, const void *f, void *tmp, hipStream_t s, doubl
     c->seed = seed;
     for (auto &x : e) (void)hipEventDestroy(x);
     if (rc) return fail(c, rc, "autotune: timing failed");
-    *us = 1e3 * (double)(b - a) / 8.0;
+    *us = 1e3 * (double)(b - a) / (double)n;
     return BGK_OK;
 }
 
 // Try the candidate shapes on f and keep the fastest by the steady step time
 // of real steps (f -> tmp, the caller's scratch state; the ping-pong buffer
-// is the caller's workspace, already in c->work).  The four fastest of the
-// sweep are timed twice more and ranked by their best time (one timing
-// varies by a few percent).
+// is the caller's workspace, already in c->work).  The sweep times 8 steps
+// per shape; such short runs vary by up to ~10% (the clock state of a short
+// burst differs from a sustained run), so the four fastest are timed twice
+// more over 32 steps after 16 untimed ones and ranked by the better of those
+// two timings alone.
 template <typename real>
 static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
 {
@@ -1625,9 +1628,9 @@ static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
     }
     for (int v : {2, 4})
         if (v <= c->vsplit_max && std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
-    auto measure = [&](const Cand &k, double *us) {
+    auto measure = [&](const Cand &k, double *us, int n, int warm) {
         set_shape(c, k.vec, k.unroll, k.vsplit, k.persist);
-        return time_steps<real>(c, f, tmp, s, us);
+        return time_steps<real>(c, f, tmp, s, us, n, warm);
     };
     int rc = BGK_OK;
     {
@@ -1645,16 +1648,17 @@ static int autotune(bgk_ctx *c, const void *f, void *tmp, hipStream_t s)
                     if (c->dim == 3 && unroll > 2) continue;  // 3D: modes 1 and 2 only
                     if (ps && c->ncells * vs <= ps * c->ncu) continue;  // grid already resident
                     Cand k{0.0, vec, unroll, vs, ps};
-                    rc = measure(k, &k.us);
+                    rc = measure(k, &k.us, 8, 0);
                     if (!rc) cands.push_back(k);
                 }
     }
     std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.us < b.us; });
     if (cands.size() > 4) cands.resize(4);
+    for (Cand &k : cands) k.us = HUGE_VAL;
     for (int rep = 0; rep < 2 && !rc; ++rep)
         for (Cand &k : cands) {
             double us = 0.0;
-            if (!rc) rc = measure(k, &us);
+            if (!rc) rc = measure(k, &us, 32, 16);
             if (!rc) k.us = std::min(k.us, us);
         }
     (void)hipStreamSynchronize(s);
