@@ -226,14 +226,17 @@ int bgk_check(bgk_ctx *ctx, const void *f, void *stream);
  * per stage, 2 or 3 planes ahead), jz chunks per cell (one work item each,
  * 1 .. a context-dependent maximum), and persist: 0 launches one workgroup
  * per work item, k > 0 launches k workgroups per compute unit that walk the
- * items of all instances (one persistent launch for a batch).  Contexts
- * with BGK_SHIFT streaming take vec 1 and unroll 1 only.
+ * items of all instances (one persistent launch for a batch).  Vec is 1
+ * for BGK_SHIFT streaming, reduced velocity spaces and 3D kinds; 3D kinds
+ * take unroll 1 or 2.  BGK_SHIFT contexts take unroll 1 (the per-cell
+ * translation kernel) or, where its row tiles fit, 2 (the row-tile kernel).
  * bgk_init picks a default.  bgk_autotune times every valid shape on the
  * state f (device, f_elems elements, read only; synchronises the stream) and
  * keeps the fastest by the steady time of a real step (streaming pass and
- * table preparation, (10 steps - 2 steps) / 8, after an untimed warm-up
- * of a few steps; the four fastest of the sweep are timed twice more and
- * ranked by their best time).  The timed steps write into `scratch` (the
+ * table preparation, ((2 + n) steps - 2 steps) / n).  The sweep times n = 8
+ * steps per shape after an untimed warm-up of a few steps; the four fastest
+ * are then timed twice more with n = 32 after 16 untimed steps and ranked
+ * by the better of those two timings alone.  The timed steps write into `scratch` (the
  * caller's device buffer of f_elems elements, overwritten) with `ws` (of
  * ws_step_bytes) as their workspace; f, scratch and ws must not overlap
  * (BGK_E_ALIAS), none may be NULL (BGK_E_INVALID).  On an error the
